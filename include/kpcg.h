@@ -1,0 +1,192 @@
+/*
+ * kpcg -- tensor-structured preconditioned CG for the finite-difference
+ * Poisson equation  -Laplace(u) = eta  on a rectangle or a cuboid, on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Chumchal, Marton, Plesinger, Simunkova, "Tensor-structured PCG for
+ * finite difference solver of domain patterns in ferroelectric material",
+ * arXiv 2501.03377.  The discrete operator is the Kronecker sum of the 1D
+ * operators of eq. (3.1) (eqs. 3.2-3.3); the solver is Algorithm 1 (PCG); the
+ * preconditioner is the Moore-Penrose pseudoinverse of the operator, built
+ * from the 1D eigendecompositions (Algs. 4-5) and applied as three mode
+ * products forward, a Hadamard scaling, and three mode products back
+ * (Algs. 6-7).
+ *
+ * Conventions shared by every entry point
+ *   Layout.    A grid function is an array of nx*ny*nz doubles with x
+ *              fastest, then y, then z: element (i, j, k) at i + nx*(j + ny*k).
+ *              This is the paper's vec() order (Sec. 2.1).  A batch of B
+ *              right-hand sides is B such arrays back to back.  nz = 1
+ *              selects the 2D problem (matrices instead of tensors).
+ *   Memory.    Pointers documented as "device" are HIP device allocations
+ *              owned by the caller (for example torch.empty(..., device='cuda')),
+ *              16-byte aligned.  The library never frees caller memory.
+ *   Streams.   Work is enqueued on the plan's HIP stream.  kp_solve blocks
+ *              until the solve has finished; kp_apply_* only enqueue.
+ *   Errors.    Every call returns a kp_status; negative values are errors and
+ *              leave outputs undefined; no call throws across the ABI.
+ *   Threads.   One plan must be used by one host thread at a time; distinct
+ *              plans are independent.
+ *   Units.     Unit grid spacing (eq. 3.1 has unit entries): scale eta by h^2.
+ *   Boundary data.  Homogeneous; non-homogeneous Dirichlet/Neumann values
+ *              are folded into eta by the caller as in Sec. 3.4.2.
+ */
+#ifndef KPCG_H
+#define KPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Boundary condition per axis, eq. (3.1): corners (alpha, beta, gamma) are
+ * P (2,2,-1), D (2,2,0), N (1,1,0), DN (2,1,0), ND (1,2,0). */
+enum kp_bc { KP_BC_P = 0, KP_BC_D = 1, KP_BC_N = 2, KP_BC_DN = 3, KP_BC_ND = 4 };
+
+/* Arithmetic of the preconditioner's mode products.  Vectors, residuals,
+ * inner products and the solution are FP64 in every mode.  F32 uses FP32
+ * matrix cores; BF16 uses BF16 matrix cores with FP32 accumulation and a
+ * per-right-hand-side power-of-two input scale; the Hadamard factor of
+ * eq. (4.6) is always applied in at least FP32. */
+enum kp_prec { KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2 };
+
+enum kp_status {
+  KP_OK = 0,
+  KP_NOT_CONVERGED = 1,   /* warning: max_iter reached; u holds the last iterate */
+  KP_EINVAL = -1,         /* invalid argument */
+  KP_ENOMEM = -2,         /* device allocation failed or workspace too small */
+  KP_EHIP = -3,           /* a HIP runtime call failed */
+  KP_ENONFINITE = -4,     /* eta or an iterate contains NaN/Inf */
+  KP_EBREAKDOWN = -5      /* <W,P> <= 0 or rho <= 0 before convergence */
+};
+
+/* Solve flags (bitwise or). */
+enum kp_flags {
+  KP_FLAG_NO_PRECOND = 1,   /* M = I: plain CG (Experiment 5.5's baseline) */
+  KP_FLAG_FLEX_BETA = 2,    /* beta_s = <R_s - R_{s-1}, Z_s>/rho_{s-1} instead of
+                               Algorithm 1's rho_s/rho_{s-1}; for inexact
+                               (low-precision) preconditioners */
+  KP_FLAG_RESIDUAL_ONLY = 4 /* stop on the relative residual alone (see kp_solve) */
+};
+
+typedef struct kp_plan kp_plan;   /* opaque */
+
+/* Per right-hand-side outcome of kp_solve. */
+typedef struct {
+  int32_t status;         /* kp_status of this right-hand side */
+  int32_t iterations;     /* s at exit (Algorithm 1's iteration counter) */
+  int32_t pinv_applications; /* preconditioner applications, including Z_0 */
+  int32_t reserved;
+  double rel_res;         /* ||R_s|| / ||eta_c||, recursive residual */
+  double true_rel_res;    /* ||eta_c - L u|| / ||eta_c|| recomputed at exit */
+  double err_est;         /* ||Z_s|| / ||U_s||; Z_s approximates the error */
+  double removed_mean;    /* mean of eta projected out (singular operators) */
+} kp_result;
+
+/* Closed-form orthonormal eigenbasis of the 1D operator L_n of eq. (3.1) for
+ * one boundary condition (Lemmas 3.1-3.4, normalised as eq. 4.5 requires).
+ * Host memory only; needs no GPU.
+ *   n      >= 3
+ *   bc     kp_bc
+ *   Q      host, n*n doubles, row-major: Q[j*n + c] = entry j of eigenvector c
+ *   lambda host, n doubles, ascending eigenvalues
+ * Returns KP_OK or KP_EINVAL. */
+int kp_basis_1d(int n, int bc, double* Q, double* lambda);
+
+/* Creates a plan: the preconditioner's initialisation (Algs. 4-5) for one
+ * grid, boundary-condition triple and precision.  Computes the closed-form
+ * bases on the host, uploads V_l, V_l^T and the eigenvalues to the current
+ * HIP device once, and records the stream.
+ *   out        receives the plan
+ *   nx, ny     >= 3;  nz >= 3, or nz == 1 for a 2D problem (bc[2] ignored)
+ *   bc         host, 3 kp_bc values for the x, y and z axes
+ *   prec       kp_prec
+ *   max_batch  largest batch a solve may use (>= 1)
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream)
+ * Limits: nx*ny*nz < 2^31; grid dimensions must fit HIP launch limits
+ * (max_batch*nz <= 65535 and ny*nz <= 4,194,240).
+ * Returns KP_OK, KP_EINVAL, KP_ENOMEM or KP_EHIP. */
+int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int prec,
+                   int max_batch, void* hip_stream);
+
+/* Releases the plan's resident operands and any workspace it allocated. */
+void kp_plan_destroy(kp_plan* plan);
+
+/* Device bytes a solve of `batch` right-hand sides needs beyond the caller's
+ * eta and u (vectors R, P, W, Z, two preconditioner scratch grids, partial
+ * sums and scalar state).  0 for invalid arguments. */
+size_t kp_plan_workspace_bytes(const kp_plan* plan, int batch);
+
+/* Device bytes held by the plan itself (eigenvectors and eigenvalues). */
+size_t kp_plan_resident_bytes(const kp_plan* plan);
+
+/* Hands the plan a caller-owned device workspace of `bytes` (>=
+ * kp_plan_workspace_bytes(plan, max_batch)), replacing any it allocated.
+ * Without this call the plan allocates its workspace on first use.
+ * Returns KP_OK, KP_EINVAL or KP_ENOMEM (too small). */
+int kp_plan_set_workspace(kp_plan* plan, void* dev_ptr, size_t bytes);
+
+/* Changes the stream later calls enqueue on. */
+int kp_plan_set_stream(kp_plan* plan, void* hip_stream);
+
+/* W = -Delta_FD(P), eq. (3.2), for `batch` grid functions (the sparse
+ * application of Sec. 4.2).  P, W: device, batch*N doubles, must not overlap.
+ * Enqueue only. */
+int kp_apply_laplacian(kp_plan* plan, const double* P, double* W, int batch);
+
+/* Z = M_p-inv(R), Algs. 6-7, in the plan's precision, for `batch` grid
+ * functions.  R, Z: device, batch*N doubles, must not overlap.  No centering
+ * is applied.  Uses the plan's workspace.  Enqueue only. */
+int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
+
+/* Solves -Delta_FD(u) = eta for `batch` right-hand sides with Algorithm 1
+ * from U_0 = 0 and the pseudoinverse preconditioner (or M = I with
+ * KP_FLAG_NO_PRECOND).
+ *   eta       device, batch*N doubles, read only
+ *   u         device, batch*N doubles, output; must not overlap eta
+ *   tol       > 0, relative tolerance
+ *   max_iter  >= 1, largest iteration count s
+ *   flags     kp_flags
+ *   results   host, batch entries (may be NULL)
+ *   res_hist  host, batch*(max_iter+1) doubles (may be NULL): ||R_s||/||eta_c||
+ *             for s = 0..iterations; entries past `iterations` are 0
+ * Singular operators (every axis P or N, Sec. 3.4.1): eta is centred
+ * (eq. 3.6; the removed mean is reported), Z_s is centred every iteration
+ * (Remark 4.1), and u is returned with zero mean: the minimum-norm solution.
+ * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
+ * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
+ * set, also ||Z_s||/||U_s|| <= tol (Z_s = M(R_s) estimates the error of U_s).
+ * Returns the most severe per-RHS status (errors first, then
+ * KP_NOT_CONVERGED); KP_EINVAL before any work for bad arguments.  Blocks
+ * until the results are on the host. */
+int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol, int max_iter,
+             int flags, kp_result* results, double* res_hist);
+
+/* Per-kernel timing (the library's tracing facility).  When enabled, every
+ * kernel launch of the plan is bracketed by HIP events on the plan's stream
+ * and its duration is added to one of KP_KERNEL_CLASSES classes, named by
+ * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
+ * products of Algs. 6-7, ...).  Timing adds two event records per launch. */
+#define KP_KERNEL_CLASSES 14
+int kp_plan_set_profiling(kp_plan* plan, int enable);
+/* Synchronises the plan's stream, then returns the accumulated milliseconds
+ * and launch count of one class.  KP_EINVAL for a bad class. */
+int kp_plan_profile(kp_plan* plan, int cls, double* total_ms, int64_t* launches);
+/* Clears the accumulated timings. */
+int kp_plan_profile_reset(kp_plan* plan);
+/* Name of a kernel class, "unknown" when out of range. */
+const char* kp_kernel_class_name(int cls);
+
+/* Human-readable name of a status code. */
+const char* kp_strerror(int status);
+
+/* Library version string. */
+const char* kp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KPCG_H */

@@ -1,0 +1,108 @@
+// Shared device-side definitions of the kpcg library (gfx950 / CDNA4).
+//
+// Grid layout of every vector: [rhs][z][y][x] with x contiguous, which is the
+// paper's vec() ordering (Sec. 2.1): the first index i varies fastest, then j,
+// then k.  A batch of right-hand sides is stacked RHS-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+// Boundary conditions of eq. (3.1).
+enum Bc { BC_P = 0, BC_D = 1, BC_N = 2, BC_DN = 3, BC_ND = 4 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+// Termination codes kept per right-hand side on the device.
+enum Done { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, ZERO_RHS = 4 };
+
+// Per right-hand-side scalar state of Algorithm 1, resident on the device so
+// that no iteration needs a host round trip.
+struct RhsState {
+  double h2;          // ||eta_c||^2
+  double mean;        // mean removed from eta (singular operators, eq. 3.6)
+  double rho;         // rho_{s-1} = <R_{s-1}, Z_{s-1}>
+  double alpha;       // alpha_s
+  double beta;        // beta_s
+  double rr;          // ||R_s||^2
+  double rsum;        // sum of the entries of R_s
+  double uu;          // ||U_s||^2
+  double pw;          // <W_s, P_{s-1}>
+  double wsum;        // sum of the entries of W_s
+  double rz;          // <R_s, Z_s> after centering of Z_s
+  double zz;          // ||Z_s||^2 after centering
+  double zmean;       // mean of Z_s (centering, Remark 4.1)
+  double rel_res;     // ||R_s|| / ||eta_c||
+  double err_est;     // ||Z_s|| / ||U_s||
+  double true_rel_res;// ||eta_c - L U|| / ||eta_c|| at exit
+  double umean;       // mean of U removed at exit (singular operators)
+  double scale;       // power-of-two scale applied to the preconditioner input
+  double inv_scale;   // its inverse, applied to the preconditioner output
+  int iter;           // s
+  int done;           // Done code
+  int pinv_count;     // preconditioner applications so far
+  int pad;
+};
+
+// Reduction slots written by the vector and mode-product kernels, one block
+// partial per slot; reduced in a fixed order for bitwise reproducibility.
+enum Slot {
+  S_SUM = 0,   // sum of entries (eta, R or Z)
+  S_SQ,        // sum of squares
+  S_DOT,       // inner product
+  S_AUX,       // second sum of squares (||U||^2)
+  S_AUX2,      // <R_old, Z> for the flexible beta
+  NSLOTS
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  // 64-lane butterfly; every lane ends with the same total, in a fixed order
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block reduction of NV values for a 256-thread block.  Fixed order:
+// butterfly within the wave, then wave 0..3 in sequence.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /*[4*NV]*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w * NV + q];
+    v[q] = t;
+  }
+  __syncthreads();
+}
+
+// bf16 <-> float with round-to-nearest-even
+__device__ __forceinline__ __bf16 f2bf(float x) { return (__bf16)x; }
+__device__ __forceinline__ float bf2f(__bf16 x) { return (float)x; }
+
+template <class T> __device__ __forceinline__ T from_double(double x);
+template <> __device__ __forceinline__ double from_double<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_double<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ __bf16 from_double<__bf16>(double x) { return (__bf16)(float)x; }
+
+template <class T> __device__ __forceinline__ T from_float(float x);
+template <> __device__ __forceinline__ double from_float<double>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float from_float<float>(float x) { return x; }
+template <> __device__ __forceinline__ __bf16 from_float<__bf16>(float x) { return (__bf16)x; }
+
+template <class T> __device__ __forceinline__ double to_double(T x) { return (double)x; }
+template <> __device__ __forceinline__ double to_double<__bf16>(__bf16 x) { return (double)(float)x; }
+
+}  // namespace kp

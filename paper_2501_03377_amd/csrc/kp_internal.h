@@ -1,0 +1,87 @@
+// Host-side interfaces between the kpcg translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kp_common.h"
+
+namespace kp {
+
+// Closed-form orthonormal eigenbasis (host), see kp_basis.cpp.
+int basis_1d(int n, int bc, double* Q, double* lam);
+
+// Device operands of the pseudoinverse preconditioner for one plan.
+struct PinvOps {
+  int dim;              // 2 or 3
+  int prec;             // Prec
+  int n[3];             // nx, ny, nz (nz = 1 in 2D)
+  int np[3];            // padded sizes (row pitch of Q and Qt)
+  const void* Q[3];     // V_l, np x np, row-major, zero-padded, in the compute type
+  const void* Qt[3];    // V_l^T
+  const double* lam[3]; // eigenvalues (FP64)
+};
+
+int pad_to_tile(int n);
+void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T1, int batch,
+                const RhsState* st, hipStream_t s);
+
+// Grid geometry and boundary conditions of one plan.
+struct Geom {
+  int nx, ny, nz, dim;
+  int bc[3];
+  int64_t N;
+  int singular;
+};
+
+// Vector-kernel launchers (kp_vector.hip).  `part` holds NSLOTS x G block
+// partials per right-hand side; G is vec_blocks(N, batch).
+int vec_blocks(int64_t N, int batch);
+void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
+                 RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
+void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
+                       double* P, double* part, RhsState* st, int batch, int G, int first,
+                       double tol, int flags, hipStream_t s);
+void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
+                      RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
+                      int flags, hipStream_t s);
+void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
+                   int batch, int G, hipStream_t s);
+void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int G, hipStream_t s);
+
+// Solve flags (mirrors include/kpcg.h).
+enum {
+  F_NO_PRECOND = 1,
+  F_FLEX_BETA = 2,
+  F_RESIDUAL_ONLY = 4,
+};
+
+}  // namespace kp
+
+namespace kp {
+
+// Kernel classes for the optional per-launch timing (HIP events).
+enum KernelClass {
+  KC_STENCIL = 0,   // W = -Delta(P) with <W,P>
+  KC_UPDATE_UR,     // U += alpha P, R -= alpha W, ||R||^2
+  KC_DOT_RZ,        // <R,Z>, sum Z, ||Z||^2
+  KC_UPDATE_P,      // P = Z - mean + beta P
+  KC_FINALIZE,      // one-block scalar recurrences
+  KC_INIT,          // centering of eta, R_0
+  KC_FINISH,        // true residual, centering of U
+  KC_MP_Z_FWD,      // mode products of the preconditioner
+  KC_MP_Y_FWD,
+  KC_MP_X_FWD,      // includes the Hadamard factor
+  KC_MP_X_BWD,
+  KC_MP_Y_BWD,
+  KC_MP_Z_BWD,
+  KC_COPY,          // Z = R when M = I
+  KC_COUNT
+};
+
+// Records begin/end events around a launch when a tracer is active on this
+// host thread; no-ops otherwise.
+void trace_begin(int cls, hipStream_t s);
+void trace_end(int cls, hipStream_t s);
+
+}  // namespace kp

@@ -1,0 +1,487 @@
+// Plan, workspace and the PCG driver of the kpcg C ABI (include/kpcg.h).
+//
+// A plan is the preconditioner's initialisation (Algs. 4-5): closed-form
+// eigenbases uploaded once.  A solve is Algorithm 1 enqueued on the plan's
+// stream; the scalar recurrences stay on the device, and the host only reads
+// the per-RHS done flags between chunks of iterations.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/kpcg.h"
+#include "kp_common.h"
+#include "kp_internal.h"
+
+using namespace kp;
+
+namespace kp {
+
+// Per-plan launch timer: a begin and an end event around every traced launch
+// on the plan's stream; elapsed times are folded into per-class totals once
+// the stream has been synchronised.
+struct Tracer {
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  hipEvent_t cur = nullptr;
+  double ms[KC_COUNT] = {};
+  int64_t cnt[KC_COUNT] = {};
+
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(int, hipStream_t s) { cur = get(); (void)hipEventRecord(cur, s); }
+  void end(int cls, hipStream_t s) {
+    hipEvent_t e = get();
+    (void)hipEventRecord(e, s);
+    pending.push_back({cls, cur, e});
+    cur = nullptr;
+  }
+  void collect() {
+    for (const Rec& r : pending) {
+      float f = 0.f;
+      if (hipEventElapsedTime(&f, r.a, r.b) == hipSuccess) {
+        ms[r.cls] += f;
+        cnt[r.cls] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int c = 0; c < KC_COUNT; ++c) { ms[c] = 0.0; cnt[c] = 0; }
+  }
+  ~Tracer() {
+    for (const Rec& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+static thread_local Tracer* g_tracer = nullptr;
+void trace_begin(int cls, hipStream_t s) { if (g_tracer) g_tracer->begin(cls, s); }
+void trace_end(int cls, hipStream_t s) { if (g_tracer) g_tracer->end(cls, s); }
+
+}  // namespace kp
+
+struct kp_plan {
+  Geom g;
+  PinvOps op;
+  int prec = 0;
+  int max_batch = 1;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* resident = nullptr;
+  size_t resident_bytes = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  double* hist = nullptr;       // device residual history
+  size_t hist_cap = 0;          // doubles
+  RhsState* st_host = nullptr;  // pinned copy of the state
+  int expect_iters = 0;         // iterations the last solve needed (first chunk size)
+  bool profiling = false;
+  Tracer tracer;
+};
+
+namespace {
+// Activates the plan's tracer on this thread for the lifetime of the guard.
+struct TraceScope {
+  Tracer* prev;
+  explicit TraceScope(kp_plan* p) : prev(g_tracer) { g_tracer = p->profiling ? &p->tracer : nullptr; }
+  ~TraceScope() { g_tracer = prev; }
+};
+}  // namespace
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+
+struct Layout {
+  size_t R, P, W, Z, T0, T1, part, st, total;
+};
+
+Layout layout_for(const kp_plan* p, int batch) {
+  Layout L{};
+  const size_t N = (size_t)p->g.N * (size_t)batch;
+  const int G = vec_blocks(p->g.N, batch);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+  L.R = take(N * 8);
+  L.P = take(N * 8);
+  L.W = take(N * 8);
+  L.Z = take(N * 8);
+  L.T0 = take(N * elem_bytes(p->prec));
+  L.T1 = take(N * elem_bytes(p->prec));
+  L.part = take((size_t)batch * NSLOTS * G * 8);
+  L.st = take((size_t)batch * sizeof(RhsState));
+  L.total = off;
+  return L;
+}
+
+bool ok(hipError_t e) { return e == hipSuccess; }
+
+int ensure_workspace(kp_plan* p) {
+  if (p->ws) return KP_OK;
+  const size_t need = layout_for(p, p->max_batch).total;
+  void* ptr = nullptr;
+  if (!ok(hipMalloc(&ptr, need))) return KP_ENOMEM;
+  p->ws = ptr;
+  p->ws_bytes = need;
+  p->ws_owned = true;
+  return KP_OK;
+}
+
+int ensure_hist(kp_plan* p, size_t doubles) {
+  if (p->hist_cap >= doubles) return KP_OK;
+  if (p->hist) (void)hipFree(p->hist);
+  p->hist = nullptr;
+  p->hist_cap = 0;
+  if (!ok(hipMalloc((void**)&p->hist, doubles * sizeof(double)))) return KP_ENOMEM;
+  p->hist_cap = doubles;
+  return KP_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
+                  const RhsState* st) {
+  char* base = (char*)p->ws;
+  if (flags & KP_FLAG_NO_PRECOND) {
+    trace_begin(KC_COPY, p->stream);
+    (void)hipMemcpyAsync(Z, R, (size_t)p->g.N * batch * 8, hipMemcpyDeviceToDevice, p->stream);
+    trace_end(KC_COPY, p->stream);
+  } else {
+    pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, p->stream);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int kp_basis_1d(int n, int bc, double* Q, double* lambda) {
+  if (n < 3 || bc < 0 || bc > 4 || !Q || !lambda) return KP_EINVAL;
+  return basis_1d(n, bc, Q, lambda) == 0 ? KP_OK : KP_EINVAL;
+}
+
+int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int prec,
+                   int max_batch, void* hip_stream) {
+  if (!out || !bc) return KP_EINVAL;
+  *out = nullptr;
+  if (nx < 3 || ny < 3 || !(nz >= 3 || nz == 1)) return KP_EINVAL;
+  if (prec < 0 || prec > 2 || max_batch < 1) return KP_EINVAL;
+  const int dim = nz == 1 ? 2 : 3;
+  for (int a = 0; a < dim; ++a)
+    if (bc[a] < 0 || bc[a] > 4) return KP_EINVAL;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N >= ((int64_t)1 << 31)) return KP_EINVAL;
+  if ((int64_t)max_batch * nz > 65535) return KP_EINVAL;
+  if (((int64_t)ny * nz + 63) / 64 > 65535) return KP_EINVAL;
+
+  kp_plan* p = new (std::nothrow) kp_plan();
+  if (!p) return KP_ENOMEM;
+  p->g.nx = nx; p->g.ny = ny; p->g.nz = nz; p->g.dim = dim; p->g.N = N;
+  p->g.bc[0] = bc[0]; p->g.bc[1] = bc[1]; p->g.bc[2] = dim == 3 ? bc[2] : KP_BC_D;
+  bool singular = true;
+  for (int a = 0; a < dim; ++a) singular = singular && (bc[a] == KP_BC_P || bc[a] == KP_BC_N);
+  p->g.singular = singular ? 1 : 0;
+  p->prec = prec;
+  p->max_batch = max_batch;
+  p->stream = (hipStream_t)hip_stream;
+  (void)hipGetDevice(&p->device);
+
+  // Host bases, padded with zeros to the tile multiple.
+  const int n[3] = {nx, ny, nz};
+  const size_t eb = elem_bytes(prec);
+  size_t bytes = 0;
+  std::vector<size_t> offQ(3), offQt(3), offL(3);
+  for (int a = 0; a < dim; ++a) {
+    const int np = pad_to_tile(n[a]);
+    p->op.np[a] = np;
+    offQ[a] = bytes; bytes += align_up((size_t)np * np * eb);
+    offQt[a] = bytes; bytes += align_up((size_t)np * np * eb);
+    offL[a] = bytes; bytes += align_up((size_t)n[a] * 8);
+  }
+  std::vector<char> host(bytes, 0);
+  for (int a = 0; a < dim; ++a) {
+    const int na = n[a], np = p->op.np[a];
+    std::vector<double> Q((size_t)na * na), lam(na);
+    if (basis_1d(na, p->g.bc[a], Q.data(), lam.data()) != 0) { delete p; return KP_EINVAL; }
+    for (int r = 0; r < na; ++r)
+      for (int c = 0; c < na; ++c) {
+        const double q = Q[(size_t)r * na + c];
+        const size_t iq = (size_t)r * np + c, it = (size_t)c * np + r;
+        if (prec == PREC_F64) {
+          ((double*)(host.data() + offQ[a]))[iq] = q;
+          ((double*)(host.data() + offQt[a]))[it] = q;
+        } else if (prec == PREC_F32) {
+          ((float*)(host.data() + offQ[a]))[iq] = (float)q;
+          ((float*)(host.data() + offQt[a]))[it] = (float)q;
+        } else {
+          const __hip_bfloat16 b = __double2bfloat16(q);
+          ((__hip_bfloat16*)(host.data() + offQ[a]))[iq] = b;
+          ((__hip_bfloat16*)(host.data() + offQt[a]))[it] = b;
+        }
+      }
+    std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
+  }
+  if (!ok(hipMalloc(&p->resident, bytes))) { delete p; return KP_ENOMEM; }
+  p->resident_bytes = bytes;
+  if (!ok(hipMemcpy(p->resident, host.data(), bytes, hipMemcpyHostToDevice))) {
+    (void)hipFree(p->resident);
+    delete p;
+    return KP_EHIP;
+  }
+  p->op.dim = dim;
+  p->op.prec = prec;
+  for (int a = 0; a < 3; ++a) {
+    p->op.n[a] = n[a];
+    if (a < dim) {
+      p->op.Q[a] = (char*)p->resident + offQ[a];
+      p->op.Qt[a] = (char*)p->resident + offQt[a];
+      p->op.lam[a] = (const double*)((char*)p->resident + offL[a]);
+    } else {
+      p->op.np[a] = 1;
+      p->op.Q[a] = p->op.Qt[a] = nullptr;
+      p->op.lam[a] = nullptr;
+    }
+  }
+  if (!ok(hipHostMalloc((void**)&p->st_host, (size_t)max_batch * sizeof(RhsState),
+                        hipHostMallocDefault))) {
+    (void)hipFree(p->resident);
+    delete p;
+    return KP_ENOMEM;
+  }
+  *out = p;
+  return KP_OK;
+}
+
+void kp_plan_destroy(kp_plan* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  if (p->ws_owned && p->ws) (void)hipFree(p->ws);
+  if (p->hist) (void)hipFree(p->hist);
+  if (p->resident) (void)hipFree(p->resident);
+  if (p->st_host) (void)hipHostFree(p->st_host);
+  delete p;
+}
+
+size_t kp_plan_workspace_bytes(const kp_plan* p, int batch) {
+  if (!p || batch < 1) return 0;
+  return layout_for(p, batch).total;
+}
+
+size_t kp_plan_resident_bytes(const kp_plan* p) { return p ? p->resident_bytes : 0; }
+
+int kp_plan_set_workspace(kp_plan* p, void* dev, size_t bytes) {
+  if (!p || !dev || ((uintptr_t)dev & (ALIGN - 1))) return KP_EINVAL;
+  if (bytes < layout_for(p, p->max_batch).total) return KP_ENOMEM;
+  if (p->ws_owned && p->ws) {
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(p->ws);
+  }
+  p->ws = dev;
+  p->ws_bytes = bytes;
+  p->ws_owned = false;
+  return KP_OK;
+}
+
+int kp_plan_set_stream(kp_plan* p, void* s) {
+  if (!p) return KP_EINVAL;
+  p->stream = (hipStream_t)s;
+  return KP_OK;
+}
+
+int kp_apply_laplacian(kp_plan* p, const double* P, double* W, int batch) {
+  if (!p || !P || !W || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!aligned16(P) || !aligned16(W)) return KP_EINVAL;
+  if (overlap(P, W, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
+  TraceScope scope(p);
+  launch_laplacian(p->g, P, W, batch, vec_blocks(p->g.N, batch), p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int kp_apply_pinv(kp_plan* p, const double* R, double* Z, int batch) {
+  if (!p || !R || !Z || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!aligned16(R) || !aligned16(Z)) return KP_EINVAL;
+  if (overlap(R, Z, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  const Layout L = layout_for(p, batch);
+  char* base = (char*)p->ws;
+  TraceScope scope(p);
+  pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, nullptr, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, int max_iter,
+             int flags, kp_result* results, double* res_hist) {
+  if (!p || !eta || !u || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 1000000) return KP_EINVAL;
+  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY)) return KP_EINVAL;
+  if (!aligned16(eta) || !aligned16(u)) return KP_EINVAL;
+  const size_t vbytes = (size_t)p->g.N * batch * 8;
+  if (overlap(eta, u, vbytes)) return KP_EINVAL;
+  // With M = I the preconditioned residual is R itself, which is no error
+  // estimate: stop on the residual alone.
+  if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  const int hs = max_iter + 1;
+  rc = ensure_hist(p, (size_t)batch * hs);
+  if (rc != KP_OK) return rc;
+  (void)hipGetLastError();
+
+  const Layout L = layout_for(p, batch);
+  char* base = (char*)p->ws;
+  double* R = (double*)(base + L.R);
+  double* P = (double*)(base + L.P);
+  double* W = (double*)(base + L.W);
+  double* Z = (double*)(base + L.Z);
+  double* part = (double*)(base + L.part);
+  RhsState* st = (RhsState*)(base + L.st);
+  const int G = vec_blocks(p->g.N, batch);
+  hipStream_t s = p->stream;
+
+  TraceScope scope(p);
+  if (!ok(hipMemsetAsync(p->hist, 0, (size_t)batch * hs * sizeof(double), s))) return KP_EHIP;
+  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
+  launch_init(p->g, eta, R, u, part, st, p->hist, hs, batch, G, s);
+  precondition(p, L, R, Z, batch, flags, st);
+  launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
+
+  // Iterations in chunks; kernels of finished right-hand sides return at once.
+  int done_iters = 0;
+  // First chunk: what the previous solve on this plan needed (or a guess per
+  // precision); afterwards one iteration per host check, so that a solve that
+  // behaves like the previous one launches no idle iterations.
+  int chunk = p->expect_iters > 0 ? p->expect_iters
+              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_F32 ? 2 : 8)));
+  bool all_done = false;
+  while (done_iters < max_iter) {
+    const int n = std::min(chunk, max_iter - done_iters);
+    for (int q = 0; q < n; ++q) {
+      launch_iter_head(p->g, P, W, R, u, part, st, p->hist, hs, batch, G, tol, flags, s);
+      precondition(p, L, R, Z, batch, flags, st);
+      launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
+    }
+    done_iters += n;
+    if (!ok(hipGetLastError())) return KP_EHIP;
+    if (!ok(hipMemcpyAsync(p->st_host, st, (size_t)batch * sizeof(RhsState),
+                           hipMemcpyDeviceToHost, s)))
+      return KP_EHIP;
+    if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
+    all_done = true;
+    for (int b = 0; b < batch; ++b) all_done = all_done && p->st_host[b].done != RUNNING;
+    if (all_done) break;
+    chunk = 1;
+  }
+  launch_finish(p->g, eta, u, part, st, batch, G, s);
+  if (!ok(hipMemcpyAsync(p->st_host, st, (size_t)batch * sizeof(RhsState), hipMemcpyDeviceToHost,
+                         s)))
+    return KP_EHIP;
+  if (res_hist &&
+      !ok(hipMemcpyAsync(res_hist, p->hist, (size_t)batch * hs * sizeof(double),
+                         hipMemcpyDeviceToHost, s)))
+    return KP_EHIP;
+  if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
+  if (!ok(hipGetLastError())) return KP_EHIP;
+  if (p->profiling) p->tracer.collect();
+
+  int worst = KP_OK;
+  int max_it = 0;
+  for (int b = 0; b < batch; ++b) {
+    const RhsState& x = p->st_host[b];
+    int stt;
+    switch (x.done) {
+      case CONVERGED: case ZERO_RHS: stt = KP_OK; break;
+      case BREAKDOWN: stt = KP_EBREAKDOWN; break;
+      case NONFINITE: stt = KP_ENONFINITE; break;
+      default: stt = KP_NOT_CONVERGED; break;
+    }
+    if (results) {
+      kp_result& r = results[b];
+      r.status = stt;
+      r.iterations = x.iter;
+      r.pinv_applications = x.pinv_count;
+      r.reserved = 0;
+      r.rel_res = x.rel_res;
+      r.true_rel_res = x.true_rel_res;
+      r.err_est = x.err_est;
+      r.removed_mean = x.mean;
+    }
+    if (stt < 0 && (worst >= 0 || stt < worst)) worst = stt;
+    else if (stt == KP_NOT_CONVERGED && worst == KP_OK) worst = stt;
+    if (stt == KP_OK) max_it = std::max(max_it, x.iter);
+  }
+  if (max_it > 0) p->expect_iters = max_it;
+  return worst;
+}
+
+const char* kp_strerror(int s) {
+  switch (s) {
+    case KP_OK: return "ok";
+    case KP_NOT_CONVERGED: return "not converged within max_iter";
+    case KP_EINVAL: return "invalid argument";
+    case KP_ENOMEM: return "out of device memory or workspace too small";
+    case KP_EHIP: return "HIP runtime error";
+    case KP_ENONFINITE: return "non-finite value in right-hand side or iterate";
+    case KP_EBREAKDOWN: return "CG breakdown (non-positive curvature or rho)";
+    default: return "unknown status";
+  }
+}
+
+const char* kp_version(void) { return "kpcg 0.1 (gfx950)"; }
+
+int kp_plan_set_profiling(kp_plan* p, int enable) {
+  if (!p) return KP_EINVAL;
+  p->profiling = enable != 0;
+  return KP_OK;
+}
+
+int kp_plan_profile(kp_plan* p, int cls, double* total_ms, int64_t* launches) {
+  if (!p || cls < 0 || cls >= KC_COUNT) return KP_EINVAL;
+  if (!ok(hipStreamSynchronize(p->stream))) return KP_EHIP;
+  p->tracer.collect();
+  if (total_ms) *total_ms = p->tracer.ms[cls];
+  if (launches) *launches = p->tracer.cnt[cls];
+  return KP_OK;
+}
+
+int kp_plan_profile_reset(kp_plan* p) {
+  if (!p) return KP_EINVAL;
+  if (!ok(hipStreamSynchronize(p->stream))) return KP_EHIP;
+  p->tracer.collect();
+  p->tracer.reset();
+  return KP_OK;
+}
+
+const char* kp_kernel_class_name(int cls) {
+  static const char* names[KC_COUNT] = {
+      "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
+      "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd_scale", "modeprod_x_bwd",
+      "modeprod_y_bwd", "modeprod_z_bwd", "copy"};
+  return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+"""ctypes binding of the kpcg C ABI (include/kpcg.h).
+
+Argument marshalling only: every step of a solve runs in the HIP library.
+The raw entry points keep the C names (kp_plan_create, kp_solve, ...); the
+`Plan` class wraps them for torch tensors.  PyTorch is used only for device
+memory and streams.  If the library has not been built this module raises
+on import: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkpcg.so")
+
+BC = {"P": 0, "D": 1, "N": 2, "DN": 3, "ND": 4}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+
+KP_OK = 0
+KP_NOT_CONVERGED = 1
+KP_EINVAL = -1
+KP_ENOMEM = -2
+KP_EHIP = -3
+KP_ENONFINITE = -4
+KP_EBREAKDOWN = -5
+
+KP_FLAG_NO_PRECOND = 1
+KP_FLAG_FLEX_BETA = 2
+KP_FLAG_RESIDUAL_ONLY = 4
+
+# Every symbol declared in include/kpcg.h.
+EXPORTS = (
+    "kp_basis_1d", "kp_plan_create", "kp_plan_destroy", "kp_plan_workspace_bytes",
+    "kp_plan_resident_bytes", "kp_plan_set_workspace", "kp_plan_set_stream",
+    "kp_apply_laplacian", "kp_apply_pinv", "kp_solve", "kp_strerror", "kp_version",
+    "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
+)
+KERNEL_CLASSES = 14
+
+
+class KpResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("pinv_applications", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("rel_res", ctypes.c_double),
+        ("true_rel_res", ctypes.c_double),
+        ("err_est", ctypes.c_double),
+        ("removed_mean", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class KpError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {kp_strerror(status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2501_03377_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "kp_basis_1d": (i, [i, i, pd, pd]),
+        "kp_plan_create": (i, [ctypes.POINTER(vp), i, i, i, ctypes.POINTER(ctypes.c_int), i, i, vp]),
+        "kp_plan_destroy": (None, [vp]),
+        "kp_plan_workspace_bytes": (sz, [vp, i]),
+        "kp_plan_resident_bytes": (sz, [vp]),
+        "kp_plan_set_workspace": (i, [vp, vp, sz]),
+        "kp_plan_set_stream": (i, [vp, vp]),
+        "kp_apply_laplacian": (i, [vp, vp, vp, i]),
+        "kp_apply_pinv": (i, [vp, vp, vp, i]),
+        "kp_solve": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(KpResult), pd]),
+        "kp_strerror": (ctypes.c_char_p, [i]),
+        "kp_version": (ctypes.c_char_p, []),
+        "kp_plan_set_profiling": (i, [vp, i]),
+        "kp_plan_profile": (i, [vp, i, pd, ctypes.POINTER(ctypes.c_int64)]),
+        "kp_plan_profile_reset": (i, [vp]),
+        "kp_kernel_class_name": (ctypes.c_char_p, [i]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+# ------------------------------------------------------- raw entry points ----
+def kp_strerror(status):
+    return _lib.kp_strerror(int(status)).decode()
+
+
+def kp_version():
+    return _lib.kp_version().decode()
+
+
+def kp_basis_1d(n, bc):
+    """Closed-form orthonormal eigenbasis (host): returns (Q, lam), Q[:, c]
+    the c-th eigenvector."""
+    Q = np.zeros((n, n))
+    lam = np.zeros(n)
+    rc = _lib.kp_basis_1d(int(n), BC[bc] if isinstance(bc, str) else int(bc),
+                          Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != KP_OK:
+        raise KpError(rc, "kp_basis_1d")
+    return Q, lam
+
+
+def kp_plan_create(nx, ny, nz, bc, prec, max_batch, stream):
+    handle = ctypes.c_void_p()
+    arr = (ctypes.c_int * 3)(*bc)
+    rc = _lib.kp_plan_create(ctypes.byref(handle), nx, ny, nz, arr, prec, max_batch,
+                             ctypes.c_void_p(stream))
+    return rc, handle
+
+
+def kp_plan_destroy(handle):
+    _lib.kp_plan_destroy(handle)
+
+
+def kp_plan_workspace_bytes(handle, batch):
+    return int(_lib.kp_plan_workspace_bytes(handle, batch))
+
+
+def kp_plan_resident_bytes(handle):
+    return int(_lib.kp_plan_resident_bytes(handle))
+
+
+def kp_plan_set_workspace(handle, ptr, nbytes):
+    return _lib.kp_plan_set_workspace(handle, ctypes.c_void_p(ptr), nbytes)
+
+
+def kp_plan_set_stream(handle, stream):
+    return _lib.kp_plan_set_stream(handle, ctypes.c_void_p(stream))
+
+
+def kp_apply_laplacian(handle, p_ptr, w_ptr, batch):
+    return _lib.kp_apply_laplacian(handle, ctypes.c_void_p(p_ptr), ctypes.c_void_p(w_ptr), batch)
+
+
+def kp_apply_pinv(handle, r_ptr, z_ptr, batch):
+    return _lib.kp_apply_pinv(handle, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr), batch)
+
+
+def kp_solve(handle, eta_ptr, u_ptr, batch, tol, max_iter, flags, results, hist):
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist is not None else None
+    return _lib.kp_solve(handle, ctypes.c_void_p(eta_ptr), ctypes.c_void_p(u_ptr), batch,
+                         float(tol), int(max_iter), int(flags), results, hp)
+
+
+def kp_plan_set_profiling(handle, enable):
+    return _lib.kp_plan_set_profiling(handle, int(enable))
+
+
+def kp_plan_profile(handle, cls):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    rc = _lib.kp_plan_profile(handle, int(cls), ctypes.byref(ms), ctypes.byref(cnt))
+    return rc, ms.value, cnt.value
+
+
+def kp_plan_profile_reset(handle):
+    return _lib.kp_plan_profile_reset(handle)
+
+
+def kp_kernel_class_name(cls):
+    return _lib.kp_kernel_class_name(int(cls)).decode()
+
+
+# ------------------------------------------------------------ torch layer ----
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A plan for one grid, boundary-condition triple and precision.
+
+    Grid functions are float64 CUDA tensors shaped (nz, ny, nx) (3D),
+    (ny, nx) (2D) or with a leading batch dimension.
+    """
+
+    def __init__(self, nx, ny, nz, bcs, prec="f64", max_batch=1, stream=None):
+        torch = _torch()
+        self.shape = (nz, ny, nx) if nz > 1 else (ny, nx)
+        self.N = nx * ny * nz
+        self.dims = (nx, ny, nz)
+        bcs = tuple(bcs) + ("D",) * (3 - len(bcs))
+        self.bcs = bcs
+        self.prec = prec
+        self.max_batch = max_batch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        rc, self._h = kp_plan_create(nx, ny, nz, [BC[b] for b in bcs], PREC[prec], max_batch,
+                                     stream.cuda_stream)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_create")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            kp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self):
+        return kp_plan_workspace_bytes(self._h, self.max_batch)
+
+    @property
+    def resident_bytes(self):
+        return kp_plan_resident_bytes(self._h)
+
+    def _check(self, t, name):
+        torch = _torch()
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        if t.numel() % self.N:
+            raise ValueError(f"{name} size is not a multiple of the grid size")
+        return t.numel() // self.N
+
+    def set_profiling(self, enable=True):
+        rc = kp_plan_set_profiling(self._h, enable)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_set_profiling")
+
+    def profile(self):
+        """{class name: (total_ms, launches)} accumulated since the last reset."""
+        out = {}
+        for c in range(KERNEL_CLASSES):
+            rc, ms, cnt = kp_plan_profile(self._h, c)
+            if rc != KP_OK:
+                raise KpError(rc, "kp_plan_profile")
+            out[kp_kernel_class_name(c)] = (ms, cnt)
+        return out
+
+    def profile_reset(self):
+        rc = kp_plan_profile_reset(self._h)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_profile_reset")
+
+    def apply_laplacian(self, P, out=None):
+        batch = self._check(P, "P")
+        W = out if out is not None else _torch().empty_like(P)
+        rc = kp_apply_laplacian(self._h, P.data_ptr(), W.data_ptr(), batch)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_apply_laplacian")
+        return W
+
+    def apply_pinv(self, R, out=None):
+        batch = self._check(R, "R")
+        Z = out if out is not None else _torch().empty_like(R)
+        rc = kp_apply_pinv(self._h, R.data_ptr(), Z.data_ptr(), batch)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_apply_pinv")
+        return Z
+
+    def solve(self, eta, tol=1e-10, max_iter=50, flags=0, out=None, raise_on_error=True):
+        """Returns (u, results, history, status); results is a list of dicts,
+        history a (batch, max_iter+1) numpy array of ||R_s|| / ||eta_c||."""
+        batch = self._check(eta, "eta")
+        u = out if out is not None else _torch().empty_like(eta)
+        results = (KpResult * batch)()
+        hist = np.zeros((batch, max_iter + 1))
+        rc = kp_solve(self._h, eta.data_ptr(), u.data_ptr(), batch, tol, max_iter, flags,
+                      results, hist)
+        if rc < 0 and raise_on_error:
+            raise KpError(rc, "kp_solve")
+        return u, [r.as_dict() for r in results], hist, rc

@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and its closed-form bases (host code) match the oracle's LAPACK
+bases.  No GPU is touched."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "kpcg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_2501_03377_amd import kpcg
+    lib = ctypes.CDLL(kpcg.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(kpcg.EXPORTS)
+
+
+def test_version_and_strerror():
+    from paper_2501_03377_amd import kpcg
+    assert "kpcg" in kpcg.kp_version()
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert kpcg.kp_strerror(code) != "unknown status"
+
+
+@pytest.mark.parametrize("bc", oracle.BCS)
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 17, 64, 96, 129, 256, 512])
+def test_closed_form_basis_matches_oracle(n, bc):
+    from paper_2501_03377_amd import kp_basis_1d
+    Q, lam = kp_basis_1d(n, bc)
+    V, lo, _ = oracle.pinv_init((n,), (bc,))
+    V, lo = V[0], lo[0]
+    assert np.max(np.abs(lam - lo)) < 1e-13 * max(1, n / 64)
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 5e-15 * max(1, n / 16)
+    L = oracle.laplacian_1d(n, bc)
+    assert np.max(np.abs(L @ Q - Q * lam)) < 1e-14 * max(1, n / 16)
+    # equal spectral projectors on each eigenvalue cluster
+    for value in np.unique(np.round(lo, 9)):
+        a = np.abs(lam - value) < 1e-9
+        b = np.abs(lo - value) < 1e-9
+        assert a.sum() == b.sum()
+        assert np.max(np.abs(Q[:, a] @ Q[:, a].T - V[:, b] @ V[:, b].T)) < 1e-12
+
+
+def test_basis_rejects_bad_input():
+    from paper_2501_03377_amd import KpError, kp_basis_1d
+    with pytest.raises(KpError):
+        kp_basis_1d(2, "D")
+    with pytest.raises(KpError):
+        kp_basis_1d(5, 7)
+
+
+def test_smallest_eigenvalue_accuracy():
+    # 4 sin^2(theta/2) keeps relative accuracy where 2 - 2 cos(theta) loses it
+    from paper_2501_03377_amd import kp_basis_1d
+    import math
+    _, lam = kp_basis_1d(512, "DN")
+    exact = 4 * math.sin(math.pi / (2 * (2 * 512 + 1))) ** 2
+    assert abs(lam[0] - exact) / exact < 1e-15

@@ -1,0 +1,106 @@
+"""GPU parity of the individual operators against the oracle: the minus
+Laplacian of eq. (3.2) and the pseudoinverse preconditioner of Algs. 6-7."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import grid_dims, oracle_laplacian, oracle_pinv, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+ALL3 = list(itertools.product(oracle.BCS, repeat=3))
+ALL2 = list(itertools.product(oracle.BCS, repeat=2))
+
+
+def _plan(shape, bcs, prec="f64", max_batch=1):
+    from paper_2501_03377_amd import Plan
+    nx, ny, nz = grid_dims(shape)
+    return Plan(nx, ny, nz, bcs, prec=prec, max_batch=max_batch)
+
+
+def test_stencil_all_bc_triples_exact_on_integers():
+    # integer data: the stencil has integer coefficients, so results are exact
+    import torch
+    rng = np.random.default_rng(0)
+    shape = (5, 6, 7)
+    p = rng.integers(-50, 50, size=shape).astype(np.float64)
+    for bcs in ALL3:
+        plan = _plan(shape, bcs)
+        w = to_host(plan.apply_laplacian(to_dev(p)))
+        torch.cuda.synchronize()
+        assert np.array_equal(w, oracle_laplacian(p, bcs)), bcs
+        plan.close()
+
+
+def test_stencil_all_bc_pairs_2d():
+    import torch
+    rng = np.random.default_rng(1)
+    shape = (9, 13)
+    p = rng.integers(-50, 50, size=shape).astype(np.float64)
+    for bcs in ALL2:
+        plan = _plan(shape, bcs)
+        w = to_host(plan.apply_laplacian(to_dev(p)))
+        torch.cuda.synchronize()
+        assert np.array_equal(w, oracle_laplacian(p, bcs)), bcs
+
+
+@pytest.mark.parametrize("shape,bcs", [((33, 67, 130), ("P", "P", "DN")),
+                                       ((128, 256, 256), ("P", "P", "DN"))])
+def test_stencil_random_large(shape, bcs):
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(shape)
+    plan = _plan(shape, bcs, max_batch=2)
+    w = to_host(plan.apply_laplacian(to_dev(np.stack([p, 2 * p]))))
+    ref = oracle_laplacian(p, bcs)
+    assert np.max(np.abs(w[0] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert np.max(np.abs(w[1] - 2 * ref)) <= 2e-13 * np.max(np.abs(ref))
+
+
+PINV_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16": 5e-2}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape,bcs", [
+    ((5, 4, 3), ("D", "N", "P")),
+    ((7, 70, 67), ("P", "DN", "ND")),
+    ((33, 65, 130), ("P", "P", "DN")),
+    ((20, 17), ("D", "D")),
+    ((64, 64), ("P", "N")),
+])
+def test_pinv_parity(shape, bcs, prec):
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(shape)
+    plan = _plan(shape, bcs, prec=prec)
+    z = to_host(plan.apply_pinv(to_dev(r)))
+    ref = oracle_pinv(r, bcs)
+    err = rel(z, ref)
+    print(f"pinv {prec} {shape} {bcs}: rel err {err:.3e}")
+    assert err <= PINV_TOL[prec], err
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_pinv_all_bc_triples_small(prec):
+    rng = np.random.default_rng(4)
+    shape = (4, 5, 6)
+    r = rng.standard_normal(shape)
+    for bcs in ALL3:
+        plan = _plan(shape, bcs, prec=prec)
+        z = to_host(plan.apply_pinv(to_dev(r)))
+        err = rel(z, oracle_pinv(r, bcs))
+        assert err <= PINV_TOL[prec], (bcs, err)
+        plan.close()
+
+
+def test_pinv_batch_matches_single():
+    import torch
+    rng = np.random.default_rng(5)
+    shape = (12, 40, 33)
+    r = rng.standard_normal((3,) + shape)
+    plan = _plan(shape, ("P", "D", "N"), prec="f64", max_batch=3)
+    zb = to_host(plan.apply_pinv(to_dev(r)))
+    for b in range(3):
+        z1 = to_host(plan.apply_pinv(to_dev(r[b])))
+        assert np.array_equal(zb[b], z1)

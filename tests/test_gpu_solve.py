@@ -1,0 +1,147 @@
+"""GPU parity of whole solves (Algorithm 1 with the pseudoinverse
+preconditioner) against the converged oracle solution."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import grid_dims, oracle_solve, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+ALL3 = list(itertools.product(oracle.BCS, repeat=3))
+ALL2 = list(itertools.product(oracle.BCS, repeat=2))
+
+
+def _solve(eta, bcs, prec="f64", tol=1e-10, max_iter=50, flags=0, batch=None):
+    from paper_2501_03377_amd import Plan
+    shape = eta.shape if batch is None else eta.shape[1:]
+    nx, ny, nz = grid_dims(shape)
+    plan = Plan(nx, ny, nz, bcs, prec=prec, max_batch=batch or 1)
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=tol, max_iter=max_iter, flags=flags,
+                                  raise_on_error=False)
+    out = to_host(u)
+    plan.close()
+    return out, res, hist, rc
+
+
+def _zero_mean_if(u, bcs):
+    return u - u.mean() if oracle.is_singular(bcs) else u
+
+
+def test_all_bc_triples_small_f64():
+    rng = np.random.default_rng(10)
+    shape = (5, 6, 7)
+    eta = rng.standard_normal(shape)
+    for bcs in ALL3:
+        u, res, hist, rc = _solve(eta, bcs)
+        ref = oracle_solve(eta, bcs)
+        err = rel(_zero_mean_if(u, bcs), ref)
+        assert rc == 0 and err <= 1e-10, (bcs, rc, err, res)
+        assert res[0]["true_rel_res"] <= 1e-10
+
+
+def test_all_bc_pairs_2d_f64():
+    rng = np.random.default_rng(11)
+    eta = rng.standard_normal((9, 13))
+    for bcs in ALL2:
+        u, res, hist, rc = _solve(eta, bcs)
+        err = rel(_zero_mean_if(u, bcs), oracle_solve(eta, bcs))
+        assert rc == 0 and err <= 1e-10, (bcs, rc, err)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("shape,bcs", [
+    ((33, 67, 130), ("P", "P", "DN")),
+    ((40, 40, 40), ("N", "N", "N")),
+    ((70, 36, 36), ("P", "P", "D")),
+])
+def test_multi_tile_ragged(shape, bcs, prec):
+    eta = synth.charge_field(shape, ncharges=2000, seed=7)
+    u, res, hist, rc = _solve(eta, bcs, prec=prec, tol=1e-10, max_iter=60,
+                              flags=2 if prec == "bf16" else 0)
+    ref = oracle_solve(eta, bcs)
+    err = rel(u, ref)
+    print(f"{prec} {shape} {bcs}: iters {res[0]['iterations']} pinv {res[0]['pinv_applications']} "
+          f"err {err:.3e} rel_res {res[0]['rel_res']:.3e} true {res[0]['true_rel_res']:.3e}")
+    assert rc == 0, res
+    assert err <= 1e-10, err
+    assert res[0]["true_rel_res"] <= 1e-10
+
+
+def test_config1_2d_dirichlet_blobs():
+    # 2D 64 x 64, Dirichlet on every edge, 16 Gaussian blobs, FP64, tol 1e-12
+    eta = synth.gaussian_blobs_2d(64, 64, 16, 2.0, seed=1)
+    u, res, hist, rc = _solve(eta, ("D", "D"), prec="f64", tol=1e-12)
+    err = rel(u, oracle_solve(eta, ("D", "D")))
+    assert rc == 0 and err <= 1e-10, (err, res)
+    assert res[0]["rel_res"] <= 1e-12 and res[0]["true_rel_res"] <= 1e-12
+
+
+def test_config2_full_size_f32():
+    # 256 x 256 x 128, (P, P, DN), 1e4 charges + N(0, 1e-3), FP32 MFMA, tol 1e-10
+    eta = synth.charge_field((128, 256, 256), seed=2)
+    u, res, hist, rc = _solve(eta, ("P", "P", "DN"), prec="f32", tol=1e-10)
+    err = rel(u, oracle_solve(eta, ("P", "P", "DN")))
+    print("cfg2", res[0], err)
+    assert rc == 0 and err <= 1e-10
+
+
+def test_batch_matches_single_f64():
+    shape = (24, 20, 36)
+    etas = np.stack([synth.charge_field(shape, ncharges=300, seed=3000 + b) for b in range(3)])
+    ub, resb, _, rc = _solve(etas, ("N", "N", "N"), batch=3)
+    assert rc == 0
+    for b in range(3):
+        u1, res1, _, _ = _solve(etas[b], ("N", "N", "N"))
+        assert np.array_equal(ub[b], u1), b
+        assert resb[b]["iterations"] == res1[0]["iterations"]
+
+
+def test_reruns_are_bitwise_identical():
+    eta = synth.charge_field((16, 32, 48), ncharges=100, seed=9)
+    a = _solve(eta, ("P", "D", "N"), prec="f32")[0]
+    b = _solve(eta, ("P", "D", "N"), prec="f32")[0]
+    assert np.array_equal(a, b)
+
+
+def test_edge_cases():
+    from paper_2501_03377_amd import KP_EINVAL, KP_ENONFINITE, KP_NOT_CONVERGED, Plan
+    import torch
+    shape = (6, 7, 8)
+    # zero right-hand side
+    u, res, _, rc = _solve(np.zeros(shape), ("D", "D", "D"))
+    assert rc == 0 and np.max(np.abs(u)) == 0.0 and res[0]["iterations"] == 0
+    # constant right-hand side on a singular operator: projected out, u = 0
+    u, res, _, rc = _solve(np.full(shape, 3.0), ("P", "N", "P"))
+    assert rc == 0 and np.max(np.abs(u)) == 0.0 and abs(res[0]["removed_mean"] - 3.0) < 1e-15
+    # non-finite input
+    bad = np.ones(shape); bad[1, 2, 3] = np.nan
+    u, res, _, rc = _solve(bad, ("D", "D", "D"))
+    assert rc == KP_ENONFINITE
+    # iteration cap
+    eta = synth.charge_field(shape, ncharges=20, seed=1)
+    u, res, hist, rc = _solve(eta, ("D", "D", "D"), flags=1, max_iter=1)
+    assert rc == KP_NOT_CONVERGED and res[0]["iterations"] == 1
+    # invalid arguments are rejected before any work
+    plan = Plan(8, 7, 6, ("D", "D", "D"))
+    x = to_dev(eta)
+    with pytest.raises(Exception):
+        plan.solve(x, tol=-1.0)
+    with pytest.raises(Exception):
+        plan.solve(x, max_iter=0)
+    from paper_2501_03377_amd.kpcg import kp_plan_create, kp_solve
+    assert kp_plan_create(2, 5, 5, [0, 0, 0], 0, 1, 0)[0] == KP_EINVAL
+    assert kp_plan_create(5, 5, 5, [0, 9, 0], 0, 1, 0)[0] == KP_EINVAL
+    assert kp_plan_create(5, 5, 2, [0, 0, 0], 0, 1, 0)[0] == KP_EINVAL
+    assert kp_solve(plan._h, x.data_ptr(), x.data_ptr(), 1, 1e-8, 5, 0, None, None) == KP_EINVAL
+
+
+def test_unpreconditioned_cg():
+    eta = synth.charge_field((10, 12, 14), ncharges=50, seed=4)
+    u, res, hist, rc = _solve(eta, ("D", "P", "N"), flags=1, max_iter=500, tol=1e-13)
+    assert rc == 0 and res[0]["iterations"] > 10
+    assert rel(u, oracle_solve(eta, ("D", "P", "N"))) <= 1e-9
