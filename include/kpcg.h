@@ -68,7 +68,8 @@ enum kp_flags {
   KP_FLAG_FLEX_BETA = 2,    /* beta_s = <R_s - R_{s-1}, Z_s>/rho_{s-1} instead of
                                Algorithm 1's rho_s/rho_{s-1}; for inexact
                                (low-precision) preconditioners */
-  KP_FLAG_RESIDUAL_ONLY = 4 /* stop on the relative residual alone (see kp_solve) */
+  KP_FLAG_RESIDUAL_ONLY = 4,/* stop on the relative residual alone (see kp_solve) */
+  KP_FLAG_NO_GRAPH = 8      /* launch every kernel directly (no HIP graph replay) */
 };
 
 typedef struct kp_plan kp_plan;   /* opaque */
@@ -105,8 +106,7 @@ int kp_basis_1d(int n, int bc, double* Q, double* lambda);
  *   prec       kp_prec
  *   max_batch  largest batch a solve may use (>= 1)
  *   hip_stream hipStream_t to enqueue on (NULL = default stream)
- * Limits: nx*ny*nz < 2^31; grid dimensions must fit HIP launch limits
- * (max_batch*nz <= 65535 and ny*nz <= 4,194,240).
+ * Limits: nx*ny*nz < 2^31; ceil(nx/64)*ceil(ny/4) <= 8192; max_batch <= 65535.
  * Returns KP_OK, KP_EINVAL, KP_ENOMEM or KP_EHIP. */
 int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int prec,
                    int max_batch, void* hip_stream);
@@ -158,17 +158,41 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
  * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
  * set, also ||Z_s||/||U_s|| <= tol (Z_s = M(R_s) estimates the error of U_s).
+ * Execution: the solve runs on a stream private to the plan, ordered after
+ * earlier work on the plan's stream.  The first chunk of iterations (as many
+ * as the previous solve on this plan needed) is captured once as a HIP graph
+ * and replayed; the cache is keyed by batch, iteration count, flags, tol,
+ * max_iter and u, and invalidated by kp_plan_set_workspace, the tuning calls
+ * and kp_plan_set_profiling.  Results are identical with KP_FLAG_NO_GRAPH.
  * Returns the most severe per-RHS status (errors first, then
  * KP_NOT_CONVERGED); KP_EINVAL before any work for bad arguments.  Blocks
  * until the results are on the host. */
 int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol, int max_iter,
              int flags, kp_result* results, double* res_hist);
 
+/* Autotuner for the preconditioner's mode products.  Every product of
+ * Algs. 6-7 is one GEMM; several tile shapes are compiled (waves per block,
+ * rows and columns per wave).  For each product of this plan the call times
+ * every tile shape on `batch` right-hand sides (`reps` launches each, HIP
+ * events on the plan's stream, on scratch data in the workspace) and keeps
+ * the fastest.  chosen: host, 2*dim ints (may be NULL), receives the choice in
+ * product order x, y, z forward then x, y, z backward (2D: x, y, x, y).
+ * Results do not depend on the choice beyond floating-point summation order
+ * within a tile, which is fixed per shape.  Returns KP_OK, KP_EINVAL,
+ * KP_ENOMEM or KP_EHIP. */
+int kp_plan_autotune(kp_plan* plan, int batch, int reps, int* chosen);
+/* Copies the current tile choices (2*dim ints) to cfg; returns 2*dim or
+ * KP_EINVAL.  kp_plan_set_tuning installs saved choices (n must be 2*dim;
+ * KP_EINVAL for unknown ids), e.g. from a cache of earlier autotune runs. */
+int kp_plan_get_tuning(const kp_plan* plan, int* cfg, int n);
+int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
+
 /* Per-kernel timing (the library's tracing facility).  When enabled, every
  * kernel launch of the plan is bracketed by HIP events on the plan's stream
  * and its duration is added to one of KP_KERNEL_CLASSES classes, named by
  * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
- * products of Algs. 6-7, ...).  Timing adds two event records per launch. */
+ * products of Algs. 6-7, ...).  Timing adds two event records per launch;
+ * while it is on, kp_solve launches every kernel directly (no graph replay). */
 #define KP_KERNEL_CLASSES 14
 int kp_plan_set_profiling(kp_plan* plan, int enable);
 /* Synchronises the plan's stream, then returns the accumulated milliseconds
@@ -178,6 +202,10 @@ int kp_plan_profile(kp_plan* plan, int cls, double* total_ms, int64_t* launches)
 int kp_plan_profile_reset(kp_plan* plan);
 /* Name of a kernel class, "unknown" when out of range. */
 const char* kp_kernel_class_name(int cls);
+
+/* Number of captured iteration graphs the plan holds, or -1 if graph capture
+ * turned out to be unavailable (solves then launch kernels directly). */
+int kp_plan_graph_count(const kp_plan* plan);
 
 /* Human-readable name of a status code. */
 const char* kp_strerror(int status);

@@ -4,8 +4,10 @@ and this thin Python binding."""
 
 from .kpcg import (Plan, KpError, KpResult, kp_basis_1d, kp_version, kp_strerror, BC, PREC,
                    KP_OK, KP_NOT_CONVERGED, KP_EINVAL, KP_ENOMEM, KP_EHIP, KP_ENONFINITE,
-                   KP_EBREAKDOWN, KP_FLAG_NO_PRECOND, KP_FLAG_FLEX_BETA, KP_FLAG_RESIDUAL_ONLY)
+                   KP_EBREAKDOWN, KP_FLAG_NO_PRECOND, KP_FLAG_FLEX_BETA, KP_FLAG_RESIDUAL_ONLY,
+                   KP_FLAG_NO_GRAPH)
 
 __all__ = ["Plan", "KpError", "KpResult", "kp_basis_1d", "kp_version", "kp_strerror", "BC", "PREC",
            "KP_OK", "KP_NOT_CONVERGED", "KP_EINVAL", "KP_ENOMEM", "KP_EHIP", "KP_ENONFINITE",
-           "KP_EBREAKDOWN", "KP_FLAG_NO_PRECOND", "KP_FLAG_FLEX_BETA", "KP_FLAG_RESIDUAL_ONLY"]
+           "KP_EBREAKDOWN", "KP_FLAG_NO_PRECOND", "KP_FLAG_FLEX_BETA", "KP_FLAG_RESIDUAL_ONLY",
+           "KP_FLAG_NO_GRAPH"]

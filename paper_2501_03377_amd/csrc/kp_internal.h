@@ -16,13 +16,22 @@ struct PinvOps {
   int dim;              // 2 or 3
   int prec;             // Prec
   int n[3];             // nx, ny, nz (nz = 1 in 2D)
-  int np[3];            // padded sizes (row pitch of Q and Qt)
-  const void* Q[3];     // V_l, np x np, row-major, zero-padded, in the compute type
-  const void* Qt[3];    // V_l^T
+  int64_t N;            // nx * ny * nz
+  const void* Bf[3];    // V_l packed for the forward product (mp_pack)
+  const void* Bb[3];    // V_l^T packed for the backward product
   const double* lam[3]; // eigenvalues (FP64)
+  int cfg[6];           // tile configuration of each mode product, in order
 };
 
-int pad_to_tile(int n);
+// Mode-product kernel configuration and packed operator layout (kp_modeprod.hip).
+int mp_num_configs();
+void mp_config(int id, int* wn, int* wm, int* wc);
+int mp_default_config(int K, int prec);
+bool mp_config_allowed(int id, int prec);
+void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch, hipStream_t s);
+size_t mp_packed_bytes(int K, int prec);
+void mp_pack(const double* B, int K, int prec, void* dst);
+
 void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T1, int batch,
                 const RhsState* st, hipStream_t s);
 
@@ -37,6 +46,7 @@ struct Geom {
 // Vector-kernel launchers (kp_vector.hip).  `part` holds NSLOTS x G block
 // partials per right-hand side; G is vec_blocks(N, batch).
 int vec_blocks(int64_t N, int batch);
+bool zgrid_fits(const Geom& g);
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
@@ -46,8 +56,10 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
                       int flags, hipStream_t s);
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
-                   int batch, int G, hipStream_t s);
+                   RhsState* mirror, int batch, int G, hipStream_t s);
 void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int G, hipStream_t s);
+void launch_copy(const Geom& g, const double* src, double* dst, const RhsState* st, int batch,
+                 int G, hipStream_t s);
 
 // Solve flags (mirrors include/kpcg.h).
 enum {
@@ -69,9 +81,9 @@ enum KernelClass {
   KC_FINALIZE,      // one-block scalar recurrences
   KC_INIT,          // centering of eta, R_0
   KC_FINISH,        // true residual, centering of U
-  KC_MP_Z_FWD,      // mode products of the preconditioner
-  KC_MP_Y_FWD,
-  KC_MP_X_FWD,      // includes the Hadamard factor
+  KC_MP_Z_FWD,      // mode products of the preconditioner; the Hadamard
+  KC_MP_Y_FWD,      // factor rides on the last forward one (z in 3D, y in 2D)
+  KC_MP_X_FWD,
   KC_MP_X_BWD,
   KC_MP_Y_BWD,
   KC_MP_Z_BWD,

@@ -1,353 +1,554 @@
 // Mode products of the pseudoinverse preconditioner (Algs. 6 and 7, Sec. 4.3.3)
 // on the gfx950 matrix cores.
 //
-// The preconditioner is Z = (V_x, V_y, V_z | G .* (V_x^T, V_y^T, V_z^T | R)).
-// With the grid stored [z][y][x] (x contiguous) each l-mode product is a GEMM:
-//   * y- and z-modes ("left" products): Y[b][m][n] = sum_k A[m][k] X[b][k][n],
-//     where k runs over the contracted axis (stride ldk) and n over the
-//     contiguous rest; A = V^T (forward) or V (backward);
-//   * x-mode ("right" product): Y[r][n] = sum_k X[r][k] B[k][n], with r the
-//     (y, z) fibre index and B = V_x (forward) or V_x^T (backward); the
-//     forward x product also applies the Hadamard factor G of eq. (4.6).
+// Z = (V_x, V_y, V_z | G .* (V_x^T, V_y^T, V_z^T | R)).  Every l-mode product
+// is applied as one GEMM that contracts the *contiguous* axis of its input:
+//     C[r][n] = sum_k X[r][k] B[k][n],    X viewed as [A0][A1][K] -> rows r,
+// and writes C transposed, Y[n][r], i.e. the layout [K'][A0][A1]: the
+// transformed axis moves to the front.  Three such products return the
+// original layout, so the sequence (3D; grids stored [z][y][x], x fastest)
+//   [z][y][x] -x->  [x'][z][y] -y-> [y'][x'][z] -z,G-> [z'][y'][x']
+//             -x->  [x][z'][y'] -y-> [y][x][z']  -z->  [z][y][x]
+// contracts x, y, z forward, applies the Hadamard factor G of eq. (4.6) in the
+// third product's epilogue, and contracts x, y, z backward (2D: x, y+G, x, y).
+// The mode products commute (Sec. 2.2), so this order is the paper's operator.
 //
-// Precisions: FP64 MFMA (v_mfma_f64_16x16x4), FP32 MFMA (v_mfma_f32_16x16x4)
-// and BF16 MFMA with FP32 accumulation (v_mfma_f32_16x16x32_bf16).  Operands:
-// lane l supplies row (A) or column (B) l%16 of the 16x16 fragment.  Output
-// item v of lane l is column l%16 and row 4*(l/16)+v for the FP32 and BF16
-// instructions but row 4*v+l/16 for the FP64 one (measured on gfx950).  The
-// contracted index is split across lanes the same way for both operands, so
-// any assignment of k to (lane, slot) gives the same sum.
+// Operands.  B (V_l forward, V_l^T backward) is packed at plan time in
+// fragment order and streamed through a double-buffered LDS chunk shared by
+// the block's four waves; each wave loads its own rows of X straight into
+// registers (CH consecutive k per lane, 16-byte loads).  MFMA: FP64
+// v_mfma_f64_16x16x4, FP32 v_mfma_f32_16x16x4, BF16 v_mfma_f32_16x16x32_bf16
+// with FP32 accumulation.  Lane l supplies row (X) / column (B) l%16 and the k
+// values CH*(l/16) .. +CH-1 of each k-block; output item v of lane l is column
+// l%16 and row 4*(l/16)+v (FP32, BF16) or 4*v+l/16 (FP64, measured on gfx950).
 #include "kp_common.h"
 #include "kp_internal.h"
 
 namespace kp {
 
-template <int PREC> struct PT;
-template <> struct PT<PREC_F64> {
-  using tc = double; using acc = d4; using frag = double; using af = double;
-  static constexpr int VEC = 1;
-  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // one 16-byte unit
+
+template <int PREC> struct MT;
+template <> struct MT<PREC_F64> {
+  using tc = double; using acc = d4;
+  static constexpr int CH = 4, NV = 2;       // k per lane per k-block, 16-byte units
+  struct chunk { double v[4]; };
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], c, 0, 0, 0);
+    return c;
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
-template <> struct PT<PREC_F32> {
-  using tc = float; using acc = f4; using frag = float; using af = float;
-  static constexpr int VEC = 1;
-  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+template <> struct MT<PREC_F32> {
+  using tc = float; using acc = f4;
+  static constexpr int CH = 4, NV = 1;
+  struct chunk { float v[4]; };
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], c, 0, 0, 0);
+    return c;
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
-template <> struct PT<PREC_BF16> {
-  using tc = __bf16; using acc = f4; using frag = bf8; using af = float;
-  static constexpr int VEC = 8;
-  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+template <> struct MT<PREC_BF16> {
+  using tc = __bf16; using acc = f4;
+  static constexpr int CH = 8, NV = 1;
+  struct chunk { bf8 v; };
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-template <class T, class S> __device__ __forceinline__ T cvt(S x);
-template <> __device__ __forceinline__ double cvt<double, double>(double x) { return x; }
-template <> __device__ __forceinline__ float cvt<float, double>(double x) { return (float)x; }
-template <> __device__ __forceinline__ __bf16 cvt<__bf16, double>(double x) { return (__bf16)(float)x; }
-template <> __device__ __forceinline__ float cvt<float, float>(float x) { return x; }
-template <> __device__ __forceinline__ __bf16 cvt<__bf16, float>(float x) { return (__bf16)x; }
-template <> __device__ __forceinline__ __bf16 cvt<__bf16, __bf16>(__bf16 x) { return x; }
-template <> __device__ __forceinline__ double cvt<double, float>(float x) { return (double)x; }
-template <> __device__ __forceinline__ float cvt<float, __bf16>(__bf16 x) { return (float)x; }
+// Block = WR x WC waves (WR = 4 row groups, WC column groups); each wave owns
+// WM row fragments x WN column fragments of 16 x 16.
+constexpr int WR = 4;
 
-// Tile: 64 x 64 outputs per 256-thread block, 2 x 2 waves of 32 x 32, each a
-// 2 x 2 grid of 16 x 16 MFMA fragments; the contracted axis advances by BK.
-constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
-constexpr int PAD = 4;
-
-// Hadamard pseudoinverse entry of eq. (4.6)/(4.7): 1/sum, or 0 when the
-// eigenvalue sum has modulus below 1e-13.
+// Hadamard pseudoinverse entry of eqs. (4.6)-(4.7): 1/sum, or 0 below 1e-13.
 __device__ __forceinline__ double ghat(double s) { return fabs(s) < 1e-13 ? 0.0 : 1.0 / s; }
 
-// ---------------------------------------------------------------------------
-// Left product: Y[b][m][n] = sum_k A[m][k] X[b][k][n], m, k in [0, K).
-//   A  : K x K operator (row pitch lda), zero-padded to a multiple of BK
-//   X  : input, element (b, k, n) at b*bstride + k*ldk + n   (type Ti)
-//   Y  : output, same indexing                               (type To)
-//   nbatch_rhs: number of b-slices per right-hand side (for the done flag)
-//   in_scale / out_scale: multiply input / output by the per-RHS power-of-two
-//   scale or its inverse (low-precision range guard).
-// For VEC = 1 the kernel reads At (= A^T, row-major) so that its LDS tile is
-// [k][m]; for VEC = 8 it reads A itself and keeps [m][k].
-// ---------------------------------------------------------------------------
-template <int PREC, class Ti, class To>
-__global__ __launch_bounds__(NT) void mode_left_kernel(
-    const typename PT<PREC>::tc* __restrict__ Aop, int lda, const Ti* __restrict__ X,
-    To* __restrict__ Y, int K, int ninner, int64_t ldk, int64_t bstride, int nbatch_rhs,
-    const RhsState* __restrict__ st, int in_scale, int out_scale) {
-  using P = PT<PREC>;
-  using tc = typename P::tc;
-  constexpr int VEC = P::VEC;
-  const int b = blockIdx.z;
-  const int rhs = b / nbatch_rhs;
-  if (st && st[rhs].done) return;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const double sin_ = (st && in_scale) ? st[rhs].scale : 1.0;
-  const Ti* Xb = X + (int64_t)b * bstride;
+template <int PREC>
+__device__ __forceinline__ typename MT<PREC>::tc to_tc(double x) {
+  if constexpr (PREC == PREC_BF16) return (__bf16)(float)x;
+  else return (typename MT<PREC>::tc)x;
+}
 
-  // VEC==1: As[k][m], Xs[k][n];  VEC==8: As[m][k], Xs[n][k]
-  __shared__ __attribute__((aligned(16))) tc As[VEC == 1 ? BK * (BM + PAD) : BM * (BK + 8)];
-  __shared__ __attribute__((aligned(16))) tc Xs[VEC == 1 ? BK * (BN + PAD) : BN * (BK + 8)];
-
-  typename P::acc acc[2][2];
+// ---- one lane's CH consecutive k values of one row --------------------------
+template <int PREC, class Ti>
+__device__ __forceinline__ typename MT<PREC>::chunk load_x(const Ti* __restrict__ row, int k0,
+                                                          int K, bool vec_ok, double scale,
+                                                          bool scaled) {
+  using M = MT<PREC>;
+  using tc = typename M::tc;
+  constexpr int CH = M::CH;
+  typename M::chunk c;
+  tc t[CH];
+  if (vec_ok && k0 < K) {
+    if constexpr (sizeof(Ti) == 8) {            // FP64 source, convert
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int q = 0; q < CH / 2; ++q) {
+        const d2 x = *reinterpret_cast<const d2*>(row + k0 + 2 * q);
+        t[2 * q] = to_tc<PREC>(scaled ? x[0] * scale : x[0]);
+        t[2 * q + 1] = to_tc<PREC>(scaled ? x[1] * scale : x[1]);
+      }
+    } else if constexpr (PREC == PREC_BF16) {   // bf16 source
+      c.v = *reinterpret_cast<const bf8*>(row + k0);
+      return c;
+    } else {                                    // fp32 source
+      const f4 x = *reinterpret_cast<const f4*>(row + k0);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int s = 0; s < CH; ++s) t[s] = x[s];
+    }
+  } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
-
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    // operator tile (padded, always in bounds)
-#pragma unroll
-    for (int q = 0; q < (BM * BK) / NT; ++q) {
-      const int e = tid + q * NT;
-      if constexpr (VEC == 1) {
-        const int kr = e / BM, mc = e % BM;
-        As[kr * (BM + PAD) + mc] = Aop[(int64_t)(k0 + kr) * lda + (m0 + mc)];
+    for (int s = 0; s < CH; ++s) {
+      if (!vec_ok && k0 + s < K) {
+        double x = to_double(row[k0 + s]);
+        t[s] = to_tc<PREC>(scaled ? x * scale : x);
       } else {
-        const int mr = e / BK, kc = e % BK;
-        As[mr * (BK + 8) + kc] = Aop[(int64_t)(m0 + mr) * lda + (k0 + kc)];
+        t[s] = (tc)0.0f;
       }
-    }
-    // data tile with bounds checks (zero fill)
-#pragma unroll
-    for (int q = 0; q < (BK * BN) / NT; ++q) {
-      const int e = tid + q * NT;
-      const int kr = e / BN, nc = e % BN;
-      const int k = k0 + kr, n = n0 + nc;
-      tc v = (tc)0.0f;
-      if (k < K && n < ninner) {
-        if (in_scale) v = cvt<tc>(to_double(Xb[(int64_t)k * ldk + n]) * sin_);
-        else v = cvt<tc>(Xb[(int64_t)k * ldk + n]);
-      }
-      if constexpr (VEC == 1) Xs[kr * (BN + PAD) + nc] = v;
-      else Xs[nc * (BK + 8) + kr] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4 * VEC) {
-      typename P::frag af[2], bfr[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int mrow = wm * 32 + i * 16 + (lane & 15);
-        const int ncol = wn * 32 + i * 16 + (lane & 15);
-        if constexpr (VEC == 1) {
-          af[i] = As[(kk + (lane >> 4)) * (BM + PAD) + mrow];
-          bfr[i] = Xs[(kk + (lane >> 4)) * (BN + PAD) + ncol];
-        } else {
-          af[i] = *reinterpret_cast<const bf8*>(&As[mrow * (BK + 8) + kk + (lane >> 4) * 8]);
-          bfr[i] = *reinterpret_cast<const bf8*>(&Xs[ncol * (BK + 8) + kk + (lane >> 4) * 8]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = P::mma(af[i], bfr[j], acc[i][j]);
     }
   }
+#pragma unroll
+  for (int s = 0; s < CH; ++s) c.v[s] = t[s];
+  return c;
+}
 
-  const double sout = (st && out_scale) ? st[rhs].inv_scale : 1.0;
-  To* Yb = Y + (int64_t)b * bstride;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 32 + i * 16 + P::row(lane, v);
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m < K && n < ninner) {
-          if (out_scale) Yb[(int64_t)m * ldk + n] = cvt<To>((double)acc[i][j][v] * sout);
-          else Yb[(int64_t)m * ldk + n] = cvt<To>(acc[i][j][v]);
-        }
-      }
+template <int PREC>
+__device__ __forceinline__ typename MT<PREC>::chunk load_b(const u4* __restrict__ l, int g,
+                                                          int c, int CB) {
+  using M = MT<PREC>;
+  typename M::chunk b;
+  if constexpr (M::NV == 1) {
+    const u4 u = l[g * CB + c];
+    __builtin_memcpy(&b, &u, 16);
+  } else {
+    const u4 u0 = l[(g * 2 + 0) * CB + c];
+    const u4 u1 = l[(g * 2 + 1) * CB + c];
+    __builtin_memcpy(&b.v[0], &u0, 16);
+    __builtin_memcpy(&b.v[2], &u1, 16);
+  }
+  return b;
 }
 
 // ---------------------------------------------------------------------------
-// Right product along x: Y[r][n] = sum_k X[r][k] B[k][n], r in [0, rows).
-//   X, Y: rows of length nx (contiguous), right-hand side b at b*N.
-//   VEC == 1 reads B (row-major, tile [k][n]); VEC == 8 reads Bt = B^T
-//   (tile [n][k]).  Both are zero-padded to multiples of the tile.
-//   With lam != nullptr the outputs are multiplied by ghat(lx[n] + ly[j] +
-//   lz[k]) where r = k*ny + j (the Hadamard step of Algs. 6-7).
+// One mode product for `batch` right-hand sides.
+//   Bpk   packed operator: 16-byte unit (kb, g, h, n) at ((kb*4+g)*NV+h)*npk+n
+//   X     input  [rhs][rows][K]  (type Ti)
+//   Y     output [rhs][K][rows]  (type To): Y[n*rows + r] = sum_k X[r][k] B[k][n]
+//   G epilogue (lc != nullptr): times ghat(la[r % a1] + lb[r / a1] + lc[n])
+//   in_scale / out_scale: per-RHS power-of-two scale on the input / its
+//   inverse on the output (low-precision range guard)
+// Grid: x = row blocks * column chunks, y = right-hand side.
 // ---------------------------------------------------------------------------
-template <int PREC, class Ti, class To>
-__global__ __launch_bounds__(NT) void mode_right_kernel(
-    const typename PT<PREC>::tc* __restrict__ Bop, int ldb, const Ti* __restrict__ X,
-    To* __restrict__ Y, int nx, int rows, int64_t N, const RhsState* __restrict__ st,
-    const double* __restrict__ lx, const double* __restrict__ ly, const double* __restrict__ lz,
-    int ny) {
-  using P = PT<PREC>;
-  using tc = typename P::tc;
-  constexpr int VEC = P::VEC;
-  const int rhs = blockIdx.z;
+template <int PREC, class Ti, class To, int WN, int WM, int WC>
+__global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
+    const u4* __restrict__ Bpk, int npk, int ncc, const Ti* __restrict__ X, To* __restrict__ Y,
+    int K, int rows, int64_t N, int vec_ok, const RhsState* __restrict__ st, int in_scale,
+    int out_scale, const double* __restrict__ la, const double* __restrict__ lb,
+    const double* __restrict__ lc, int a1) {
+  using M = MT<PREC>;
+  constexpr int NT = 64 * WR * WC;
+  constexpr int CW = 16 * WN;                 // columns per wave
+  constexpr int CB = WC * CW;                 // columns per block
+  constexpr int BR = WR * 16 * WM;            // rows per block
+  constexpr int CH = M::CH, NV = M::NV, KB = 4 * CH;
+  constexpr int UNITS = 4 * NV * CB;          // 16-byte units per operator k-block
+  // k-blocks per LDS stage (one barrier per stage): more for the faster
+  // MFMAs, at most 32 KiB per stage (two stages resident)
+  constexpr int KSP = PREC == PREC_BF16 ? 4 : (PREC == PREC_F32 ? 2 : 1);
+  constexpr int KSL = 32768 / (16 * UNITS) > 0 ? 32768 / (16 * UNITS) : 1;
+  constexpr int KS = KSP < KSL ? KSP : KSL;
+  constexpr int SUNITS = KS * UNITS;          // units per stage
+  constexpr int UPT = (SUNITS + NT - 1) / NT; // units per thread per stage
+
+  const int rhs = blockIdx.y;
   if (st && st[rhs].done) return;
-  const int r0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int cc = blockIdx.x % ncc, rb = blockIdx.x / ncc;
+  const int c0 = cc * CB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wr = wave % WR, wc = wave / WR;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int rw = rb * BR + wr * WM * 16;      // this wave's first row
+  const int cw = wc * CW;                     // this wave's first column in the block
   const Ti* Xb = X + (int64_t)rhs * N;
+  const bool scaled = (st != nullptr) && in_scale;
+  const double scale = scaled ? st[rhs].scale : 1.0;
+  const int nkb = (K + KB - 1) / KB;
 
-  __shared__ __attribute__((aligned(16))) tc Xs[BM * (BK + (VEC == 1 ? 1 : 8))];   // [r][k]
-  __shared__ __attribute__((aligned(16))) tc Bs[VEC == 1 ? BK * (BN + PAD) : BN * (BK + 8)];
-  constexpr int XP = BK + (VEC == 1 ? 1 : 8);
+  __shared__ u4 lds[2][SUNITS];
 
-  typename P::acc acc[2][2];
+  const Ti* xrow[WM];
+  bool rok[WM];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i) {
+    const int r = rw + 16 * i + l16;
+    rok[i] = r < rows;
+    xrow[i] = Xb + (int64_t)(rok[i] ? r : 0) * K;
+  }
+
+  typename M::acc acc[WM][WN];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
-  for (int k0 = 0; k0 < nx; k0 += BK) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < (BM * BK) / NT; ++q) {
-      const int e = tid + q * NT;
-      const int rr = e / BK, kc = e % BK;
-      const int r = r0 + rr, k = k0 + kc;
-      tc v = (tc)0.0f;
-      if (r < rows && k < nx) v = cvt<tc>(Xb[(int64_t)r * nx + k]);
-      Xs[rr * XP + kc] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < (BK * BN) / NT; ++q) {
-      const int e = tid + q * NT;
-      if constexpr (VEC == 1) {
-        const int kr = e / BN, nc = e % BN;
-        Bs[kr * (BN + PAD) + nc] = Bop[(int64_t)(k0 + kr) * ldb + (n0 + nc)];
-      } else {
-        const int nr = e / BK, kc = e % BK;
-        Bs[nr * (BK + 8) + kc] = Bop[(int64_t)(n0 + nr) * ldb + (k0 + kc)];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4 * VEC) {
-      typename P::frag af[2], bfr[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int rrow = wm * 32 + i * 16 + (lane & 15);
-        const int ncol = wn * 32 + i * 16 + (lane & 15);
-        if constexpr (VEC == 1) {
-          af[i] = Xs[rrow * XP + kk + (lane >> 4)];
-          bfr[i] = Bs[(kk + (lane >> 4)) * (BN + PAD) + ncol];
-        } else {
-          af[i] = *reinterpret_cast<const bf8*>(&Xs[rrow * XP + kk + (lane >> 4) * 8]);
-          bfr[i] = *reinterpret_cast<const bf8*>(&Bs[ncol * (BK + 8) + kk + (lane >> 4) * 8]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = P::mma(af[i], bfr[j], acc[i][j]);
-    }
+  // Prefetch registers: the operator stage one stage ahead (through LDS), the
+  // data rows XD k-blocks ahead (register ring).  Plain unrolled loops, no
+  // closures over these arrays: a captured array gets an address and lands in
+  // scratch memory.
+  constexpr int XD = PREC == PREC_F64 ? 2 : 3;
+  u4 breg[UPT];
+  typename M::chunk xq[XD][WM];
+  constexpr bool FULL = (SUNITS % NT) == 0;
+  const u4* bsrc = Bpk + c0;
+  const int cmax = npk - c0;                  // packed columns left for this block
+  const int nst = (nkb + KS - 1) / KS;
+
+  // loads stage `sg` of the operator into breg (zeros past the end)
+#define KP_LOAD_STAGE(sg)                                                                  \
+  _Pragma("unroll") for (int q = 0; q < UPT; ++q) {                                       \
+    const int su = tid + q * NT;                                                           \
+    if (FULL || su < SUNITS) {                                                             \
+      const int kk = su / UNITS, u = su % UNITS, c = u % CB, gh = u / CB;                  \
+      const int kbg = (sg) * KS + kk;                                                      \
+      breg[q] = (c < cmax && kbg < nkb)                                                    \
+                    ? bsrc[((int64_t)kbg * 4 * NV + gh) * npk + c]                         \
+                    : (u4){0u, 0u, 0u, 0u};                                                \
+    }                                                                                      \
+  }
+#define KP_STORE_STAGE(bf)                                                                 \
+  _Pragma("unroll") for (int q = 0; q < UPT; ++q) {                                       \
+    const int su = tid + q * NT;                                                           \
+    if (FULL || su < SUNITS) lds[bf][su] = breg[q];                                        \
   }
 
-  To* Yb = Y + (int64_t)rhs * N;
+  KP_LOAD_STAGE(0)
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int d = 0; d < XD; ++d) {
+    const int k0 = d * KB + CH * g;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < WM; ++i)
+      xq[d][i] = load_x<PREC, Ti>(xrow[i], (rok[i] && d < nkb) ? k0 : K, K, vec_ok, scale, scaled);
+  }
+  KP_STORE_STAGE(0)
+  __syncthreads();
+
+  for (int sg = 0; sg < nst; ++sg) {
+    const int buf = sg & 1;
+    const bool more = sg + 1 < nst;
+    if (more) { KP_LOAD_STAGE(sg + 1) }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = r0 + wm * 32 + i * 16 + P::row(lane, v);
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (r < rows && n < nx) {
-          double val = (double)acc[i][j][v];
-          if (lx) {
-            const int jy = r % ny, kz = r / ny;
-            val *= ghat(lx[n] + ly[jy] + (lz ? lz[kz] : 0.0));
-          }
-          Yb[(int64_t)r * nx + n] = cvt<To>(val);
+    for (int kk = 0; kk < KS; ++kk) {
+      const int kb = sg * KS + kk;
+      if (KS == 1 || kb < nkb) {
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const typename M::chunk b =
+              load_b<PREC>(lds[buf] + kk * UNITS, g, cw + 16 * j + l16, CB);
+#pragma unroll
+          for (int i = 0; i < WM; ++i) acc[i][j] = M::mma(xq[0][i], b, acc[i][j]);
         }
       }
+      // advance the data ring and fetch k-block kb + XD
+#pragma unroll
+      for (int d = 0; d + 1 < XD; ++d)
+#pragma unroll
+        for (int i = 0; i < WM; ++i) xq[d][i] = xq[d + 1][i];
+      const int kn = kb + XD;
+      const int k0 = kn * KB + CH * g;
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+        xq[XD - 1][i] =
+            load_x<PREC, Ti>(xrow[i], (rok[i] && kn < nkb) ? k0 : K, K, vec_ok, scale, scaled);
+    }
+    if (more) { KP_STORE_STAGE(buf ^ 1) }
+    __syncthreads();
+  }
+#undef KP_LOAD_STAGE
+#undef KP_STORE_STAGE
+
+  // ---- epilogue: optional G factor and output scale, transposed store ------
+  const double oscale = (st && out_scale) ? st[rhs].inv_scale : 1.0;
+  To* Yb = Y + (int64_t)rhs * N;
+  double rowsum[WM][4];
+  if (lc) {
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rw + 16 * i + M::row(lane, v);
+        const int rc = r < rows ? r : 0;
+        rowsum[i][v] = la[rc % a1] + (lb ? lb[rc / a1] : 0.0);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int n = c0 + cw + 16 * j + l16;
+    if (n >= K) continue;
+    const double lcn = lc ? lc[n] : 0.0;
+    To* dst = Yb + (int64_t)n * rows;
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      To out[4];
+      int rr[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        rr[v] = rw + 16 * i + M::row(lane, v);
+        double val = (double)acc[i][j][v];
+        if (lc) {
+          const double sum = rowsum[i][v] + lcn;
+          if constexpr (PREC == PREC_F64) {
+            val *= ghat(sum);
+          } else {
+            // FP32 reciprocal: the low-precision preconditioner is accurate
+            // to its own rounding anyway
+            val = fabs(sum) < 1e-13 ? 0.0 : (double)((float)val * __frcp_rn((float)sum));
+          }
+        }
+        if (out_scale) val *= oscale;
+        if constexpr (sizeof(To) == 2) out[v] = (__bf16)(float)val;
+        else out[v] = (To)val;
+      }
+      bool done_store = false;
+      if constexpr (PREC != PREC_F64) {
+        // the four rows of this lane are consecutive
+        if ((rows & 3) == 0 && rr[3] < rows) {
+          if constexpr (sizeof(To) == 8) {
+            const d2 a = {out[0], out[1]}, b2 = {out[2], out[3]};
+            *reinterpret_cast<d2*>(dst + rr[0]) = a;
+            *reinterpret_cast<d2*>(dst + rr[0] + 2) = b2;
+          } else if constexpr (sizeof(To) == 4) {
+            const f4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<f4*>(dst + rr[0]) = a;
+          } else {
+            const bf4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<bf4*>(dst + rr[0]) = a;
+          }
+          done_store = true;
+        }
+      }
+      if (!done_store) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (rr[v] < rows) dst[rr[v]] = out[v];
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ host ----
-template <int PREC, class Ti, class To>
-static void launch_left(int cls, const void* A, int lda, const void* X, void* Y, int K,
-                        int ninner, int64_t ldk, int64_t bstride, int nb_total, int nbatch_rhs,
-                        const RhsState* st, int in_scale, int out_scale, hipStream_t s) {
-  dim3 grid((ninner + BN - 1) / BN, (K + BM - 1) / BM, nb_total);
-  trace_begin(cls, s);
-  hipLaunchKernelGGL((mode_left_kernel<PREC, Ti, To>), grid, dim3(NT), 0, s,
-                     (const typename PT<PREC>::tc*)A, lda, (const Ti*)X, (To*)Y, K, ninner, ldk,
-                     bstride, nbatch_rhs, st, in_scale, out_scale);
-  trace_end(cls, s);
+// Tile configurations (column fragments per wave, row fragments per wave,
+// column wave groups).  Block = 4 x wc waves, rows per block 64*wm, columns
+// per block 16*wn*wc.  The operator packing does not depend on the choice, so
+// any configuration may serve any product; the autotuner times them.
+struct MpCfg { int wn, wm, wc; };
+static const MpCfg kCfgs[] = {
+    {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {6, 2, 1}, {8, 2, 1}, {12, 1, 1}, {16, 1, 1},
+    {2, 4, 2}, {3, 4, 2}, {4, 2, 2}, {4, 4, 2}, {6, 2, 2}, {8, 1, 2}, {8, 2, 2}, {16, 1, 2},
+};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+int mp_num_configs() { return kNumCfgs; }
+
+// Whether configuration `id` is compiled for `prec` (FP64 omits the two tiles
+// 16 fragments wide, whose accumulators would spill).
+bool mp_config_allowed(int id, int prec) {
+  return id >= 0 && id < kNumCfgs && !(prec == PREC_F64 && (id == 7 || id == 15));
+}
+
+void mp_config(int id, int* wn, int* wm, int* wc) {
+  *wn = kCfgs[id].wn; *wm = kCfgs[id].wm; *wc = kCfgs[id].wc;
+}
+
+// Default configuration for a K x K operator: the two-column-group tile whose
+// block width covers K most tightly (eight waves per block), else the widest
+// single-group tile.
+int mp_default_config(int K, int prec) {
+  (void)prec;
+  const int frags = (K + 15) / 16;
+  int best = -1, best_cb = 1 << 30;
+  for (int id = 0; id < kNumCfgs; ++id) {
+    const MpCfg& c = kCfgs[id];
+    if (c.wc != 2 || c.wm == 4) continue;
+    const int cb = c.wn * c.wc;
+    if (cb >= frags && cb < best_cb) { best = id; best_cb = cb; }
+  }
+  if (best >= 0) return best;
+  return prec == PREC_F64 ? 13 : 15;   // widest: 256 (FP64) or 512 columns per block
+}
+
+static int chunk_k(int prec) { return prec == PREC_BF16 ? 32 : 16; }
+static int elem_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+
+static void packed_geometry(int K, int prec, int* npk, int* nkb) {
+  *npk = ((K + 15) / 16) * 16;
+  *nkb = (K + chunk_k(prec) - 1) / chunk_k(prec);
+}
+
+size_t mp_packed_bytes(int K, int prec) {
+  int npk, nkb;
+  packed_geometry(K, prec, &npk, &nkb);
+  return (size_t)nkb * chunk_k(prec) * npk * elem_size(prec);
+}
+
+// Packs B (K x K, row-major, FP64) into the fragment order read by mp_kernel,
+// converted to the compute type (round to nearest even).  Zero padding.
+void mp_pack(const double* B, int K, int prec, void* dst) {
+  int npk, nkb;
+  packed_geometry(K, prec, &npk, &nkb);
+  const int KBk = chunk_k(prec), es = elem_size(prec);
+  const int CH = prec == PREC_BF16 ? 8 : 4;
+  const int NV = (CH * es) / 16, per = 16 / es;
+  const size_t total = (size_t)nkb * KBk * npk;
+  for (size_t e = 0; e < total * es; ++e) ((unsigned char*)dst)[e] = 0;
+  for (int k = 0; k < K; ++k)
+    for (int n = 0; n < K; ++n) {
+      const int kb = k / KBk, rem = k % KBk, g = rem / CH, s = rem % CH;
+      const int h = (s * es) / 16, w = s % per;
+      const size_t idx = ((((size_t)kb * 4 + g) * NV + h) * npk + n) * per + w;
+      const double v = B[(size_t)k * K + n];
+      if (es == 8) {
+        ((double*)dst)[idx] = v;
+      } else if (es == 4) {
+        ((float*)dst)[idx] = (float)v;
+      } else {
+        const float f = (float)v;
+        uint32_t u;
+        __builtin_memcpy(&u, &f, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+        ((uint16_t*)dst)[idx] = (uint16_t)(u >> 16);
+      }
+    }
+}
+
+template <int PREC, class Ti, class To, int WN, int WM, int WC>
+static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int rows,
+                       int batch, int vec_ok, const RhsState* st, int in_scale, int out_scale,
+                       const double* la, const double* lb, const double* lc, int a1,
+                       hipStream_t s) {
+  const int K = op.n[ax];
+  const int cb = 16 * WN * WC, ncc = (K + cb - 1) / cb;
+  constexpr int BR = WR * 16 * WM;
+  const int nrb = (rows + BR - 1) / BR;
+  int npk, nkb;
+  packed_geometry(K, PREC, &npk, &nkb);
+  dim3 grid(nrb * ncc, batch);
+  hipLaunchKernelGGL((mp_kernel<PREC, Ti, To, WN, WM, WC>), grid, dim3(64 * WR * WC), 0, s,
+                     (const u4*)(fwd ? op.Bf[ax] : op.Bb[ax]), npk, ncc, (const Ti*)X, (To*)Y, K,
+                     rows, (int64_t)op.N, vec_ok, st, in_scale, out_scale, la, lb, lc, a1);
 }
 
 template <int PREC, class Ti, class To>
-static void launch_right(int cls, const void* B, int ldb, const void* X, void* Y, int nx,
-                         int rows, int64_t N, int batch, const RhsState* st, const double* lx,
-                         const double* ly, const double* lz, int ny, hipStream_t s) {
-  dim3 grid((nx + BN - 1) / BN, (rows + BM - 1) / BM, batch);
+static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, const void* X,
+                      void* Y, int batch, const RhsState* st, int in_scale, int out_scale,
+                      const double* la, const double* lb, const double* lc, int a1,
+                      hipStream_t s) {
+  const int K = op.n[ax];
+  const int rows = (int)(op.N / K);
+  const int CH = PREC == PREC_BF16 ? 8 : 4;
+  const int vec_ok = (K % CH == 0) ? 1 : 0;
   trace_begin(cls, s);
-  hipLaunchKernelGGL((mode_right_kernel<PREC, Ti, To>), grid, dim3(NT), 0, s,
-                     (const typename PT<PREC>::tc*)B, ldb, (const Ti*)X, (To*)Y, nx, rows, N, st,
-                     lx, ly, lz, ny);
+#define KP_CASE(ID, W, M_, C)                                                                 \
+  case ID:                                                                                    \
+    launch_cfg<PREC, Ti, To, W, M_, C>(op, ax, fwd, X, Y, rows, batch, vec_ok, st, in_scale,  \
+                                       out_scale, la, lb, lc, a1, s);                         \
+    break;
+#define KP_COMMON_CASES                                                                      \
+  KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(3, 4, 4, 1)             \
+  KP_CASE(4, 6, 2, 1) KP_CASE(5, 8, 2, 1) KP_CASE(6, 12, 1, 1)                               \
+  KP_CASE(8, 2, 4, 2) KP_CASE(9, 3, 4, 2) KP_CASE(10, 4, 2, 2) KP_CASE(11, 4, 4, 2)           \
+  KP_CASE(12, 6, 2, 2) KP_CASE(14, 8, 2, 2)
+  if constexpr (PREC == PREC_F64) {     // the 16-fragment-wide tiles spill in FP64
+    switch (cfg) {
+      KP_COMMON_CASES
+      default: KP_CASE(13, 8, 1, 2)
+    }
+  } else {
+    switch (cfg) {
+      KP_COMMON_CASES
+      KP_CASE(7, 16, 1, 1)
+      KP_CASE(15, 16, 1, 2)
+      default: KP_CASE(13, 8, 1, 2)
+    }
+  }
+#undef KP_COMMON_CASES
+#undef KP_CASE
   trace_end(cls, s);
 }
 
-int pad_to_tile(int n) { return ((n + 63) / 64) * 64; }
-
-// Applies Z = M(R) for `batch` right-hand sides.  R and Z are FP64 grids;
-// T0 and T1 are scratch grids in the preconditioner's storage type.
+// Z = M(R) for `batch` right-hand sides.  R and Z are FP64 grids in the
+// natural layout; T0 and T1 are scratch grids in the compute type.
 template <int PREC>
 static void pinv_apply_t(const PinvOps& op, const double* R, double* Z, void* T0, void* T1,
                          int batch, const RhsState* st, hipStream_t s) {
-  using tc = typename PT<PREC>::tc;
-  const int nx = op.n[0], ny = op.n[1], nz = op.n[2];
-  const int64_t N = (int64_t)nx * ny * nz;
-  const int64_t plane = (int64_t)nx * ny;
-  const bool three_d = op.dim == 3;
+  using tc = typename MT<PREC>::tc;
   const int scl = (PREC == PREC_F64) ? 0 : 1;
-  // A-side operand selection: VEC 1 reads A^T, VEC 8 reads A.
-  constexpr bool V1 = PT<PREC>::VEC == 1;
-  auto fwdA = [&](int ax) { return V1 ? op.Q[ax] : op.Qt[ax]; };   // A = V^T
-  auto bwdA = [&](int ax) { return V1 ? op.Qt[ax] : op.Q[ax]; };   // A = V
-  // x-mode B operand: VEC 1 reads B, VEC 8 reads B^T.
-  const void* Bf = V1 ? op.Q[0] : op.Qt[0];    // forward  B = V_x
-  const void* Bb = V1 ? op.Qt[0] : op.Q[0];    // backward B = V_x^T
-  const int ldp[3] = {op.np[0], op.np[1], op.np[2]};
-
-  if (three_d) {
-    // forward z: T0 = R x_3 V_z^T  (reads FP64, scales into the compute range)
-    launch_left<PREC, double, tc>(KC_MP_Z_FWD, fwdA(2), ldp[2], R, T0, nz, (int)plane, plane, N, batch, 1, st,
-                                  scl, 0, s);
-    // forward y: T1 = T0 x_2 V_y^T, one slice per z-plane
-    launch_left<PREC, tc, tc>(KC_MP_Y_FWD, fwdA(1), ldp[1], T0, T1, ny, nx, nx, plane, batch * nz, nz, st, 0, 0,
-                              s);
+  const int nx = op.n[0];
+  const int* c = op.cfg;
+  if (op.dim == 3) {
+    launch_mp<PREC, double, tc>(KC_MP_X_FWD, c[0], op, 0, true, R, T0, batch, st, scl, 0, nullptr,
+                                nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, tc>(KC_MP_Y_FWD, c[1], op, 1, true, T0, T1, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, tc>(KC_MP_Z_FWD, c[2], op, 2, true, T1, T0, batch, st, 0, 0, op.lam[0],
+                            op.lam[1], op.lam[2], nx, s);
+    launch_mp<PREC, tc, tc>(KC_MP_X_BWD, c[3], op, 0, false, T0, T1, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, tc>(KC_MP_Y_BWD, c[4], op, 1, false, T1, T0, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, double>(KC_MP_Z_BWD, c[5], op, 2, false, T0, Z, batch, st, 0, scl,
+                                nullptr, nullptr, nullptr, 1, s);
   } else {
-    launch_left<PREC, double, tc>(KC_MP_Y_FWD, fwdA(1), ldp[1], R, T1, ny, nx, nx, plane, batch, 1, st, scl, 0,
-                                  s);
+    launch_mp<PREC, double, tc>(KC_MP_X_FWD, c[0], op, 0, true, R, T0, batch, st, scl, 0, nullptr,
+                                nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, tc>(KC_MP_Y_FWD, c[1], op, 1, true, T0, T1, batch, st, 0, 0, op.lam[0],
+                            nullptr, op.lam[1], nx, s);
+    launch_mp<PREC, tc, tc>(KC_MP_X_BWD, c[2], op, 0, false, T1, T0, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, s);
+    launch_mp<PREC, tc, double>(KC_MP_Y_BWD, c[3], op, 1, false, T0, Z, batch, st, 0, scl,
+                                nullptr, nullptr, nullptr, 1, s);
   }
-  // forward x with the Hadamard factor: T0 = G .* (T1 x_1 V_x^T)
-  launch_right<PREC, tc, tc>(KC_MP_X_FWD, Bf, ldp[0], T1, T0, nx, ny * nz, N, batch, st, op.lam[0], op.lam[1],
-                             three_d ? op.lam[2] : nullptr, ny, s);
-  // backward x: T1 = T0 x_1 V_x
-  launch_right<PREC, tc, tc>(KC_MP_X_BWD, Bb, ldp[0], T0, T1, nx, ny * nz, N, batch, st, nullptr, nullptr,
-                             nullptr, ny, s);
-  if (three_d) {
-    launch_left<PREC, tc, tc>(KC_MP_Y_BWD, bwdA(1), ldp[1], T1, T0, ny, nx, nx, plane, batch * nz, nz, st, 0, 0,
-                              s);
-    launch_left<PREC, tc, double>(KC_MP_Z_BWD, bwdA(2), ldp[2], T0, Z, nz, (int)plane, plane, N, batch, 1, st, 0,
-                                  scl, s);
-  } else {
-    launch_left<PREC, tc, double>(KC_MP_Y_BWD, bwdA(1), ldp[1], T1, Z, ny, nx, nx, plane, batch, 1, st, 0, scl,
-                                  s);
+}
+
+// Launches product q of the preconditioner alone (autotuning): q < dim are the
+// forward products (the first reads FP64, the last carries G), q >= dim the
+// backward ones (the last writes FP64).
+template <int PREC>
+static void product_t(const PinvOps& op, int q, const void* in, void* out, int batch,
+                      hipStream_t s) {
+  using tc = typename MT<PREC>::tc;
+  const int dim = op.dim, ax = q % dim;
+  const bool fwd = q < dim;
+  const bool gq = q == dim - 1;
+  const double* la = gq ? op.lam[0] : nullptr;
+  const double* lb = (gq && dim == 3) ? op.lam[1] : nullptr;
+  const double* lc = gq ? op.lam[dim - 1] : nullptr;
+  const int cls = fwd ? (ax == 0 ? KC_MP_X_FWD : (ax == 1 ? KC_MP_Y_FWD : KC_MP_Z_FWD))
+                      : (ax == 0 ? KC_MP_X_BWD : (ax == 1 ? KC_MP_Y_BWD : KC_MP_Z_BWD));
+  if (q == 0)
+    launch_mp<PREC, double, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la,
+                                lb, lc, op.n[0], s);
+  else if (q == 2 * dim - 1)
+    launch_mp<PREC, tc, double>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la,
+                                lb, lc, op.n[0], s);
+  else
+    launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la, lb,
+                            lc, op.n[0], s);
+}
+
+void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch,
+                  hipStream_t s) {
+  switch (op.prec) {
+    case PREC_F64: product_t<PREC_F64>(op, q, in, out, batch, s); break;
+    case PREC_F32: product_t<PREC_F32>(op, q, in, out, batch, s); break;
+    default: product_t<PREC_BF16>(op, q, in, out, batch, s); break;
   }
 }
 

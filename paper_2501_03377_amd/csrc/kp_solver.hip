@@ -5,9 +5,9 @@
 // stream; the scalar recurrences stay on the device, and the host only reads
 // the per-RHS done flags between chunks of iterations.
 #include <hip/hip_runtime.h>
-#include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -26,9 +26,10 @@ namespace kp {
 // on the plan's stream; elapsed times are folded into per-class totals once
 // the stream has been synchronised.
 struct Tracer {
-  struct Rec { int cls; hipEvent_t a, b; };
+  struct Rec { int cls; hipEvent_t a, b; bool pooled; };
   std::vector<hipEvent_t> pool;
   std::vector<Rec> pending;
+  std::vector<Rec>* capture = nullptr;   // records of a graph being captured
   hipEvent_t cur = nullptr;
   double ms[KC_COUNT] = {};
   int64_t cnt[KC_COUNT] = {};
@@ -43,7 +44,8 @@ struct Tracer {
   void end(int cls, hipStream_t s) {
     hipEvent_t e = get();
     (void)hipEventRecord(e, s);
-    pending.push_back({cls, cur, e});
+    if (capture) capture->push_back({cls, cur, e, false});   // owned by the graph
+    else pending.push_back({cls, cur, e, true});
     cur = nullptr;
   }
   void collect() {
@@ -53,8 +55,10 @@ struct Tracer {
         ms[r.cls] += f;
         cnt[r.cls] += 1;
       }
-      pool.push_back(r.a);
-      pool.push_back(r.b);
+      if (r.pooled) {
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+      }
     }
     pending.clear();
   }
@@ -62,7 +66,8 @@ struct Tracer {
     for (int c = 0; c < KC_COUNT; ++c) { ms[c] = 0.0; cnt[c] = 0; }
   }
   ~Tracer() {
-    for (const Rec& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (const Rec& r : pending)
+      if (r.pooled) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
@@ -85,12 +90,37 @@ struct kp_plan {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  double* hist = nullptr;       // device residual history
+  double* hist = nullptr;       // residual history, pinned host memory mapped to the device
+  double* hist_dev = nullptr;   // its device address
   size_t hist_cap = 0;          // doubles
-  RhsState* st_host = nullptr;  // pinned copy of the state
+  RhsState* st_host = nullptr;  // pinned, mapped mirror of the state (written by the device)
+  RhsState* st_dev = nullptr;   // its device address
   int expect_iters = 0;         // iterations the last solve needed (first chunk size)
   bool profiling = false;
   Tracer tracer;
+  hipStream_t own = nullptr;    // private stream of kp_solve (graph capture needs one)
+  hipEvent_t ev_in = nullptr;   // orders kp_solve after earlier work on `stream`
+  // Captured chunks of iterations, keyed by everything their kernels capture.
+  struct GraphKey {
+    int batch, n, flags, hs;
+    double tol;
+    const void* u;
+    const void* hist;
+    const void* eta;    // whole-solve graphs only (nullptr for iteration chunks)
+    bool operator==(const GraphKey& o) const {
+      return batch == o.batch && n == o.n && flags == o.flags && hs == o.hs && tol == o.tol &&
+             u == o.u && hist == o.hist && eta == o.eta;
+    }
+  };
+  struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    std::vector<Tracer::Rec> trace;   // event pairs recorded by every replay
+  };
+  std::vector<GraphEntry> graphs;     // most recently used last
+  bool graphs_ok = true;              // cleared if capture is unavailable
+  const void* last_eta = nullptr;     // buffers of the previous solve: when a solve
+  const void* last_u = nullptr;       // repeats them, the whole solve is one graph
 };
 
 namespace {
@@ -125,7 +155,8 @@ Layout layout_for(const kp_plan* p, int batch) {
   L.Z = take(N * 8);
   L.T0 = take(N * elem_bytes(p->prec));
   L.T1 = take(N * elem_bytes(p->prec));
-  L.part = take((size_t)batch * NSLOTS * G * 8);
+  (void)G;
+  L.part = take((size_t)batch * NSLOTS * 8192 * 8);   // GMAX partials per slot
   L.st = take((size_t)batch * sizeof(RhsState));
   L.total = off;
   return L;
@@ -144,12 +175,17 @@ int ensure_workspace(kp_plan* p) {
   return KP_OK;
 }
 
+// Residual history in pinned host memory that the device writes directly, so
+// reading it needs no copy kernel.
 int ensure_hist(kp_plan* p, size_t doubles) {
   if (p->hist_cap >= doubles) return KP_OK;
-  if (p->hist) (void)hipFree(p->hist);
+  if (p->hist) (void)hipHostFree(p->hist);
   p->hist = nullptr;
+  p->hist_dev = nullptr;
   p->hist_cap = 0;
-  if (!ok(hipMalloc((void**)&p->hist, doubles * sizeof(double)))) return KP_ENOMEM;
+  if (!ok(hipHostMalloc((void**)&p->hist, doubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
+    return KP_ENOMEM;
+  if (!ok(hipHostGetDevicePointer((void**)&p->hist_dev, p->hist, 0))) return KP_EHIP;
   p->hist_cap = doubles;
   return KP_OK;
 }
@@ -163,15 +199,18 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
-                  const RhsState* st) {
+                  const RhsState* st, hipStream_t s) {
   char* base = (char*)p->ws;
   if (flags & KP_FLAG_NO_PRECOND) {
-    trace_begin(KC_COPY, p->stream);
-    (void)hipMemcpyAsync(Z, R, (size_t)p->g.N * batch * 8, hipMemcpyDeviceToDevice, p->stream);
-    trace_end(KC_COPY, p->stream);
+    launch_copy(p->g, R, Z, st, batch, vec_blocks(p->g.N, batch), s);
   } else {
-    pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, p->stream);
+    pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, s);
   }
+}
+
+void clear_graphs(kp_plan* p) {
+  for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
+  p->graphs.clear();
 }
 
 }  // namespace
@@ -194,8 +233,7 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     if (bc[a] < 0 || bc[a] > 4) return KP_EINVAL;
   const int64_t N = (int64_t)nx * ny * nz;
   if (N >= ((int64_t)1 << 31)) return KP_EINVAL;
-  if ((int64_t)max_batch * nz > 65535) return KP_EINVAL;
-  if (((int64_t)ny * nz + 63) / 64 > 65535) return KP_EINVAL;
+  if (max_batch > 65535) return KP_EINVAL;
 
   kp_plan* p = new (std::nothrow) kp_plan();
   if (!p) return KP_ENOMEM;
@@ -204,44 +242,32 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   bool singular = true;
   for (int a = 0; a < dim; ++a) singular = singular && (bc[a] == KP_BC_P || bc[a] == KP_BC_N);
   p->g.singular = singular ? 1 : 0;
+  if (!zgrid_fits(p->g)) { delete p; return KP_EINVAL; }
   p->prec = prec;
   p->max_batch = max_batch;
   p->stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&p->device);
 
-  // Host bases, padded with zeros to the tile multiple.
+  // Host bases (closed form), packed per axis for the forward (B = V) and the
+  // backward (B = V^T) mode products.
   const int n[3] = {nx, ny, nz};
-  const size_t eb = elem_bytes(prec);
   size_t bytes = 0;
-  std::vector<size_t> offQ(3), offQt(3), offL(3);
+  size_t offF[3] = {0, 0, 0}, offB[3] = {0, 0, 0}, offL[3] = {0, 0, 0};
   for (int a = 0; a < dim; ++a) {
-    const int np = pad_to_tile(n[a]);
-    p->op.np[a] = np;
-    offQ[a] = bytes; bytes += align_up((size_t)np * np * eb);
-    offQt[a] = bytes; bytes += align_up((size_t)np * np * eb);
+    const size_t pb = mp_packed_bytes(n[a], prec);
+    offF[a] = bytes; bytes += align_up(pb);
+    offB[a] = bytes; bytes += align_up(pb);
     offL[a] = bytes; bytes += align_up((size_t)n[a] * 8);
   }
   std::vector<char> host(bytes, 0);
   for (int a = 0; a < dim; ++a) {
-    const int na = n[a], np = p->op.np[a];
-    std::vector<double> Q((size_t)na * na), lam(na);
+    const int na = n[a];
+    std::vector<double> Q((size_t)na * na), Qt((size_t)na * na), lam(na);
     if (basis_1d(na, p->g.bc[a], Q.data(), lam.data()) != 0) { delete p; return KP_EINVAL; }
     for (int r = 0; r < na; ++r)
-      for (int c = 0; c < na; ++c) {
-        const double q = Q[(size_t)r * na + c];
-        const size_t iq = (size_t)r * np + c, it = (size_t)c * np + r;
-        if (prec == PREC_F64) {
-          ((double*)(host.data() + offQ[a]))[iq] = q;
-          ((double*)(host.data() + offQt[a]))[it] = q;
-        } else if (prec == PREC_F32) {
-          ((float*)(host.data() + offQ[a]))[iq] = (float)q;
-          ((float*)(host.data() + offQt[a]))[it] = (float)q;
-        } else {
-          const __hip_bfloat16 b = __double2bfloat16(q);
-          ((__hip_bfloat16*)(host.data() + offQ[a]))[iq] = b;
-          ((__hip_bfloat16*)(host.data() + offQt[a]))[it] = b;
-        }
-      }
+      for (int c = 0; c < na; ++c) Qt[(size_t)c * na + r] = Q[(size_t)r * na + c];
+    mp_pack(Q.data(), na, prec, host.data() + offF[a]);
+    mp_pack(Qt.data(), na, prec, host.data() + offB[a]);
     std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
   }
   if (!ok(hipMalloc(&p->resident, bytes))) { delete p; return KP_ENOMEM; }
@@ -253,20 +279,34 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   }
   p->op.dim = dim;
   p->op.prec = prec;
+  p->op.N = N;
+  // product order: x, y, z forward, x, y, z backward (3D); x, y, x, y (2D)
+  for (int q = 0; q < 6; ++q) {
+    const int ax = dim == 3 ? q % 3 : q % 2;
+    p->op.cfg[q] = (q < 2 * dim) ? mp_default_config(n[ax], prec) : 0;
+  }
   for (int a = 0; a < 3; ++a) {
     p->op.n[a] = n[a];
     if (a < dim) {
-      p->op.Q[a] = (char*)p->resident + offQ[a];
-      p->op.Qt[a] = (char*)p->resident + offQt[a];
+      p->op.Bf[a] = (char*)p->resident + offF[a];
+      p->op.Bb[a] = (char*)p->resident + offB[a];
       p->op.lam[a] = (const double*)((char*)p->resident + offL[a]);
     } else {
-      p->op.np[a] = 1;
-      p->op.Q[a] = p->op.Qt[a] = nullptr;
+      p->op.Bf[a] = p->op.Bb[a] = nullptr;
       p->op.lam[a] = nullptr;
     }
   }
+  if (!ok(hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking)) ||
+      !ok(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming))) {
+    if (p->own) (void)hipStreamDestroy(p->own);
+    (void)hipFree(p->resident);
+    delete p;
+    return KP_EHIP;
+  }
   if (!ok(hipHostMalloc((void**)&p->st_host, (size_t)max_batch * sizeof(RhsState),
-                        hipHostMallocDefault))) {
+                        hipHostMallocMapped | hipHostMallocCoherent)) ||
+      !ok(hipHostGetDevicePointer((void**)&p->st_dev, p->st_host, 0))) {
+    if (p->st_host) (void)hipHostFree(p->st_host);
     (void)hipFree(p->resident);
     delete p;
     return KP_ENOMEM;
@@ -279,8 +319,12 @@ void kp_plan_destroy(kp_plan* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
+  if (p->own) (void)hipStreamSynchronize(p->own);
+  clear_graphs(p);
+  if (p->own) (void)hipStreamDestroy(p->own);
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ws_owned && p->ws) (void)hipFree(p->ws);
-  if (p->hist) (void)hipFree(p->hist);
+  if (p->hist) (void)hipHostFree(p->hist);
   if (p->resident) (void)hipFree(p->resident);
   if (p->st_host) (void)hipHostFree(p->st_host);
   delete p;
@@ -303,6 +347,7 @@ int kp_plan_set_workspace(kp_plan* p, void* dev, size_t bytes) {
   p->ws = dev;
   p->ws_bytes = bytes;
   p->ws_owned = false;
+  clear_graphs(p);    // captured kernels point into the old workspace
   return KP_OK;
 }
 
@@ -338,7 +383,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
              int flags, kp_result* results, double* res_hist) {
   if (!p || !eta || !u || batch < 1 || batch > p->max_batch) return KP_EINVAL;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 1000000) return KP_EINVAL;
-  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY)) return KP_EINVAL;
+  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH))
+    return KP_EINVAL;
   if (!aligned16(eta) || !aligned16(u)) return KP_EINVAL;
   const size_t vbytes = (size_t)p->g.N * batch * 8;
   if (overlap(eta, u, vbytes)) return KP_EINVAL;
@@ -361,52 +407,116 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   double* part = (double*)(base + L.part);
   RhsState* st = (RhsState*)(base + L.st);
   const int G = vec_blocks(p->g.N, batch);
-  hipStream_t s = p->stream;
+  // Work runs on the plan's private stream, ordered after earlier work on the
+  // caller's stream.
+  hipStream_t s = p->own;
+  if (!ok(hipEventRecord(p->ev_in, p->stream)) || !ok(hipStreamWaitEvent(s, p->ev_in, 0)))
+    return KP_EHIP;
 
   TraceScope scope(p);
-  if (!ok(hipMemsetAsync(p->hist, 0, (size_t)batch * hs * sizeof(double), s))) return KP_EHIP;
-  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
-  launch_init(p->g, eta, R, u, part, st, p->hist, hs, batch, G, s);
-  precondition(p, L, R, Z, batch, flags, st);
-  launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
+  std::memset(p->hist, 0, (size_t)batch * hs * sizeof(double));   // no kernel writes it now
 
-  // Iterations in chunks; kernels of finished right-hand sides return at once.
-  int done_iters = 0;
-  // First chunk: what the previous solve on this plan needed (or a guess per
-  // precision); afterwards one iteration per host check, so that a solve that
-  // behaves like the previous one launches no idle iterations.
-  int chunk = p->expect_iters > 0 ? p->expect_iters
-              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_F32 ? 2 : 8)));
-  bool all_done = false;
-  while (done_iters < max_iter) {
-    const int n = std::min(chunk, max_iter - done_iters);
+  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
+  auto head = [&]() {
+    launch_init(p->g, eta, R, u, part, st, p->hist_dev, hs, batch, G, s);
+    precondition(p, L, R, Z, batch, flags, st, s);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
+  };
+  auto iterations = [&](int n) {
     for (int q = 0; q < n; ++q) {
-      launch_iter_head(p->g, P, W, R, u, part, st, p->hist, hs, batch, G, tol, flags, s);
-      precondition(p, L, R, Z, batch, flags, st);
+      launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
+      precondition(p, L, R, Z, batch, flags, st, s);
       launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
     }
+  };
+  // exit step: true residual, centering of U, state to the mapped host mirror
+  auto tail = [&]() { launch_finish(p->g, eta, u, part, st, p->st_dev, batch, G, s); };
+
+  // Finds or captures the graph of `key`; returns its index or -1.
+  auto graph_for = [&](const kp_plan::GraphKey& key, auto&& body) -> int {
+    for (size_t e = 0; e < p->graphs.size(); ++e)
+      if (p->graphs[e].key == key) {
+        std::rotate(p->graphs.begin() + e, p->graphs.begin() + e + 1, p->graphs.end());
+        return (int)p->graphs.size() - 1;
+      }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool okc = ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    if (okc) {
+      body();
+      okc = ok(hipStreamEndCapture(s, &graph)) && graph != nullptr;
+    }
+    if (okc) okc = ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!okc) {
+      p->graphs_ok = false;   // capture unavailable: launch directly from now on
+      return -1;
+    }
+    if (p->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, exec, {}});
+    return (int)p->graphs.size() - 1;
+  };
+
+  // The first chunk of iterations is what the previous solve on this plan
+  // needed (or a guess per precision).  It runs as one captured HIP graph
+  // (cached per plan); when the caller repeats the previous solve's buffers
+  // the whole solve -- start, chunk and exit step -- is one graph.  Any
+  // further iterations run one at a time, each followed by the exit step and
+  // a stream synchronisation.  Kernels of finished right-hand sides return at
+  // once, so a solve that behaves like the previous one takes a single
+  // synchronisation and launches no idle iterations.
+  const bool use_graphs = p->graphs_ok && !p->profiling && !(flags & KP_FLAG_NO_GRAPH);
+  const bool repeat = eta == p->last_eta && u == p->last_u;
+  p->last_eta = eta;
+  p->last_u = u;
+  int done_iters = 0;
+  int chunk = p->expect_iters > 0 ? p->expect_iters
+              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_F32 ? 2 : 8)));
+  bool first = true;
+  while (true) {
+    const int n = std::min(chunk, max_iter - done_iters);
+    bool launched = false;
+    if (first && use_graphs) {
+      if (repeat) {
+        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, eta};
+        const int gi = graph_for(key, [&]() { head(); iterations(n); tail(); });
+        if (gi >= 0) {
+          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
+          launched = true;
+        }
+      } else {
+        head();
+        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, nullptr};
+        const int gi = graph_for(key, [&]() { iterations(n); });
+        if (gi >= 0) {
+          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
+        } else {
+          iterations(n);
+        }
+        tail();
+        launched = true;
+      }
+    }
+    if (!launched) {
+      if (first) head();
+      iterations(n);
+      tail();
+    }
+    first = false;
     done_iters += n;
     if (!ok(hipGetLastError())) return KP_EHIP;
-    if (!ok(hipMemcpyAsync(p->st_host, st, (size_t)batch * sizeof(RhsState),
-                           hipMemcpyDeviceToHost, s)))
-      return KP_EHIP;
     if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
-    all_done = true;
+    if (p->profiling) p->tracer.collect();
+    bool all_done = true;
     for (int b = 0; b < batch; ++b) all_done = all_done && p->st_host[b].done != RUNNING;
-    if (all_done) break;
+    if (all_done || done_iters >= max_iter) break;
     chunk = 1;
   }
-  launch_finish(p->g, eta, u, part, st, batch, G, s);
-  if (!ok(hipMemcpyAsync(p->st_host, st, (size_t)batch * sizeof(RhsState), hipMemcpyDeviceToHost,
-                         s)))
-    return KP_EHIP;
-  if (res_hist &&
-      !ok(hipMemcpyAsync(res_hist, p->hist, (size_t)batch * hs * sizeof(double),
-                         hipMemcpyDeviceToHost, s)))
-    return KP_EHIP;
-  if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
-  if (!ok(hipGetLastError())) return KP_EHIP;
-  if (p->profiling) p->tracer.collect();
+  if (res_hist) std::memcpy(res_hist, p->hist, (size_t)batch * hs * sizeof(double));
 
   int worst = KP_OK;
   int max_it = 0;
@@ -453,8 +563,84 @@ const char* kp_strerror(int s) {
 
 const char* kp_version(void) { return "kpcg 0.1 (gfx950)"; }
 
+int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
+  if (!p || batch < 1 || batch > p->max_batch || reps < 1 || reps > 1000) return KP_EINVAL;
+  (void)hipGetLastError();
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  if (p->own) (void)hipStreamSynchronize(p->own);
+  const Layout L = layout_for(p, batch);
+  char* base = (char*)p->ws;
+  hipStream_t s = p->stream;
+  const size_t vb = (size_t)p->g.N * batch * 8;
+  const size_t tb = (size_t)p->g.N * batch * (p->prec == PREC_F64 ? 8 : (p->prec == PREC_F32 ? 4 : 2));
+  // defined contents for timing (values do not change the work)
+  if (!ok(hipMemsetAsync(base + L.R, 0, vb, s)) || !ok(hipMemsetAsync(base + L.T0, 0, tb, s)) ||
+      !ok(hipMemsetAsync(base + L.T1, 0, tb, s)))
+    return KP_EHIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!ok(hipEventCreate(&e0)) || !ok(hipEventCreate(&e1))) return KP_EHIP;
+  Tracer* saved = g_tracer;
+  g_tracer = nullptr;
+  const int nprod = 2 * p->g.dim;
+  for (int q = 0; q < nprod; ++q) {
+    const int ax = q % p->g.dim;
+    const int K = p->op.n[ax];
+    const int kf = (K + 15) / 16;
+    const void* in = q == 0 ? (const void*)(base + L.R) : (const void*)(base + L.T0);
+    void* out = q == nprod - 1 ? (void*)(base + L.Z) : (void*)(base + L.T1);
+    float best = 1e30f;
+    int best_id = p->op.cfg[q];
+    for (int id = 0; id < mp_num_configs(); ++id) {
+      if (!mp_config_allowed(id, p->prec)) continue;
+      int wn, wm, wc;
+      mp_config(id, &wn, &wm, &wc);
+      const int cb = wn * wc;
+      if (cb > 2 * kf && cb > 4) continue;          // mostly zero columns
+      PinvOps trial = p->op;
+      trial.cfg[q] = id;
+      pinv_product(trial, q, in, out, batch, s);     // warm-up
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) pinv_product(trial, q, in, out, batch, s);
+      (void)hipEventRecord(e1, s);
+      if (!ok(hipEventSynchronize(e1))) { g_tracer = saved; return KP_EHIP; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_id = id; }
+    }
+    p->op.cfg[q] = best_id;
+    if (chosen) chosen[q] = best_id;
+  }
+  clear_graphs(p);    // captured kernels carry the old tile choices
+  g_tracer = saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
+  if (!p || !cfg || n < 2 * p->g.dim) return KP_EINVAL;
+  for (int q = 0; q < 2 * p->g.dim; ++q) cfg[q] = p->op.cfg[q];
+  return 2 * p->g.dim;
+}
+
+int kp_plan_set_tuning(kp_plan* p, const int* cfg, int n) {
+  if (!p || !cfg || n != 2 * p->g.dim) return KP_EINVAL;
+  for (int q = 0; q < n; ++q)
+    if (!mp_config_allowed(cfg[q], p->prec)) return KP_EINVAL;
+  for (int q = 0; q < n; ++q) p->op.cfg[q] = cfg[q];
+  clear_graphs(p);
+  return KP_OK;
+}
+
+int kp_plan_graph_count(const kp_plan* p) {
+  if (!p) return KP_EINVAL;
+  return p->graphs_ok ? (int)p->graphs.size() : -1;
+}
+
 int kp_plan_set_profiling(kp_plan* p, int enable) {
   if (!p) return KP_EINVAL;
+  if (p->profiling != (enable != 0)) clear_graphs(p);   // captured with or without events
   p->profiling = enable != 0;
   return KP_OK;
 }
@@ -479,7 +665,7 @@ int kp_plan_profile_reset(kp_plan* p) {
 const char* kp_kernel_class_name(int cls) {
   static const char* names[KC_COUNT] = {
       "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
-      "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd_scale", "modeprod_x_bwd",
+      "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
       "modeprod_y_bwd", "modeprod_z_bwd", "copy"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
 }

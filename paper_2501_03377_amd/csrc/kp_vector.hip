@@ -14,9 +14,10 @@
 namespace kp {
 
 constexpr int VT = 256;
+constexpr int GMAX = 8192;     // most block partials per slot
 
-__device__ __forceinline__ double* slot_ptr(double* part, int rhs, int slot, int G) {
-  return part + ((int64_t)rhs * NSLOTS + slot) * G;
+__device__ __forceinline__ double* slot_ptr(double* part, int rhs, int slot) {
+  return part + ((int64_t)rhs * NSLOTS + slot) * GMAX;
 }
 
 // One axis of the 3/5/7-point stencil: 2c - lo - hi with the ghost rule of the
@@ -35,38 +36,37 @@ __device__ __forceinline__ double axis_term(const double* __restrict__ p, uint32
   return (2.0 * c - lo) - hi;
 }
 
-__device__ __forceinline__ double minus_laplacian_at(const Geom& g, const double* __restrict__ p,
-                                                     uint32_t idx) {
-  const uint32_t nx = g.nx, ny = g.ny;
-  const uint32_t i = idx % nx, t = idx / nx;
-  const uint32_t j = t % ny, k = t / ny;
-  const double c = p[idx];
-  double v = axis_term(p, idx, i, g.nx, 1u, g.bc[0], c);
-  v += axis_term(p, idx, j, g.ny, nx, g.bc[1], c);
-  if (g.dim == 3) v += axis_term(p, idx, k, g.nz, nx * ny, g.bc[2], c);
-  return v;
-}
-
 template <int NV>
 __device__ __forceinline__ void write_partials(double (&v)[NV], const int (&slots)[NV],
-                                               double* part, int rhs, int G) {
+                                               double* part, int rhs, int bid) {
   __shared__ double lds[4 * NV];
   block_sum<NV>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) slot_ptr(part, rhs, slots[q], G)[blockIdx.x] = v[q];
+    for (int q = 0; q < NV; ++q) slot_ptr(part, rhs, slots[q])[bid] = v[q];
   }
 }
 
+// Reduces the G <= GMAX block partials of each slot in a fixed order: thread t
+// adds partials t, t + VT, t + 2 VT, ... in rounds of four loads issued
+// together, then the block reduction of block_sum.
 template <int NV>
 __device__ __forceinline__ void read_partials(const double* part, int rhs, const int (&slots)[NV],
                                               int G, double (&v)[NV]) {
   __shared__ double lds[4 * NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
+    const double* src = part + ((int64_t)rhs * NSLOTS + slots[q]) * GMAX;
     double t = 0.0;
-    const double* src = part + ((int64_t)rhs * NSLOTS + slots[q]) * G;
-    for (int b = threadIdx.x; b < G; b += VT) t += src[b];
+    for (int b0 = 0; b0 < G; b0 += 4 * VT) {
+      double x[4];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int b = b0 + threadIdx.x + w * VT;
+        x[w] = b < G ? src[b] : 0.0;
+      }
+      t += ((x[0] + x[1]) + x[2]) + x[3];
+    }
     v[q] = t;
   }
   block_sum<NV>(v, lds);
@@ -88,9 +88,10 @@ __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict
   const int rhs = blockIdx.y;
   const double* e = eta + (int64_t)rhs * g.N;
   double v[1] = {0.0};
+#pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) v[0] += e[i];
   const int sl[1] = {S_SUM};
-  write_partials<1>(v, sl, part, rhs, G);
+  write_partials<1>(v, sl, part, rhs, blockIdx.x);
 }
 
 __global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, RhsState* st, int G) {
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
   const int64_t off = (int64_t)rhs * g.N;
   const double m = st[rhs].mean;
   double v[2] = {0.0, 0.0};
+#pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
     const double r = eta[off + i] - m;      // eq. (3.6); m = 0 if nonsingular
     R[off + i] = r;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
     v[1] += r * r;
   }
   const int sl[2] = {S_SUM, S_SQ};
-  write_partials<2>(v, sl, part, rhs, G);
+  write_partials<2>(v, sl, part, rhs, blockIdx.x);
 }
 
 __global__ __launch_bounds__(VT) void k_fin_h(Geom g, const double* part, RhsState* st,
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(VT) void k_dot_rz(Geom g, const double* __restrict_
   if (st[rhs].done) return;
   const int64_t off = (int64_t)rhs * g.N;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
     const double z = Z[off + i];
     v[0] += R[off + i] * z;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(VT) void k_dot_rz(Geom g, const double* __restrict_
     if (W) v[3] += W[off + i] * z;
   }
   const int sl[4] = {S_DOT, S_SUM, S_SQ, S_AUX2};
-  write_partials<4>(v, sl, part, rhs, G);
+  write_partials<4>(v, sl, part, rhs, blockIdx.x);
 }
 
 __global__ __launch_bounds__(VT) void k_fin_rho(Geom g, const double* part, RhsState* st, int G,
@@ -217,35 +220,181 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
   const int64_t off = (int64_t)rhs * g.N;
   const double zm = st[rhs].zmean, b = st[rhs].beta;
   if (first) {
-    for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
+  #pragma unroll 4
+  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
       P[off + i] = Z[off + i] - zm;
   } else {
-    for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
+  #pragma unroll 4
+  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
       P[off + i] = (Z[off + i] - zm) + b * P[off + i];   // P_s = Z_s + beta_s P_{s-1}
   }
 }
 
-// ------------------------------------------------------- iteration head ----
-// W = -Delta(P), with <W, P> and sum W.
-__global__ __launch_bounds__(VT) void k_stencil_dot(Geom g, const double* __restrict__ P,
-                                                    double* __restrict__ W, double* part,
-                                                    const RhsState* st, int G) {
+// ------------------------------------------------------ tiled stencil ----
+// Kernels that apply the 7-point (5-point in 2D) minus Laplacian of eq. (3.2).
+// A 256-thread block owns a 64 x 16 tile of (x, y) cells of PB consecutive
+// z-planes; each thread computes 4 cells per plane (rows ty, ty+4, ty+8,
+// ty+12) and issues all their neighbour loads before any arithmetic.  Blocks
+// are mapped to work XCD-aware: the hardware deals blocks to the 8 XCDs round
+// robin, and block b is given work item (b % 8) * share + b / 8, so that each
+// XCD sweeps a contiguous range of planes and finds the y- and z-neighbours
+// of a plane in its own L2.  Boundary neighbours are loaded from a valid
+// address and replaced at compute time by the ghost rule of eq. (3.1)
+// (periodic neighbours are loaded wrapped).
+constexpr int STX = 64, STY = 16, SRY = 4;
+constexpr int NXCD = 8;
+
+enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP };
+
+struct ZGrid {
+  int ntx, ntiles;    // tiles along x, tiles per plane
+  int pb, ngroups;    // planes per block, plane groups
+  int nwork, share;   // work items (tiles x groups) and items per XCD
+  int nblocks;        // blocks per right-hand side
+};
+
+__device__ __forceinline__ double ghost_lo(int bc, double c) {
+  return (bc == BC_N || bc == BC_ND) ? c : 0.0;   // Neumann end: ghost = cell
+}
+__device__ __forceinline__ double ghost_hi(int bc, double c) {
+  return (bc == BC_N || bc == BC_DN) ? c : 0.0;
+}
+
+// ZM_PW:   partials <L P, P>, sum L P; W = L P stored when W != nullptr
+// ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2
+// ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U
+// ZM_LAP:  W = L P only
+template <int MODE>
+__global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __restrict__ P,
+                                           double* __restrict__ W, double* __restrict__ R,
+                                           double* __restrict__ U, const double* __restrict__ eta,
+                                           double* part, const RhsState* st) {
   const int rhs = blockIdx.y;
-  if (st && st[rhs].done) return;
+  if (MODE != ZM_TRUE && MODE != ZM_LAP && st[rhs].done) return;
+  const int b = blockIdx.x;
+  const int w = (b % NXCD) * zg.share + b / NXCD;   // XCD-aware work item
+  const bool wok = w < zg.nwork;
+  const int tile = wok ? w % zg.ntiles : 0, grp = wok ? w / zg.ntiles : 0;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int bcx = g.bc[0], bcy = g.bc[1], bcz = g.bc[2];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i = (tile % zg.ntx) * STX + tx;
+  const int y0 = (tile / zg.ntx) * STY + ty;
+  const bool col_ok = wok && i < nx;
+  const int ic = i < nx ? i : nx - 1;
+  const int il = i > 0 ? ic - 1 : (bcx == BC_P ? nx - 1 : ic);
+  const int ir = i < nx - 1 ? ic + 1 : (bcx == BC_P ? 0 : ic);
+  const bool three = g.dim == 3;
+  const uint32_t plane = (uint32_t)nx * ny;
   const int64_t off = (int64_t)rhs * g.N;
   const double* p = P + off;
-  double v[2] = {0.0, 0.0};
-  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
-    const double w = minus_laplacian_at(g, p, i);
-    W[off + i] = w;
-    v[0] += w * p[i];
-    v[1] += w;
+  const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
+  const double mean = (MODE == ZM_TRUE) ? st[rhs].mean : 0.0;
+  const int kb = grp * zg.pb, ke = min(kb + zg.pb, nz);
+
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = kb; k < ke; ++k) {
+    const int kl = k > 0 ? k - 1 : (bcz == BC_P ? nz - 1 : k);
+    const int kh = k < nz - 1 ? k + 1 : (bcz == BC_P ? 0 : k);
+    double c[SRY], lx[SRY], hx[SRY], ly[SRY], hy[SRY], lz[SRY], hz[SRY], ea[SRY], eb[SRY];
+    int jj[SRY];
+#pragma unroll
+    for (int r = 0; r < SRY; ++r) {              // all loads first
+      const int j = y0 + SRY * r;
+      jj[r] = j;
+      const int jc = j < ny ? j : ny - 1;
+      const int jl = jc > 0 ? jc - 1 : (bcy == BC_P ? ny - 1 : jc);
+      const int jh = jc < ny - 1 ? jc + 1 : (bcy == BC_P ? 0 : jc);
+      const uint32_t rb = (uint32_t)k * plane + (uint32_t)jc * nx;
+      c[r] = p[rb + ic];
+      lx[r] = p[rb + il];
+      hx[r] = p[rb + ir];
+      ly[r] = p[(uint32_t)k * plane + (uint32_t)jl * nx + ic];
+      hy[r] = p[(uint32_t)k * plane + (uint32_t)jh * nx + ic];
+      if (three) {
+        lz[r] = p[(uint32_t)kl * plane + (uint32_t)jc * nx + ic];
+        hz[r] = p[(uint32_t)kh * plane + (uint32_t)jc * nx + ic];
+      }
+      const bool ok = col_ok && j < ny;
+      const int64_t idx = off + rb + ic;
+      if (MODE == ZM_UR) {
+        ea[r] = ok ? R[idx] : 0.0;
+        eb[r] = ok ? U[idx] : 0.0;
+      } else if (MODE == ZM_TRUE) {
+        ea[r] = ok ? eta[idx] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < SRY; ++r) {
+      const int j = jj[r];
+      const double cc = c[r];
+      const double vx_l = i > 0 || bcx == BC_P ? lx[r] : ghost_lo(bcx, cc);
+      const double vx_h = i < nx - 1 || bcx == BC_P ? hx[r] : ghost_hi(bcx, cc);
+      const double vy_l = j > 0 || bcy == BC_P ? ly[r] : ghost_lo(bcy, cc);
+      const double vy_h = j < ny - 1 || bcy == BC_P ? hy[r] : ghost_hi(bcy, cc);
+      double wv = (2.0 * cc - vx_l) - vx_h;
+      wv += (2.0 * cc - vy_l) - vy_h;
+      if (three) {
+        const double vz_l = k > 0 || bcz == BC_P ? lz[r] : ghost_lo(bcz, cc);
+        const double vz_h = k < nz - 1 || bcz == BC_P ? hz[r] : ghost_hi(bcz, cc);
+        wv += (2.0 * cc - vz_l) - vz_h;
+      }
+      if (col_ok && j < ny) {
+        const int64_t idx = off + (uint32_t)k * plane + (uint32_t)j * nx + i;
+        if (MODE == ZM_PW) {
+          a0 += wv * cc;
+          a1 += wv;
+          if (W) W[idx] = wv;
+        } else if (MODE == ZM_UR) {
+          const double u = eb[r] + alpha * cc;    // U_s = U_{s-1} + alpha_s P_{s-1}
+          const double rr = ea[r] - alpha * wv;   // R_s = R_{s-1} - alpha_s W_s
+          U[idx] = u;
+          R[idx] = rr;
+          a0 += rr;
+          a1 += rr * rr;
+          a2 += u * u;
+        } else if (MODE == ZM_TRUE) {
+          const double rr = (ea[r] - mean) - wv;
+          a0 += rr * rr;
+          a1 += cc;
+        } else {
+          W[idx] = wv;
+        }
+      }
+    }
   }
-  if (part) {
+  if (MODE == ZM_LAP) return;
+  if (MODE == ZM_UR) {
+    double v[3] = {a0, a1, a2};
+    const int sl[3] = {S_SUM, S_SQ, S_AUX};
+    write_partials<3>(v, sl, part, rhs, b);
+  } else if (MODE == ZM_PW) {
+    double v[2] = {a0, a1};
     const int sl[2] = {S_DOT, S_SUM};
-    write_partials<2>(v, sl, part, rhs, G);
+    write_partials<2>(v, sl, part, rhs, b);
+  } else {
+    double v[2] = {a0, a1};
+    const int sl[2] = {S_SQ, S_SUM};
+    write_partials<2>(v, sl, part, rhs, b);
   }
 }
+
+ZGrid zgrid_for(const Geom& g) {
+  ZGrid z;
+  z.ntx = (g.nx + STX - 1) / STX;
+  z.ntiles = z.ntx * ((g.ny + STY - 1) / STY);
+  // planes per block: the fewest that keep the blocks within GMAX partials
+  z.pb = 1;
+  while ((int64_t)z.ntiles * ((g.nz + z.pb - 1) / z.pb) > GMAX && z.pb < g.nz) z.pb *= 2;
+  z.ngroups = (g.nz + z.pb - 1) / z.pb;
+  z.nwork = z.ntiles * z.ngroups;
+  z.share = (z.nwork + NXCD - 1) / NXCD;
+  z.nblocks = z.share * NXCD;
+  return z;
+}
+
+// The partial sums of one right-hand side fit in GMAX slots.
+bool zgrid_fits(const Geom& g) { return zgrid_for(g).nblocks <= GMAX; }
 
 __global__ __launch_bounds__(VT) void k_fin_alpha(Geom g, const double* part, RhsState* st, int G) {
   const int rhs = blockIdx.x;
@@ -260,28 +409,6 @@ __global__ __launch_bounds__(VT) void k_fin_alpha(Geom g, const double* part, Rh
   if (!isfinite(v[0])) { s.done = NONFINITE; return; }
   if (!(v[0] > 0.0)) { s.done = BREAKDOWN; return; }
   s.alpha = s.rho / v[0];                                  // alpha_s
-}
-
-__global__ __launch_bounds__(VT) void k_update_ur(Geom g, const double* __restrict__ P,
-                                                  const double* __restrict__ W,
-                                                  double* __restrict__ R, double* __restrict__ U,
-                                                  double* part, const RhsState* st, int G) {
-  const int rhs = blockIdx.y;
-  if (st[rhs].done) return;
-  const int64_t off = (int64_t)rhs * g.N;
-  const double a = st[rhs].alpha;
-  double v[3] = {0.0, 0.0, 0.0};
-  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
-    const double u = U[off + i] + a * P[off + i];        // U_s = U_{s-1} + alpha_s P_{s-1}
-    const double r = R[off + i] - a * W[off + i];        // R_s = R_{s-1} - alpha_s W_s
-    U[off + i] = u;
-    R[off + i] = r;
-    v[0] += r;
-    v[1] += r * r;
-    v[2] += u * u;
-  }
-  const int sl[3] = {S_SUM, S_SQ, S_AUX};
-  write_partials<3>(v, sl, part, rhs, G);
 }
 
 __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsState* st,
@@ -306,24 +433,8 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
 }
 
 // --------------------------------------------------------------- finish ----
-// True residual ||(eta - mean) - L U||^2 and sum U (no early exit).
-__global__ __launch_bounds__(VT) void k_true_res(Geom g, const double* __restrict__ eta,
-                                                 const double* __restrict__ U, double* part,
-                                                 const RhsState* st, int G) {
-  const int rhs = blockIdx.y;
-  const int64_t off = (int64_t)rhs * g.N;
-  const double m = st[rhs].mean;
-  double v[2] = {0.0, 0.0};
-  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
-    const double r = (eta[off + i] - m) - minus_laplacian_at(g, U + off, i);
-    v[0] += r * r;
-    v[1] += U[off + i];
-  }
-  const int sl[2] = {S_SQ, S_SUM};
-  write_partials<2>(v, sl, part, rhs, G);
-}
-
-__global__ __launch_bounds__(VT) void k_fin_true(Geom g, const double* part, RhsState* st, int G) {
+__global__ __launch_bounds__(VT) void k_fin_true(Geom g, const double* part, RhsState* st, int G,
+                                                 RhsState* mirror) {
   const int rhs = blockIdx.x;
   double v[2];
   const int sl[2] = {S_SQ, S_SUM};
@@ -332,6 +443,19 @@ __global__ __launch_bounds__(VT) void k_fin_true(Geom g, const double* part, Rhs
   RhsState& s = st[rhs];
   s.true_rel_res = s.h2 > 0.0 ? sqrt(v[0] / s.h2) : 0.0;
   s.umean = g.singular ? v[1] / (double)g.N : 0.0;
+  if (mirror) mirror[rhs] = s;   // host-mapped copy read after the stream sync
+}
+
+// Z = R for M = I (a kernel rather than a device copy, so that it can sit in
+// a captured graph).
+__global__ __launch_bounds__(VT) void k_copy(Geom g, const double* __restrict__ src,
+                                             double* __restrict__ dst, const RhsState* st, int G) {
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int64_t off = (int64_t)rhs * g.N;
+#pragma unroll 4
+  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
+    dst[off + i] = src[off + i];
 }
 
 __global__ __launch_bounds__(VT) void k_center_u(Geom g, double* __restrict__ U, const RhsState* st,
@@ -339,16 +463,18 @@ __global__ __launch_bounds__(VT) void k_center_u(Geom g, double* __restrict__ U,
   const int rhs = blockIdx.y;
   const int64_t off = (int64_t)rhs * g.N;
   const double m = st[rhs].umean;
+#pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) U[off + i] -= m;
 }
 
 // ------------------------------------------------------------------ host ----
 int vec_blocks(int64_t N, int batch) {
   // Depends on N only, so that a right-hand side reduces in the same order
-  // alone and inside any batch (batch invariance of every result).
+  // alone and inside any batch (batch invariance of every result).  At most
+  // 4 * VT partials, which the finalize kernels read in one round of loads.
   (void)batch;
-  int64_t g = (N + VT * 4 - 1) / (VT * 4);
-  if (g > 2048) g = 2048;
+  int64_t g = (N + VT * 16 - 1) / (VT * 16);
+  if (g > 4 * VT) g = 4 * VT;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -389,36 +515,56 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
                       int flags, hipStream_t s) {
-  dim3 grid(G, batch);
+  const ZGrid z = zgrid_for(g);
+  const int Gz = z.nblocks;
+  dim3 zgrid(z.nblocks, batch);
+  // W is only needed by the flexible beta (<W, Z>)
   trace_begin(KC_STENCIL, s);
-  hipLaunchKernelGGL(k_stencil_dot, grid, dim3(VT), 0, s, g, P, W, part, st, G);
+  hipLaunchKernelGGL(k_zm<ZM_PW>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
+                     (flags & F_FLEX_BETA) ? W : (double*)nullptr, (double*)nullptr,
+                     (double*)nullptr, (const double*)nullptr, part, (const RhsState*)st);
   trace_end(KC_STENCIL, s);
   trace_begin(KC_FINALIZE, s);
-  hipLaunchKernelGGL(k_fin_alpha, dim3(batch), dim3(VT), 0, s, g, part, st, G);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(batch), dim3(VT), 0, s, g, part, st, Gz);
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_UR, s);
-  hipLaunchKernelGGL(k_update_ur, grid, dim3(VT), 0, s, g, P, W, R, U, part, st, G);
+  hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
+                     R, U, (const double*)nullptr, part, (const RhsState*)st);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
-  hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, G,
+  hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,
                      tol, flags);
   trace_end(KC_FINALIZE, s);
+  (void)G;
 }
 
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
-                   int batch, int G, hipStream_t s) {
-  dim3 grid(G, batch);
+                   RhsState* mirror, int batch, int G, hipStream_t s) {
+  const ZGrid z = zgrid_for(g);
+  const int Gz = z.nblocks;
   trace_begin(KC_FINISH, s);
-  hipLaunchKernelGGL(k_true_res, grid, dim3(VT), 0, s, g, eta, U, part, st, G);
-  hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, G);
-  if (g.singular) hipLaunchKernelGGL(k_center_u, grid, dim3(VT), 0, s, g, U, st, G);
+  hipLaunchKernelGGL(k_zm<ZM_TRUE>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
+                     (const double*)U, (double*)nullptr, (double*)nullptr, (double*)nullptr, eta,
+                     part, (const RhsState*)st);
+  hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, Gz, mirror);
+  if (g.singular) hipLaunchKernelGGL(k_center_u, dim3(G, batch), dim3(VT), 0, s, g, U, st, G);
   trace_end(KC_FINISH, s);
 }
 
+void launch_copy(const Geom& g, const double* src, double* dst, const RhsState* st, int batch,
+                 int G, hipStream_t s) {
+  trace_begin(KC_COPY, s);
+  hipLaunchKernelGGL(k_copy, dim3(G, batch), dim3(VT), 0, s, g, src, dst, st, G);
+  trace_end(KC_COPY, s);
+}
+
 void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int G, hipStream_t s) {
+  const ZGrid z = zgrid_for(g);
+  (void)G;
   trace_begin(KC_STENCIL, s);
-  hipLaunchKernelGGL(k_stencil_dot, dim3(G, batch), dim3(VT), 0, s, g, P, W, (double*)nullptr,
-                     (const RhsState*)nullptr, G);
+  hipLaunchKernelGGL(k_zm<ZM_LAP>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, P, W,
+                     (double*)nullptr, (double*)nullptr, (const double*)nullptr, (double*)nullptr,
+                     (const RhsState*)nullptr);
   trace_end(KC_STENCIL, s);
 }
 

@@ -29,6 +29,7 @@ KP_EBREAKDOWN = -5
 KP_FLAG_NO_PRECOND = 1
 KP_FLAG_FLEX_BETA = 2
 KP_FLAG_RESIDUAL_ONLY = 4
+KP_FLAG_NO_GRAPH = 8
 
 # Every symbol declared in include/kpcg.h.
 EXPORTS = (
@@ -36,6 +37,7 @@ EXPORTS = (
     "kp_plan_resident_bytes", "kp_plan_set_workspace", "kp_plan_set_stream",
     "kp_apply_laplacian", "kp_apply_pinv", "kp_solve", "kp_strerror", "kp_version",
     "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
+    "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
 )
 KERNEL_CLASSES = 14
 
@@ -85,6 +87,10 @@ def _load():
         "kp_plan_profile": (i, [vp, i, pd, ctypes.POINTER(ctypes.c_int64)]),
         "kp_plan_profile_reset": (i, [vp]),
         "kp_kernel_class_name": (ctypes.c_char_p, [i]),
+        "kp_plan_autotune": (i, [vp, i, i, ctypes.POINTER(ctypes.c_int)]),
+        "kp_plan_get_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
+        "kp_plan_set_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
+        "kp_plan_graph_count": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +185,27 @@ def kp_kernel_class_name(cls):
     return _lib.kp_kernel_class_name(int(cls)).decode()
 
 
+def kp_plan_autotune(handle, batch, reps):
+    chosen = (ctypes.c_int * 6)()
+    rc = _lib.kp_plan_autotune(handle, int(batch), int(reps), chosen)
+    return rc, list(chosen)
+
+
+def kp_plan_get_tuning(handle):
+    cfg = (ctypes.c_int * 6)()
+    n = _lib.kp_plan_get_tuning(handle, cfg, 6)
+    return n, list(cfg)[: max(n, 0)]
+
+
+def kp_plan_set_tuning(handle, cfg):
+    arr = (ctypes.c_int * len(cfg))(*cfg)
+    return _lib.kp_plan_set_tuning(handle, arr, len(cfg))
+
+
+def kp_plan_graph_count(handle):
+    return _lib.kp_plan_graph_count(handle)
+
+
 # ------------------------------------------------------------ torch layer ----
 def _torch():
     import torch
@@ -235,6 +262,44 @@ class Plan:
         if t.numel() % self.N:
             raise ValueError(f"{name} size is not a multiple of the grid size")
         return t.numel() // self.N
+
+    def tuning_key(self, batch=1):
+        nx, ny, nz = self.dims
+        return f"{nx}x{ny}x{nz}:{self.prec}:b{batch}"
+
+    def autotune(self, batch=1, reps=5, cache=None):
+        """Times every tile shape for each mode product and keeps the fastest.
+        With `cache` (a path), reuses and records choices in a JSON file."""
+        import json
+        key = self.tuning_key(batch)
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table and kp_plan_set_tuning(self._h, table[key]) == KP_OK:
+                return table[key]
+        rc, chosen = kp_plan_autotune(self._h, batch, reps)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_autotune")
+        n, cfg = kp_plan_get_tuning(self._h)
+        if cache:
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    table = json.load(f)
+            table[key] = cfg
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+        return cfg
+
+    @property
+    def tuning(self):
+        return kp_plan_get_tuning(self._h)[1]
+
+    @tuning.setter
+    def tuning(self, cfg):
+        rc = kp_plan_set_tuning(self._h, list(cfg))
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_set_tuning")
 
     def set_profiling(self, enable=True):
         rc = kp_plan_set_profiling(self._h, enable)

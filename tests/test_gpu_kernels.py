@@ -104,3 +104,36 @@ def test_pinv_batch_matches_single():
     for b in range(3):
         z1 = to_host(plan.apply_pinv(to_dev(r[b])))
         assert np.array_equal(zb[b], z1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_tile_shapes_are_bitwise_identical(prec):
+    # every tile shape sums over k in the same order, so the result does not
+    # depend on the autotuner's choice
+    from paper_2501_03377_amd.kpcg import kp_plan_set_tuning
+    import torch
+    rng = np.random.default_rng(6)
+    shape = (20, 36, 70)
+    r = to_dev(rng.standard_normal((2,) + shape))
+    plan = _plan(shape, ("P", "D", "N"), prec=prec, max_batch=2)
+    ref = to_host(plan.apply_pinv(r))
+    n = 16
+    for cfg in range(n):
+        if prec == "f64" and cfg in (7, 15):
+            continue
+        assert kp_plan_set_tuning(plan._h, [cfg] * 6) == 0
+        z = to_host(plan.apply_pinv(r))
+        assert np.array_equal(z, ref), cfg
+
+
+def test_autotune_keeps_results():
+    rng = np.random.default_rng(8)
+    shape = (16, 48, 96)
+    r = rng.standard_normal(shape)
+    plan = _plan(shape, ("P", "P", "DN"), prec="f32")
+    before = to_host(plan.apply_pinv(to_dev(r)))
+    cfg = plan.autotune(batch=1, reps=2)
+    assert len(cfg) == 6
+    after = to_host(plan.apply_pinv(to_dev(r)))
+    assert np.array_equal(before, after)
+    assert rel(after, oracle_pinv(r, ("P", "P", "DN"))) <= PINV_TOL["f32"]

@@ -145,3 +145,39 @@ def test_unpreconditioned_cg():
     u, res, hist, rc = _solve(eta, ("D", "P", "N"), flags=1, max_iter=500, tol=1e-13)
     assert rc == 0 and res[0]["iterations"] > 10
     assert rel(u, oracle_solve(eta, ("D", "P", "N"))) <= 1e-9
+
+
+@pytest.mark.parametrize("prec,profile", [("f32", False), ("f64", True), ("bf16", False)])
+def test_graph_replays_match_eager(prec, profile):
+    # the captured iteration graph is replayed several times, with eager
+    # solves and synchronisations in between; every replay must equal the
+    # eager result bitwise
+    from paper_2501_03377_amd import KP_FLAG_FLEX_BETA, KP_FLAG_NO_GRAPH, Plan
+    from paper_2501_03377_amd.kpcg import kp_plan_graph_count
+    import torch
+    shape = (18, 30, 40)
+    eta = to_dev(synth.charge_field(shape, ncharges=200, seed=21))
+    fl = KP_FLAG_FLEX_BETA if prec == "bf16" else 0
+    plan = Plan(40, 30, 18, ("P", "N", "DN"), prec=prec)
+    plan.set_profiling(profile)
+    u_eager, res_e, _, rc = plan.solve(eta, tol=1e-10, flags=fl | KP_FLAG_NO_GRAPH)
+    ref = to_host(u_eager)
+    assert rc == 0
+    out = torch.empty_like(eta)
+    for rep in range(4):
+        # first call: chunk graph; second call repeats the buffers: whole-solve graph
+        for call in range(2):
+            out.fill_(float("nan"))
+            _, res_g, _, rc = plan.solve(eta, tol=1e-10, flags=fl, out=out)
+            torch.cuda.synchronize()
+            assert rc == 0 and np.array_equal(to_host(out), ref), (rep, call)
+            assert res_g[0]["iterations"] == res_e[0]["iterations"]
+        # eager work in between
+        plan.solve(eta, tol=1e-10, flags=fl | KP_FLAG_NO_GRAPH)
+    if profile:
+        # timing events need direct launches: no graph was captured
+        assert kp_plan_graph_count(plan._h) == 0
+        prof = plan.profile()
+        assert prof["stencil_dot"][1] > 0
+    else:
+        assert kp_plan_graph_count(plan._h) >= 1
