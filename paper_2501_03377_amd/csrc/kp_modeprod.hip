@@ -352,15 +352,17 @@ struct MpCfg { int wn, wm, wc; };
 static const MpCfg kCfgs[] = {
     {1, 4, 1}, {2, 4, 1}, {3, 4, 1}, {4, 4, 1}, {6, 2, 1}, {8, 2, 1}, {12, 1, 1}, {16, 1, 1},
     {2, 4, 2}, {3, 4, 2}, {4, 2, 2}, {4, 4, 2}, {6, 2, 2}, {8, 1, 2}, {8, 2, 2}, {16, 1, 2},
+    // tall tiles (FP32 and BF16 accumulators only): fewer re-reads of the operator
+    {16, 2, 1}, {8, 4, 2},
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 int mp_num_configs() { return kNumCfgs; }
 
-// Whether configuration `id` is compiled for `prec` (FP64 omits the two tiles
-// 16 fragments wide, whose accumulators would spill).
+// Whether configuration `id` is compiled for `prec` (FP64 omits the tiles
+// whose accumulators would spill: 16 fragments wide or 32 fragments per wave).
 bool mp_config_allowed(int id, int prec) {
-  return id >= 0 && id < kNumCfgs && !(prec == PREC_F64 && (id == 7 || id == 15));
+  return id >= 0 && id < kNumCfgs && !(prec == PREC_F64 && (id == 7 || id >= 15));
 }
 
 void mp_config(int id, int* wn, int* wm, int* wc) {
@@ -475,6 +477,8 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
       KP_COMMON_CASES
       KP_CASE(7, 16, 1, 1)
       KP_CASE(15, 16, 1, 2)
+      KP_CASE(16, 16, 2, 1)
+      KP_CASE(17, 8, 4, 2)
       default: KP_CASE(13, 8, 1, 2)
     }
   }

@@ -117,9 +117,9 @@ def test_tile_shapes_are_bitwise_identical(prec):
     r = to_dev(rng.standard_normal((2,) + shape))
     plan = _plan(shape, ("P", "D", "N"), prec=prec, max_batch=2)
     ref = to_host(plan.apply_pinv(r))
-    n = 16
+    n = 18
     for cfg in range(n):
-        if prec == "f64" and cfg in (7, 15):
+        if prec == "f64" and (cfg == 7 or cfg >= 15):
             continue
         assert kp_plan_set_tuning(plan._h, [cfg] * 6) == 0
         z = to_host(plan.apply_pinv(r))
