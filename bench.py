@@ -1,14 +1,23 @@
-"""Benchmark: 3D solves per second at relative residual 1e-10 on one MI355X.
+"""Benchmark: solves per second at relative residual 1e-10 on one MI355X.
 
-Workload (one step = one whole solve, plan cached): the 256 x 256 x 128 grid,
-periodic in x and y, Dirichlet-Neumann in z; eta = 10^4 unit point charges of
-random sign at uniformly drawn cells plus N(0, 1e-3) noise, minus its mean
-(seed 2); FP64 vectors, preconditioner mode products on FP32 matrix cores;
-tol 1e-10.  The same right-hand side is then solved with the FP64 and the
-BF16 preconditioner for the mixed-versus-FP64 comparison, and the CPU oracle
-is timed on a bounded sample on the host cores.
+Default workload (single256; one step = one whole solve, plan cached): the
+256 x 256 x 128 grid, periodic in x and y, Dirichlet-Neumann in z; eta = 10^4
+unit point charges of random sign at uniformly drawn cells plus N(0, 1e-3)
+noise, minus its mean (seed 2); FP64 vectors, preconditioner mode products on
+FP32 matrix cores; tol 1e-10.  The same right-hand side is then solved with
+the FP64 and the BF16 preconditioner for the mixed-versus-FP64 comparison, and
+the CPU oracle is timed on a bounded sample on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+Other workloads (--workload):
+  latency2d  2D 64 x 64, Dirichlet on every edge, 16 Gaussian blobs (seed 1), FP64
+             preconditioner, tol 1e-12 (latency-bound)
+  batch64    64 right-hand sides on 128^3, Neumann on every face (singular),
+             the same charge generator with seeds 3000 + b, BF16 preconditioner
+             with the flexible beta, tol 1e-10; one step = one batched solve of 64
+  large512   512^3, (P, P, D), 10^6 charges (seed 5), FP32 preconditioner (FP64
+             and BF16 in the comparison), tol 1e-10
+
+    python bench.py [--workload single256] [--steps K] [--warmup W] [--gpus 1]
 
 Prints one JSON line.
 """
@@ -26,74 +35,132 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "3D solves/s at rel-res 1e-10, mixed vs FP64 PCG; p50/p99 latency"
-GRID = (256, 256, 128)            # nx, ny, nz
-BCS = ("P", "P", "DN")
-TOL = 1e-10
-SEED = 2
+COPY_CAL_BYTES = 256 << 20     # bytes read (and written) by the calibration copy
 PEAK = {"hbm_GBs": 8000.0, "f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # TFLOP/s
 MODEPROD = ("modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
             "modeprod_y_bwd", "modeprod_z_bwd")
 
+WORKLOADS = {
+    "single256": dict(grid=(256, 256, 128), bcs=("P", "P", "DN"), batch=1, prec="f32", tol=1e-10,
+                 steps=40, field="charges", ncharges=10_000, seed=2,
+                 desc="3D 256x256x128, BC (P,P,DN), 1e4 random-sign unit charges + "
+                      "N(0,1e-3) noise, zero mean, seed 2; one solve per step"),
+    "latency2d": dict(grid=(64, 64, 1), bcs=("D", "D"), batch=1, prec="f64", tol=1e-12,
+                 steps=200, field="blobs", seed=1,
+                 desc="2D 64x64, BC (D,D), 16 Gaussian blobs (sigma 2, seed 1); "
+                      "one solve per step"),
+    "batch64": dict(grid=(128, 128, 128), bcs=("N", "N", "N"), batch=64, prec="bf16", tol=1e-10,
+                 steps=10, field="charges", ncharges=10_000, seed=3000,
+                 desc="64 RHS on 3D 128^3, BC (N,N,N) singular, 1e4 charges + N(0,1e-3) "
+                      "noise per RHS (seed 3000+b), zero mean; one batched solve per step"),
+    "large512": dict(grid=(512, 512, 512), bcs=("P", "P", "D"), batch=1, prec="f32", tol=1e-10,
+                 steps=10, field="charges", ncharges=1_000_000, seed=5,
+                 desc="3D 512^3, BC (P,P,D), 1e6 random-sign unit charges + N(0,1e-3) "
+                      "noise, zero mean, seed 5; one solve per step"),
+}
 
-def kernel_units(name, prec, N, batch=1):
-    """Algorithmic work of one launch: ('flop', F) for a mode product
-    (2 N n_axis multiply-adds per axis; the last forward product, z in 3D,
-    also applies the Hadamard factor, N more: Table 2 totals
-    4N(nx+ny+nz) + N), or
-    ('byte', B) for an HBM-bound vector kernel (FP64 words moved)."""
-    nx, ny, nz = GRID
-    if name in MODEPROD:
-        n_axis = {"x": nx, "y": ny, "z": nz}[name.split("_")[1]]
-        f = 2.0 * N * n_axis + (N if name == "modeprod_z_fwd" else 0.0)
-        return "flop", f * batch
-    # stencil_dot reads P (<L P, P>); update_ur reads P, R, U and writes R, U
-    # (L P recomputed); dot_rz reads R, Z; update_p reads Z, P and writes P
-    words = {"stencil_dot": 1, "update_ur": 5, "dot_rz": 2, "update_p": 3}.get(name)
-    if words is None:
-        return None, 0.0
-    return "byte", 8.0 * words * N * batch
+
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def run_solves(plan, eta_d, u, steps, flags=0, max_iter=60):
+def make_eta(wl):
+    import synth
+    nx, ny, nz = wl["grid"]
+    shape = (nz, ny, nx) if nz > 1 else (ny, nx)
+    if wl["field"] == "blobs":
+        one = lambda b: synth.gaussian_blobs_2d(nx, ny, 16, 2.0, seed=wl["seed"] + b)
+    else:
+        one = lambda b: synth.charge_field(shape, ncharges=wl["ncharges"], noise_std=1e-3,
+                                           seed=wl["seed"] + b)
+    if wl["batch"] == 1:
+        return one(0)
+    return np.stack([one(b) for b in range(wl["batch"])])
+
+
+def solve_work(name, grid, results, flex=False):
+    """Algorithmic work of one kernel class over one whole (batched) solve,
+    summed over the right-hand sides that are still active in each launch
+    (a converged RHS skips its blocks).  Returns ('flop', F) for a mode
+    product: 2 N n_axis per application, plus N for the Hadamard factor on
+    the last forward product (z in 3D, y in 2D), so that the six add up to
+    Table 2's 4N(nx+ny+nz) + N; or ('byte', B) for an HBM-bound vector
+    kernel, FP64 words moved per unknown times 8 N.  A RHS that converged
+    after s iterations used s + 1 pinv applications p (one at start, one per
+    iteration) and s stencil and U/R updates; its last P update is skipped."""
+    nx, ny, nz = grid
+    N = nx * ny * nz
+    tot = 0.0
+    for r in results:
+        s, p = r["iterations"], r["pinv_applications"]
+        if name in MODEPROD:
+            n_axis = {"x": nx, "y": ny, "z": nz}[name.split("_")[1]]
+            last_fwd = "modeprod_z_fwd" if nz > 1 else "modeprod_y_fwd"
+            tot += p * (2.0 * N * n_axis + (N if name == last_fwd else 0.0))
+        elif name == "stencil_dot":      # reads P (W = L P stored for the flexible beta)
+            tot += s * (1 + flex) * 8.0 * N
+        elif name == "update_ur":        # reads P, R, U, writes R, U (L P recomputed)
+            tot += s * 5 * 8.0 * N
+        elif name == "dot_rz":           # reads R, Z (and W for the flexible beta)
+            tot += p * (2 + flex) * 8.0 * N
+        elif name == "update_p":         # P_0 = Z_0: 2 words; P = Z + beta P: 3 words
+            tot += (2 + 3 * max(p - 2, 0)) * 8.0 * N if p >= 2 else 0.0
+        else:
+            return None, 0.0
+    return ("flop" if name in MODEPROD else "byte"), tot
+
+
+def run_solves(plan, eta_d, u, steps, tol, flags=0, max_iter=60):
     import torch
     lat, res = [], None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
-        _, res, _, rc = plan.solve(eta_d, tol=TOL, max_iter=max_iter, flags=flags, out=u)
+        _, res, _, rc = plan.solve(eta_d, tol=tol, max_iter=max_iter, flags=flags, out=u)
         lat.append(time.perf_counter() - t)
         if rc != 0:
             raise RuntimeError(f"solve failed with status {rc}: {res}")
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, np.array(lat), res[0]
+    return time.perf_counter() - t0, np.array(lat), res
 
 
-def cpu_baseline(eta, budget_s=25.0):
+def cpu_baseline(wl, eta, budget_s=25.0):
     """The FP64 oracle on the host cores: plan (LAPACK eigh) plus PCG to
-    stagnation, repeated while the time budget lasts (at least once)."""
+    stagnation, over the workload's right-hand sides in turn while the time
+    budget lasts (at least one solve; a single-RHS workload repeats its RHS).
+    Returns the oracle solutions by RHS index and the timing record."""
     import oracle
     from threadpoolctl import threadpool_info
-    H = eta.T
-    runs, t_plan, t_solve, sol = 0, 0.0, 0.0, None
+    bcs = wl["bcs"]
+    etas = eta if wl["batch"] > 1 else eta[None]
+    sols, runs, t_plan, t_solve = {}, 0, 0.0, 0.0
     t_all = time.perf_counter()
     while runs == 0 or (time.perf_counter() - t_all) < budget_s * 0.5:
+        b = runs % len(etas)
+        H = etas[b].T
         t = time.perf_counter()
-        M = oracle.PinvPreconditioner(H.shape, BCS)
+        M = oracle.PinvPreconditioner(H.shape, bcs)
         t_plan += time.perf_counter() - t
         t = time.perf_counter()
-        r = oracle.pcg(H, BCS, precond=M)
+        r = oracle.pcg(H, bcs, precond=M)
         t_solve += time.perf_counter() - t
-        sol = r.u.T
+        sols.setdefault(b, r.u.T)
         runs += 1
+        if len(etas) > 1 and runs == len(etas):
+            break
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    return sol, {
+    nx, ny, nz = wl["grid"]
+    gtxt = f"{nx}x{ny}" + (f"x{nz}" if nz > 1 else "")
+    return sols, {
         "value": runs / (t_plan + t_solve),
         "unit": "solves/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"{runs} complete oracle solve(s) of the same 256x256x128 right-hand side "
-                  f"(LAPACK eigh plan + Algorithm 1 to true residual <= 1e-14, FP64 numpy)",
+        "sample": f"{runs} complete oracle solve(s) over {len(sols)} of the workload's "
+                  f"{len(etas)} {gtxt} right-hand side(s) (LAPACK eigh plan + Algorithm 1 "
+                  f"to true residual <= 1e-14, FP64 numpy)",
         "plan_s": t_plan / runs,
         "solve_s": t_solve / runs,
         "host_cpus": os.cpu_count(),
@@ -103,13 +170,17 @@ def cpu_baseline(eta, budget_s=25.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--workload", default="single256", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16"])
+    ap.add_argument("--prec", default=None, choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the FP64/BF16 comparison runs (for profiler runs)")
+                    help="skip the comparison runs in the other precisions (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of 256 MiB three times, the reference "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -117,130 +188,141 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
     from paper_2501_03377_amd import Plan, KP_FLAG_FLEX_BETA
 
-    torch.cuda.set_device(0)
-    nx, ny, nz = GRID
+    wl = WORKLOADS[args.workload]
+    prec = args.prec or wl["prec"]
+    steps = args.steps or wl["steps"]
+    tol, batch, bcs = wl["tol"], wl["batch"], wl["bcs"]
+    nx, ny, nz = wl["grid"]
     N = nx * ny * nz
-    eta = synth.charge_field((nz, ny, nx), ncharges=10_000, noise_std=1e-3, seed=SEED)
-    eta_d = torch.from_numpy(eta).cuda()
-    u = torch.empty_like(eta_d)
-    flags = KP_FLAG_FLEX_BETA if args.prec == "bf16" else 0
 
-    def kernel_table(prof, prec):
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    log(f"workload {args.workload}: generating input")
+    eta = make_eta(wl)
+    eta_d = torch.from_numpy(eta).cuda()
+    flex = lambda p: KP_FLAG_FLEX_BETA if p == "bf16" else 0
+
+    def kernel_table(prof, p, results, nsolves):
         table = {}
         for name, (ms, cnt) in prof.items():
             if cnt == 0:
                 continue
             avg_us = 1000.0 * ms / cnt
-            kind, units = kernel_units(name, prec, N)
+            kind, work = solve_work(name, wl["grid"], results, p == "bf16")
+            units = work * nsolves / cnt            # algorithmic work per launch
             entry = {"avg_us": round(avg_us, 2), "launches": cnt, "total_ms": round(ms, 3)}
             if kind == "flop":
                 tf = units / (avg_us * 1e-6) / 1e12
-                entry.update({"TFLOPs": round(tf, 2), "frac_peak": round(tf / PEAK[prec], 4)})
+                entry.update({"TFLOPs": round(tf, 2), "frac_peak": round(tf / PEAK[p], 4)})
             elif kind == "byte":
                 gbs = units / (avg_us * 1e-6) / 1e9
                 entry.update({"GBs": round(gbs, 1), "frac_peak": round(gbs / PEAK["hbm_GBs"], 4)})
             table[name] = entry
         return table
 
-    plan = Plan(nx, ny, nz, BCS, prec=args.prec)
-    tuning = plan.autotune(batch=1, reps=3) if not args.no_tune else plan.tuning
-    run_solves(plan, eta_d, u, args.warmup, flags)
-    # ---- timed region: the production path (captured graphs, no timing events)
-    T, lat, res = run_solves(plan, eta_d, u, args.steps, flags)
-    # ----
-    u_main = u.cpu().numpy()
-    # Kernel durations: a second region of the same steps with the library's
-    # per-launch HIP events on (launches are then direct, not graph replays;
-    # kernel durations do not depend on that).
-    plan.set_profiling(True)
-    plan.profile_reset()
-    Tp, _, _ = run_solves(plan, eta_d, u, args.steps, flags)
-    prof = plan.profile()
-    plan.set_profiling(False)
-    kernels = kernel_table(prof, args.prec)
+    def measure(p, k):
+        """Tuned plan, warmup, k timed solves (graphs, no timing events), then
+        k profiled solves (per-launch HIP events, direct launches)."""
+        log(f"{p}: plan + autotune")
+        plan = Plan(nx, ny, nz, bcs, prec=p, max_batch=batch)
+        tuning = plan.autotune(batch=batch, reps=3) if not args.no_tune else plan.tuning
+        uu = torch.empty_like(eta_d)
+        run_solves(plan, eta_d, uu, args.warmup, tol, flex(p))
+        log(f"{p}: {k} timed solves")
+        T, lat, res = run_solves(plan, eta_d, uu, k, tol, flex(p))
+        uh = uu.cpu().numpy()
+        log(f"{p}: {k} profiled solves")
+        plan.set_profiling(True)
+        plan.profile_reset()
+        Tp, _, _ = run_solves(plan, eta_d, uu, k, tol, flex(p))
+        prof = plan.profile()
+        plan.close()
+        return dict(T=T, lat=lat, res=res, u=uh, tuning=tuning, Tp=Tp,
+                    kernels=kernel_table(prof, p, res, k))
+
+    m = measure(prec, steps)
+    kernels, res = m["kernels"], m["res"]
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    kind, units = kernel_units(dom, args.prec, N)
+    kind, _ = solve_work(dom, wl["grid"], res)
     d = kernels[dom]
     if kind == "flop":
-        roof = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": PEAK[args.prec],
+        roof = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": PEAK[prec],
                 "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": None, "kernel": dom}
     else:
         roof = {"bound": "hbm", "achieved": d.get("GBs"), "peak": PEAK["hbm_GBs"],
                 "unit": "GB/s", "frac": d.get("frac_peak"), "traffic": None, "kernel": dom}
 
+    its = [r["iterations"] for r in res]
     out = {
         "metric": METRIC,
-        "value": args.steps / T,
+        "value": batch * steps / m["T"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": 1000.0 * T / args.steps,
+        "ms_per_step": 1000.0 * m["T"] / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16"}[args.prec],
+        "dtype": {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16"}[prec],
         "data": "synthetic",
         "config": {
-            "workload": "3D 256x256x128, BC (P,P,DN), 1e4 random-sign unit charges + N(0,1e-3) "
-                        "noise, zero mean, seed 2; one solve per step to rel. residual 1e-10 "
-                        f"with the {args.prec.upper()} pseudoinverse preconditioner",
-            "grid": list(GRID), "bcs": list(BCS), "pinv_precision": args.prec, "tol": TOL,
-            "batch": 1, "tile_configs": tuning,
+            "workload": f"{args.workload}: {wl['desc']}; to rel. residual {tol:g} with the "
+                        f"{prec.upper()} pseudoinverse preconditioner",
+            "grid": list(wl["grid"]), "bcs": list(bcs), "pinv_precision": prec, "tol": tol,
+            "batch": batch, "tile_configs": m["tuning"],
         },
-        "p50_ms": float(np.percentile(lat, 50) * 1000.0),
-        "p99_ms": float(np.percentile(lat, 99) * 1000.0),
-        "iterations": res["iterations"],
-        "pinv_applications": res["pinv_applications"],
-        "rel_res": res["rel_res"],
-        "true_rel_res": res["true_rel_res"],
-        "unknowns_iterations_per_s": N * res["iterations"] * args.steps / T,
-        "ms_per_step_profiled": 1000.0 * Tp / args.steps,
+        "p50_ms": float(np.percentile(m["lat"], 50) * 1000.0),
+        "p99_ms": float(np.percentile(m["lat"], 99) * 1000.0),
+        "iterations": max(its),
+        "iterations_min": min(its),
+        "pinv_applications": max(r["pinv_applications"] for r in res),
+        "rel_res": max(r["rel_res"] for r in res),
+        "true_rel_res": max(r["true_rel_res"] for r in res),
+        "unknowns_iterations_per_s": N * sum(its) * steps / m["T"],
+        "ms_per_step_profiled": 1000.0 * m["Tp"] / steps,
         "roofline": roof,
         "kernels": kernels,
     }
 
     if not args.no_compare:
         comp = {}
-        for prec in ("f64", "f32", "bf16"):
-            if prec == args.prec:
+        for p in ("f64", "f32", "bf16"):
+            if p == prec:
                 continue
-            p2 = Plan(nx, ny, nz, BCS, prec=prec)
-            if not args.no_tune:
-                p2.autotune(batch=1, reps=3)
-            fl = KP_FLAG_FLEX_BETA if prec == "bf16" else 0
-            u2 = torch.empty_like(eta_d)
-            run_solves(p2, eta_d, u2, 3, fl)
-            k2 = max(5, args.steps // 4)
-            T2, lat2, res2 = run_solves(p2, eta_d, u2, k2, fl)
-            u2h = u2.cpu().numpy()
-            p2.set_profiling(True)
-            p2.profile_reset()
-            run_solves(p2, eta_d, u2, k2, fl)
-            comp[prec] = {"solves_per_s": k2 / T2,
-                          "p50_ms": float(np.percentile(lat2, 50) * 1000.0),
-                          "iterations": res2["iterations"],
-                          "pinv_applications": res2["pinv_applications"],
-                          "kernels": kernel_table(p2.profile(), prec),
-                          "u": u2h}
-            p2.close()
+            c = measure(p, max(3, steps // 4))
+            comp[p] = {"solves_per_s": batch * len(c["lat"]) / c["T"],
+                       "p50_ms": float(np.percentile(c["lat"], 50) * 1000.0),
+                       "iterations": max(r["iterations"] for r in c["res"]),
+                       "pinv_applications": max(r["pinv_applications"] for r in c["res"]),
+                       "kernels": c["kernels"], "u": c["u"]}
         out["compare"] = comp
 
     if not args.no_cpu_baseline:
-        sol, cpu = cpu_baseline(eta)
+        log("oracle on the host cores")
+        sols, cpu = cpu_baseline(wl, eta)
         out["cpu_baseline"] = cpu
-        nrm = np.linalg.norm(sol)
-        out["rel_err_vs_oracle"] = float(np.linalg.norm(u_main - sol) / nrm)
-        for prec, c in out.get("compare", {}).items():
-            c["rel_err_vs_oracle"] = float(np.linalg.norm(c["u"] - sol) / nrm)
+
+        def err(uh):
+            uh = uh if batch > 1 else uh[None]
+            return max(float(np.linalg.norm(uh[b] - s) / np.linalg.norm(s))
+                       for b, s in sols.items())
+        out["rel_err_vs_oracle"] = err(m["u"])
+        out["rel_err_sample"] = f"max over RHS {sorted(sols)}"
+        for c in out.get("compare", {}).values():
+            c["rel_err_vs_oracle"] = err(c["u"])
     for c in out.get("compare", {}).values():
         c.pop("u", None)
     if "f64" in out.get("compare", {}):
         out["speedup_vs_fp64"] = out["value"] / out["compare"]["f64"]["solves_per_s"]
-    plan.close()
     print(json.dumps(out))
 
 

@@ -21,6 +21,8 @@
 // with FP32 accumulation.  Lane l supplies row (X) / column (B) l%16 and the k
 // values CH*(l/16) .. +CH-1 of each k-block; output item v of lane l is column
 // l%16 and row 4*(l/16)+v (FP32, BF16) or 4*v+l/16 (FP64, measured on gfx950).
+#include <type_traits>
+
 #include "kp_common.h"
 #include "kp_internal.h"
 
@@ -34,30 +36,27 @@ template <int PREC> struct MT;
 template <> struct MT<PREC_F64> {
   using tc = double; using acc = d4;
   static constexpr int CH = 4, NV = 2;       // k per lane per k-block, 16-byte units
+  static constexpr int STEPS = 4;            // MFMAs per k-block and fragment pair
   struct chunk { double v[4]; };
-  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], c, 0, 0, 0);
-    return c;
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c, int s) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[s], b.v[s], c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 template <> struct MT<PREC_F32> {
   using tc = float; using acc = f4;
-  static constexpr int CH = 4, NV = 1;
+  static constexpr int CH = 4, NV = 1, STEPS = 4;
   struct chunk { float v[4]; };
-  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], c, 0, 0, 0);
-    return c;
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c, int s) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[s], b.v[s], c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct MT<PREC_BF16> {
   using tc = __bf16; using acc = f4;
-  static constexpr int CH = 8, NV = 1;
+  static constexpr int CH = 8, NV = 1, STEPS = 1;
   struct chunk { bf8 v; };
-  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c) {
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c, int) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
@@ -77,44 +76,48 @@ __device__ __forceinline__ typename MT<PREC>::tc to_tc(double x) {
 }
 
 // ---- one lane's CH consecutive k values of one row --------------------------
-template <int PREC, class Ti>
-__device__ __forceinline__ typename MT<PREC>::chunk load_x(const Ti* __restrict__ row, int k0,
-                                                          int K, bool vec_ok, double scale,
-                                                          bool scaled) {
-  using M = MT<PREC>;
-  using tc = typename M::tc;
-  constexpr int CH = M::CH;
-  typename M::chunk c;
-  tc t[CH];
-  if (vec_ok && k0 < K) {
-    if constexpr (sizeof(Ti) == 8) {            // FP64 source, convert
+// Loaded raw (source type) into a register ring and converted only when the
+// MFMA needs them, so that no arithmetic waits on a load in flight.  Lanes
+// past the end of the row (k0 >= K, and rows past the end, which arrive with
+// k0 = K) read the row's last CH values instead: the packed operator is zero
+// for k >= K, so they add nothing (both are finite data of the same grid).
+// VEC: the row length is a multiple of CH (16-byte loads); else CH scalar
+// loads.
+template <int PREC, class Ti> struct XRaw { Ti v[MT<PREC>::CH]; };
+
+template <int PREC, class Ti, bool VEC>
+__device__ __forceinline__ XRaw<PREC, Ti> load_raw(const Ti* __restrict__ row, int k0, int K) {
+  constexpr int CH = MT<PREC>::CH;
+  XRaw<PREC, Ti> x;
+  if constexpr (VEC) {
+    const Ti* src = row + (k0 < K ? k0 : K - CH);
+    static_assert((CH * sizeof(Ti)) % 16 == 0, "whole 16-byte units");
 #pragma unroll
-      for (int q = 0; q < CH / 2; ++q) {
-        const d2 x = *reinterpret_cast<const d2*>(row + k0 + 2 * q);
-        t[2 * q] = to_tc<PREC>(scaled ? x[0] * scale : x[0]);
-        t[2 * q + 1] = to_tc<PREC>(scaled ? x[1] * scale : x[1]);
-      }
-    } else if constexpr (PREC == PREC_BF16) {   // bf16 source
-      c.v = *reinterpret_cast<const bf8*>(row + k0);
-      return c;
-    } else {                                    // fp32 source
-      const f4 x = *reinterpret_cast<const f4*>(row + k0);
-#pragma unroll
-      for (int s = 0; s < CH; ++s) t[s] = x[s];
+    for (int q = 0; q < (int)(CH * sizeof(Ti)) / 16; ++q) {
+      const u4 u = *reinterpret_cast<const u4*>(reinterpret_cast<const char*>(src) + 16 * q);
+      __builtin_memcpy(reinterpret_cast<char*>(x.v) + 16 * q, &u, 16);
     }
   } else {
 #pragma unroll
-    for (int s = 0; s < CH; ++s) {
-      if (!vec_ok && k0 + s < K) {
-        double x = to_double(row[k0 + s]);
-        t[s] = to_tc<PREC>(scaled ? x * scale : x);
-      } else {
-        t[s] = (tc)0.0f;
-      }
+    for (int s = 0; s < CH; ++s) x.v[s] = row[k0 + s < K ? k0 + s : K - 1];
+  }
+  return x;
+}
+
+template <int PREC, class Ti>
+__device__ __forceinline__ typename MT<PREC>::chunk cvt_raw(const XRaw<PREC, Ti>& x, double scale,
+                                                           bool scaled) {
+  using M = MT<PREC>;
+  typename M::chunk c;
+  if constexpr (std::is_same<Ti, typename M::tc>::value) {
+    __builtin_memcpy(&c, &x, sizeof(c));
+  } else {
+#pragma unroll
+    for (int s = 0; s < M::CH; ++s) {
+      const double d = to_double(x.v[s]);
+      c.v[s] = to_tc<PREC>(scaled ? d * scale : d);
     }
   }
-#pragma unroll
-  for (int s = 0; s < CH; ++s) c.v[s] = t[s];
   return c;
 }
 
@@ -145,12 +148,19 @@ __device__ __forceinline__ typename MT<PREC>::chunk load_b(const u4* __restrict_
 //   inverse on the output (low-precision range guard)
 // Grid: x = row blocks * column chunks, y = right-hand side.
 // ---------------------------------------------------------------------------
-template <int PREC, class Ti, class To, int WN, int WM, int WC>
+constexpr int group_size(int wn, int most) {
+  int j = wn < most ? wn : most;
+  while (wn % j != 0) --j;
+  return j;
+}
+static_assert(group_size(6, 4) == 3 && group_size(12, 8) == 6 && group_size(16, 8) == 8, "");
+
+template <int PREC, class Ti, class To, int WN, int WM, int WC, bool VEC>
 __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
     const u4* __restrict__ Bpk, int npk, int ncc, const Ti* __restrict__ X, To* __restrict__ Y,
-    int K, int rows, int64_t N, int vec_ok, const RhsState* __restrict__ st, int in_scale,
-    int out_scale, const double* __restrict__ la, const double* __restrict__ lb,
-    const double* __restrict__ lc, int a1) {
+    int K, int rows, int64_t N, const RhsState* __restrict__ st, int in_scale, int out_scale,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1) {
   using M = MT<PREC>;
   constexpr int NT = 64 * WR * WC;
   constexpr int CW = 16 * WN;                 // columns per wave
@@ -158,13 +168,24 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   constexpr int BR = WR * 16 * WM;            // rows per block
   constexpr int CH = M::CH, NV = M::NV, KB = 4 * CH;
   constexpr int UNITS = 4 * NV * CB;          // 16-byte units per operator k-block
-  // k-blocks per LDS stage (one barrier per stage): more for the faster
-  // MFMAs, at most 32 KiB per stage (two stages resident)
-  constexpr int KSP = PREC == PREC_BF16 ? 4 : (PREC == PREC_F32 ? 2 : 1);
+  // k-blocks per LDS stage (one barrier per stage), at most 32 KiB per stage
+  // (two stages resident).  The data rows are prefetched one stage ahead in a
+  // register ring of KS k-blocks indexed by the unrolled step, so no register
+  // ever moves inside the ring.
+  constexpr int KSP = PREC == PREC_F64 ? 2 : 4;
   constexpr int KSL = 32768 / (16 * UNITS) > 0 ? 32768 / (16 * UNITS) : 1;
   constexpr int KS = KSP < KSL ? KSP : KSL;
   constexpr int SUNITS = KS * UNITS;          // units per stage
   constexpr int UPT = (SUNITS + NT - 1) / NT; // units per thread per stage
+  // operator fragments read per group: the largest divisor of WN whose
+  // fragments take at most 32 VGPRs
+  constexpr int JG = group_size(WN, PREC == PREC_F64 ? 4 : 8);
+  // data ring depth: KS k-blocks, halved while the raw data would take more
+  // than 64 VGPRs (the FP64 sources of the first product are twice as wide)
+  constexpr int RAWV = CH * (int)sizeof(Ti) / 4;
+  constexpr int XD = (KS * WM * RAWV <= 64 || KS == 1) ? KS
+                     : ((KS / 2) * WM * RAWV <= 64 || KS == 2) ? KS / 2 : KS / 4;
+  static_assert(KS % XD == 0, "ring depth divides the stage");
 
   const int rhs = blockIdx.y;
   if (st && st[rhs].done) return;
@@ -199,13 +220,10 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
-  // Prefetch registers: the operator stage one stage ahead (through LDS), the
-  // data rows XD k-blocks ahead (register ring).  Plain unrolled loops, no
-  // closures over these arrays: a captured array gets an address and lands in
-  // scratch memory.
-  constexpr int XD = PREC == PREC_F64 ? 2 : 3;
+  // Plain unrolled loops, no closures over these arrays: a captured array
+  // gets an address and lands in scratch memory.
   u4 breg[UPT];
-  typename M::chunk xq[XD][WM];
+  XRaw<PREC, Ti> xq[XD][WM];
   constexpr bool FULL = (SUNITS % NT) == 0;
   const u4* bsrc = Bpk + c0;
   const int cmax = npk - c0;                  // packed columns left for this block
@@ -235,7 +253,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
     const int k0 = d * KB + CH * g;
 #pragma unroll
     for (int i = 0; i < WM; ++i)
-      xq[d][i] = load_x<PREC, Ti>(xrow[i], (rok[i] && d < nkb) ? k0 : K, K, vec_ok, scale, scaled);
+      xq[d][i] = load_raw<PREC, Ti, VEC>(xrow[i], (rok[i] && d < nkb) ? k0 : K, K);
   }
   KP_STORE_STAGE(0)
   __syncthreads();
@@ -247,26 +265,33 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const int kb = sg * KS + kk;
+      const int slot = kk % XD;
       if (KS == 1 || kb < nkb) {
+        typename M::chunk xa[WM];
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          const typename M::chunk b =
-              load_b<PREC>(lds[buf] + kk * UNITS, g, cw + 16 * j + l16, CB);
+        for (int i = 0; i < WM; ++i) xa[i] = cvt_raw<PREC, Ti>(xq[slot][i], scale, scaled);
 #pragma unroll
-          for (int i = 0; i < WM; ++i) acc[i][j] = M::mma(xq[0][i], b, acc[i][j]);
+        for (int j0 = 0; j0 < WN; j0 += JG) {
+          typename M::chunk b[JG];
+#pragma unroll
+          for (int jj = 0; jj < JG; ++jj)
+            b[jj] = load_b<PREC>(lds[buf] + kk * UNITS, g, cw + 16 * (j0 + jj) + l16, CB);
+          // consecutive MFMAs update different accumulators
+#pragma unroll
+          for (int s = 0; s < M::STEPS; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj)
+#pragma unroll
+              for (int i = 0; i < WM; ++i)
+                acc[i][j0 + jj] = M::mma(xa[i], b[jj], acc[i][j0 + jj], s);
         }
       }
-      // advance the data ring and fetch k-block kb + XD
-#pragma unroll
-      for (int d = 0; d + 1 < XD; ++d)
-#pragma unroll
-        for (int i = 0; i < WM; ++i) xq[d][i] = xq[d + 1][i];
+      // this ring slot now takes k-block kb + XD
       const int kn = kb + XD;
       const int k0 = kn * KB + CH * g;
 #pragma unroll
       for (int i = 0; i < WM; ++i)
-        xq[XD - 1][i] =
-            load_x<PREC, Ti>(xrow[i], (rok[i] && kn < nkb) ? k0 : K, K, vec_ok, scale, scaled);
+        xq[slot][i] = load_raw<PREC, Ti, VEC>(xrow[i], (rok[i] && kn < nkb) ? k0 : K, K);
     }
     if (more) { KP_STORE_STAGE(buf ^ 1) }
     __syncthreads();
@@ -359,10 +384,14 @@ constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 int mp_num_configs() { return kNumCfgs; }
 
-// Whether configuration `id` is compiled for `prec` (FP64 omits the tiles
-// whose accumulators would spill: 16 fragments wide or 32 fragments per wave).
+// Whether configuration `id` is compiled for `prec` (tiles whose registers
+// would spill are left out: in FP64 those 16 fragments wide or with 4 row
+// fragments of 4 or more columns, in BF16 the 16 x 2 tile).
 bool mp_config_allowed(int id, int prec) {
-  return id >= 0 && id < kNumCfgs && !(prec == PREC_F64 && (id == 7 || id >= 15));
+  if (id < 0 || id >= kNumCfgs) return false;
+  if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || id >= 15);
+  if (prec == PREC_BF16) return id != 16;
+  return true;
 }
 
 void mp_config(int id, int* wn, int* wm, int* wc) {
@@ -430,9 +459,9 @@ void mp_pack(const double* B, int K, int prec, void* dst) {
     }
 }
 
-template <int PREC, class Ti, class To, int WN, int WM, int WC>
+template <int PREC, class Ti, class To, int WN, int WM, int WC, bool VEC>
 static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int rows,
-                       int batch, int vec_ok, const RhsState* st, int in_scale, int out_scale,
+                       int batch, const RhsState* st, int in_scale, int out_scale,
                        const double* la, const double* lb, const double* lc, int a1,
                        hipStream_t s) {
   const int K = op.n[ax];
@@ -442,9 +471,9 @@ static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void*
   int npk, nkb;
   packed_geometry(K, PREC, &npk, &nkb);
   dim3 grid(nrb * ncc, batch);
-  hipLaunchKernelGGL((mp_kernel<PREC, Ti, To, WN, WM, WC>), grid, dim3(64 * WR * WC), 0, s,
+  hipLaunchKernelGGL((mp_kernel<PREC, Ti, To, WN, WM, WC, VEC>), grid, dim3(64 * WR * WC), 0, s,
                      (const u4*)(fwd ? op.Bf[ax] : op.Bb[ax]), npk, ncc, (const Ti*)X, (To*)Y, K,
-                     rows, (int64_t)op.N, vec_ok, st, in_scale, out_scale, la, lb, lc, a1);
+                     rows, (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1);
 }
 
 template <int PREC, class Ti, class To>
@@ -455,29 +484,50 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
   const int CH = PREC == PREC_BF16 ? 8 : 4;
-  const int vec_ok = (K % CH == 0) ? 1 : 0;
   trace_begin(cls, s);
+  if (K % CH != 0) {
+    // rows too ragged for 16-byte loads: one scalar-load tile serves every
+    // configuration (such grids are small)
+    launch_cfg<PREC, Ti, To, 4, 2, 2, false>(op, ax, fwd, X, Y, rows, batch, st, in_scale,
+                                             out_scale, la, lb, lc, a1, s);
+    trace_end(cls, s);
+    return;
+  }
 #define KP_CASE(ID, W, M_, C)                                                                 \
   case ID:                                                                                    \
-    launch_cfg<PREC, Ti, To, W, M_, C>(op, ax, fwd, X, Y, rows, batch, vec_ok, st, in_scale,  \
-                                       out_scale, la, lb, lc, a1, s);                         \
+    launch_cfg<PREC, Ti, To, W, M_, C, true>(op, ax, fwd, X, Y, rows, batch, st, in_scale,    \
+                                             out_scale, la, lb, lc, a1, s);                   \
     break;
 #define KP_COMMON_CASES                                                                      \
-  KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(3, 4, 4, 1)             \
-  KP_CASE(4, 6, 2, 1) KP_CASE(5, 8, 2, 1) KP_CASE(6, 12, 1, 1)                               \
-  KP_CASE(8, 2, 4, 2) KP_CASE(9, 3, 4, 2) KP_CASE(10, 4, 2, 2) KP_CASE(11, 4, 4, 2)           \
-  KP_CASE(12, 6, 2, 2) KP_CASE(14, 8, 2, 2)
-  if constexpr (PREC == PREC_F64) {     // the 16-fragment-wide tiles spill in FP64
+  KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(4, 6, 2, 1)             \
+  KP_CASE(5, 8, 2, 1) KP_CASE(6, 12, 1, 1) KP_CASE(8, 2, 4, 2) KP_CASE(9, 3, 4, 2)            \
+  KP_CASE(10, 4, 2, 2) KP_CASE(12, 6, 2, 2) KP_CASE(14, 8, 2, 2)
+  // tiles whose registers would spill are left out: FP64 accumulators and
+  // operands are twice as wide, and the FP64-sourced BF16 product holds
+  // 16 VGPRs of raw data per row fragment and k-block
+  if constexpr (PREC == PREC_F64) {
     switch (cfg) {
       KP_COMMON_CASES
+      default: KP_CASE(13, 8, 1, 2)
+    }
+  } else if constexpr (PREC == PREC_F32) {
+    switch (cfg) {
+      KP_COMMON_CASES
+      KP_CASE(3, 4, 4, 1)
+      KP_CASE(7, 16, 1, 1)
+      KP_CASE(11, 4, 4, 2)
+      KP_CASE(15, 16, 1, 2)
+      KP_CASE(16, 16, 2, 1)
+      KP_CASE(17, 8, 4, 2)
       default: KP_CASE(13, 8, 1, 2)
     }
   } else {
     switch (cfg) {
       KP_COMMON_CASES
+      KP_CASE(3, 4, 4, 1)
       KP_CASE(7, 16, 1, 1)
+      KP_CASE(11, 4, 4, 2)
       KP_CASE(15, 16, 1, 2)
-      KP_CASE(16, 16, 2, 1)
       KP_CASE(17, 8, 4, 2)
       default: KP_CASE(13, 8, 1, 2)
     }

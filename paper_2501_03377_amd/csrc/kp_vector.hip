@@ -230,18 +230,24 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
   }
 }
 
-// ------------------------------------------------------ tiled stencil ----
+// ------------------------------------------------------ marching stencil ----
 // Kernels that apply the 7-point (5-point in 2D) minus Laplacian of eq. (3.2).
-// A 256-thread block owns a 64 x 16 tile of (x, y) cells of PB consecutive
-// z-planes; each thread computes 4 cells per plane (rows ty, ty+4, ty+8,
-// ty+12) and issues all their neighbour loads before any arithmetic.  Blocks
-// are mapped to work XCD-aware: the hardware deals blocks to the 8 XCDs round
-// robin, and block b is given work item (b % 8) * share + b / 8, so that each
-// XCD sweeps a contiguous range of planes and finds the y- and z-neighbours
-// of a plane in its own L2.  Boundary neighbours are loaded from a valid
-// address and replaced at compute time by the ghost rule of eq. (3.1)
-// (periodic neighbours are loaded wrapped).
-constexpr int STX = 64, STY = 16, SRY = 4;
+// A 256-thread block owns a 64 x 16 tile of (x, y) cells and marches over PB
+// consecutive z-planes.  Each wave covers the 64 columns of 4 consecutive
+// rows: lane l holds the cells of column i0 + l in those rows for the planes
+// k-1, k and k+1 in registers, so a plane's centre values are loaded once
+// from memory.  The x-neighbours come from the adjacent lanes (a shuffle);
+// the two tile-edge columns of the 4 rows are fetched by one load in which
+// 8 lanes take part and broadcast with readlane; the y-neighbours of the
+// inner rows are the lane's own registers and only the rows above and below
+// the strip are loaded.  Every load for plane k+1 (and the centres of plane
+// k+2) is issued before plane k is computed.  Blocks are mapped to work
+// XCD-aware: the hardware deals blocks to the 8 XCDs round robin, and block
+// b is given work item (b % 8) * share + b / 8, so that each XCD sweeps a
+// contiguous range of plane groups and finds the neighbours in its own L2.
+// Boundary neighbours are loaded from a valid address and replaced at compute
+// time by the ghost rule of eq. (3.1); periodic neighbours are loaded wrapped.
+constexpr int STX = 64, RY = 4, STY = RY * (VT / 64);
 constexpr int NXCD = 8;
 
 enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP };
@@ -258,6 +264,21 @@ __device__ __forceinline__ double ghost_lo(int bc, double c) {
 }
 __device__ __forceinline__ double ghost_hi(int bc, double c) {
   return (bc == BC_N || bc == BC_DN) ? c : 0.0;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// plane index of a z-neighbour: wrapped when periodic, else clamped (the
+// value loaded at a wall is replaced by the ghost rule)
+__device__ __forceinline__ int zload(int k, int nz, int bcz) {
+  if (k < 0) return bcz == BC_P ? nz - 1 : 0;
+  if (k >= nz) return bcz == BC_P ? 0 : nz - 1;
+  return k;
 }
 
 // ZM_PW:   partials <L P, P>, sum L P; W = L P stored when W != nullptr
@@ -277,70 +298,102 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   const int tile = wok ? w % zg.ntiles : 0, grp = wok ? w / zg.ntiles : 0;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int bcx = g.bc[0], bcy = g.bc[1], bcz = g.bc[2];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int i = (tile % zg.ntx) * STX + tx;
-  const int y0 = (tile / zg.ntx) * STY + ty;
-  const bool col_ok = wok && i < nx;
-  const int ic = i < nx ? i : nx - 1;
-  const int il = i > 0 ? ic - 1 : (bcx == BC_P ? nx - 1 : ic);
-  const int ir = i < nx - 1 ? ic + 1 : (bcx == BC_P ? 0 : ic);
+  const int lane = threadIdx.x & 63;
+  const int i0 = (tile % zg.ntx) * STX;
+  const int i = i0 + lane;
+  const int y0 = (tile / zg.ntx) * STY + (threadIdx.x >> 6) * RY;   // first row of the wave
+  const bool run = wok && y0 < ny;                                   // wave-uniform
+  const bool col_ok = i < nx;
+  const int ic = col_ok ? i : nx - 1;
+  // tile-edge columns: left neighbour of lane 0, right neighbour of lane e
+  const int ie = min(i0 + STX - 1, nx - 1), e = ie - i0;
+  const int xl = i0 > 0 ? i0 - 1 : (bcx == BC_P ? nx - 1 : 0);
+  const int xr = ie < nx - 1 ? ie + 1 : (bcx == BC_P ? 0 : ie);
+  const bool lwall = i0 == 0 && bcx != BC_P, rwall = ie == nx - 1 && bcx != BC_P;
+  // rows of the strip and the halo rows above and below it
+  const int re = min(y0 + RY - 1, ny - 1) - y0;          // last valid row offset
+  const int yl = y0 > 0 ? y0 - 1 : (bcy == BC_P ? ny - 1 : 0);
+  const int yh = y0 + re < ny - 1 ? y0 + re + 1 : (bcy == BC_P ? 0 : y0 + re);
+  const bool bwall = y0 == 0 && bcy != BC_P, twall = y0 + re == ny - 1 && bcy != BC_P;
   const bool three = g.dim == 3;
   const uint32_t plane = (uint32_t)nx * ny;
   const int64_t off = (int64_t)rhs * g.N;
   const double* p = P + off;
   const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
   const double mean = (MODE == ZM_TRUE) ? st[rhs].mean : 0.0;
-  const int kb = grp * zg.pb, ke = min(kb + zg.pb, nz);
+  const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
+  // edge-load lanes: lane r < RY fetches the left edge of row r, lane 32 + r
+  // the right edge
+  const int er = (lane & 31) < RY ? (lane & 31) : 0;
+  const bool eload = (lane & 31) < RY;
+  const uint32_t erow = (uint32_t)min(y0 + er, ny - 1) * nx + (lane < 32 ? xl : xr);
+
+  auto centre = [&](int kk, double (&v)[RY]) {
+    const uint32_t base = (uint32_t)zload(kk, nz, bcz) * plane + ic;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) v[r] = p[base + (uint32_t)min(y0 + r, ny - 1) * nx];
+  };
+  auto halo = [&](int kk, double& lo, double& hi, double& ed) {
+    const uint32_t base = (uint32_t)kk * plane;
+    lo = p[base + (uint32_t)yl * nx + ic];
+    hi = p[base + (uint32_t)yh * nx + ic];
+    ed = eload ? p[base + erow] : 0.0;
+  };
 
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = kb; k < ke; ++k) {
-    const int kl = k > 0 ? k - 1 : (bcz == BC_P ? nz - 1 : k);
-    const int kh = k < nz - 1 ? k + 1 : (bcz == BC_P ? 0 : k);
-    double c[SRY], lx[SRY], hx[SRY], ly[SRY], hy[SRY], lz[SRY], hz[SRY], ea[SRY], eb[SRY];
-    int jj[SRY];
+  double pv[RY], cv[RY], nv[RY], nn[RY];
 #pragma unroll
-    for (int r = 0; r < SRY; ++r) {              // all loads first
-      const int j = y0 + SRY * r;
-      jj[r] = j;
-      const int jc = j < ny ? j : ny - 1;
-      const int jl = jc > 0 ? jc - 1 : (bcy == BC_P ? ny - 1 : jc);
-      const int jh = jc < ny - 1 ? jc + 1 : (bcy == BC_P ? 0 : jc);
-      const uint32_t rb = (uint32_t)k * plane + (uint32_t)jc * nx;
-      c[r] = p[rb + ic];
-      lx[r] = p[rb + il];
-      hx[r] = p[rb + ir];
-      ly[r] = p[(uint32_t)k * plane + (uint32_t)jl * nx + ic];
-      hy[r] = p[(uint32_t)k * plane + (uint32_t)jh * nx + ic];
-      if (three) {
-        lz[r] = p[(uint32_t)kl * plane + (uint32_t)jc * nx + ic];
-        hz[r] = p[(uint32_t)kh * plane + (uint32_t)jc * nx + ic];
-      }
-      const bool ok = col_ok && j < ny;
-      const int64_t idx = off + rb + ic;
-      if (MODE == ZM_UR) {
-        ea[r] = ok ? R[idx] : 0.0;
-        eb[r] = ok ? U[idx] : 0.0;
-      } else if (MODE == ZM_TRUE) {
-        ea[r] = ok ? eta[idx] : 0.0;
+  for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = 0.0;
+  double hlo = 0.0, hhi = 0.0, hed = 0.0;
+  if (kb < ke) {
+    if (three) {
+      centre(kb - 1, pv);
+      centre(kb + 1, nv);
+    }
+    centre(kb, cv);
+    halo(kb, hlo, hhi, hed);
+  }
+  for (int k = kb; k < ke; ++k) {
+    // issue the loads of the next step
+    double nlo = 0.0, nhi = 0.0, ned = 0.0;
+    if (k + 1 < ke) {
+      if (three) centre(k + 2, nn);
+      halo(k + 1, nlo, nhi, ned);
+    }
+    double ea[RY], eb[RY];
+    const uint32_t pbase = (uint32_t)k * plane;
+    if (MODE == ZM_UR || MODE == ZM_TRUE) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const int64_t idx = off + pbase + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
+        if (MODE == ZM_UR) {
+          ea[r] = R[idx];
+          eb[r] = U[idx];
+        } else {
+          ea[r] = eta[idx];
+        }
       }
     }
+    // x-neighbours from the adjacent lanes, tile edges from the edge lanes
 #pragma unroll
-    for (int r = 0; r < SRY; ++r) {
-      const int j = jj[r];
-      const double cc = c[r];
-      const double vx_l = i > 0 || bcx == BC_P ? lx[r] : ghost_lo(bcx, cc);
-      const double vx_h = i < nx - 1 || bcx == BC_P ? hx[r] : ghost_hi(bcx, cc);
-      const double vy_l = j > 0 || bcy == BC_P ? ly[r] : ghost_lo(bcy, cc);
-      const double vy_h = j < ny - 1 || bcy == BC_P ? hy[r] : ghost_hi(bcy, cc);
-      double wv = (2.0 * cc - vx_l) - vx_h;
-      wv += (2.0 * cc - vy_l) - vy_h;
+    for (int r = 0; r < RY; ++r) {
+      const double cc = cv[r];
+      const double el = readlane_d(hed, r), eh = readlane_d(hed, 32 + r);
+      double vxl = __shfl_up(cc, 1), vxh = __shfl_down(cc, 1);
+      if (lane == 0) vxl = lwall ? ghost_lo(bcx, cc) : el;
+      if (lane == e) vxh = rwall ? ghost_hi(bcx, cc) : eh;
+      double vyl = r > 0 ? cv[r > 0 ? r - 1 : 0] : (bwall ? ghost_lo(bcy, cc) : hlo);
+      double vyh = cv[r < RY - 1 ? r + 1 : r];
+      if (r >= re) vyh = twall ? ghost_hi(bcy, cc) : hhi;
+      double wv = (2.0 * cc - vxl) - vxh;
+      wv += (2.0 * cc - vyl) - vyh;
       if (three) {
-        const double vz_l = k > 0 || bcz == BC_P ? lz[r] : ghost_lo(bcz, cc);
-        const double vz_h = k < nz - 1 || bcz == BC_P ? hz[r] : ghost_hi(bcz, cc);
-        wv += (2.0 * cc - vz_l) - vz_h;
+        const double vzl = k > 0 || bcz == BC_P ? pv[r] : ghost_lo(bcz, cc);
+        const double vzh = k < nz - 1 || bcz == BC_P ? nv[r] : ghost_hi(bcz, cc);
+        wv += (2.0 * cc - vzl) - vzh;
       }
-      if (col_ok && j < ny) {
-        const int64_t idx = off + (uint32_t)k * plane + (uint32_t)j * nx + i;
+      if (col_ok && r <= re) {
+        const int64_t idx = off + pbase + (uint32_t)(y0 + r) * nx + i;
         if (MODE == ZM_PW) {
           a0 += wv * cc;
           a1 += wv;
@@ -362,6 +415,15 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
         }
       }
     }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      pv[r] = cv[r];
+      cv[r] = nv[r];
+      nv[r] = nn[r];
+    }
+    hlo = nlo;
+    hhi = nhi;
+    hed = ned;
   }
   if (MODE == ZM_LAP) return;
   if (MODE == ZM_UR) {
@@ -383,9 +445,13 @@ ZGrid zgrid_for(const Geom& g) {
   ZGrid z;
   z.ntx = (g.nx + STX - 1) / STX;
   z.ntiles = z.ntx * ((g.ny + STY - 1) / STY);
-  // planes per block: the fewest that keep the blocks within GMAX partials
-  z.pb = 1;
-  while ((int64_t)z.ntiles * ((g.nz + z.pb - 1) / z.pb) > GMAX && z.pb < g.nz) z.pb *= 2;
+  // planes per block: up to 16, fewer while a right-hand side would have
+  // under 1024 blocks, more while it would exceed the GMAX partial slots
+  // (a function of the grid only, so batched and single solves sum alike)
+  z.pb = 16;
+  auto blocks = [&](int pb) { return (int64_t)z.ntiles * ((g.nz + pb - 1) / pb); };
+  while (z.pb > 1 && blocks(z.pb) < 1024) z.pb >>= 1;
+  while (blocks(z.pb) > GMAX - NXCD && z.pb < g.nz) z.pb <<= 1;
   z.ngroups = (g.nz + z.pb - 1) / z.pb;
   z.nwork = z.ntiles * z.ngroups;
   z.share = (z.nwork + NXCD - 1) / NXCD;

@@ -106,22 +106,32 @@ def test_pinv_batch_matches_single():
         assert np.array_equal(zb[b], z1)
 
 
+# tile configurations compiled per precision (the others would spill)
+TILE_CONFIGS = {"f64": [c for c in range(18) if c not in (3, 7, 11, 15, 16, 17)],
+                "f32": list(range(18)),
+                "bf16": [c for c in range(18) if c != 16]}
+
+
+@pytest.mark.parametrize("shape", [(20, 36, 70), (24, 40, 72)])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_tile_shapes_are_bitwise_identical(prec):
+def test_tile_shapes_are_bitwise_identical(prec, shape):
     # every tile shape sums over k in the same order, so the result does not
-    # depend on the autotuner's choice
+    # depend on the autotuner's choice; (20, 36, 70) has rows too ragged for
+    # 16-byte loads, (24, 40, 72) takes the vector path with ragged k-blocks
     from paper_2501_03377_amd.kpcg import kp_plan_set_tuning
-    import torch
     rng = np.random.default_rng(6)
-    shape = (20, 36, 70)
     r = to_dev(rng.standard_normal((2,) + shape))
     plan = _plan(shape, ("P", "D", "N"), prec=prec, max_batch=2)
     ref = to_host(plan.apply_pinv(r))
-    n = 18
-    for cfg in range(n):
-        if prec == "f64" and (cfg == 7 or cfg >= 15):
+    rh = to_host(r)
+    for b in range(2):
+        assert rel(ref[b], oracle_pinv(rh[b], ("P", "D", "N"))) <= PINV_TOL[prec]
+    for cfg in range(18):
+        rc = kp_plan_set_tuning(plan._h, [cfg] * 6)
+        if cfg not in TILE_CONFIGS[prec]:
+            assert rc != 0, cfg
             continue
-        assert kp_plan_set_tuning(plan._h, [cfg] * 6) == 0
+        assert rc == 0, cfg
         z = to_host(plan.apply_pinv(r))
         assert np.array_equal(z, ref), cfg
 

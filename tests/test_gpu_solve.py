@@ -72,7 +72,7 @@ def test_multi_tile_ragged(shape, bcs, prec):
     assert res[0]["true_rel_res"] <= 1e-10
 
 
-def test_config1_2d_dirichlet_blobs():
+def test_2d_64x64_dirichlet_blobs_f64():
     # 2D 64 x 64, Dirichlet on every edge, 16 Gaussian blobs, FP64, tol 1e-12
     eta = synth.gaussian_blobs_2d(64, 64, 16, 2.0, seed=1)
     u, res, hist, rc = _solve(eta, ("D", "D"), prec="f64", tol=1e-12)
@@ -81,12 +81,12 @@ def test_config1_2d_dirichlet_blobs():
     assert res[0]["rel_res"] <= 1e-12 and res[0]["true_rel_res"] <= 1e-12
 
 
-def test_config2_full_size_f32():
+def test_full_size_256x256x128_ppdn_f32():
     # 256 x 256 x 128, (P, P, DN), 1e4 charges + N(0, 1e-3), FP32 MFMA, tol 1e-10
     eta = synth.charge_field((128, 256, 256), seed=2)
     u, res, hist, rc = _solve(eta, ("P", "P", "DN"), prec="f32", tol=1e-10)
     err = rel(u, oracle_solve(eta, ("P", "P", "DN")))
-    print("cfg2", res[0], err)
+    print("256x256x128", res[0], err)
     assert rc == 0 and err <= 1e-10
 
 
