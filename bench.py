@@ -60,6 +60,111 @@ WORKLOADS = {
 }
 
 
+# ------------------------------------------------------- HBM traffic record ----
+# Measured HBM bytes per launch come from two rocprofv3 counter runs of this
+# script (FETCH_SIZE, then WRITE_SIZE, with --copy-calibration), turned into a
+# record under profiles/ by --ingest-traffic.  Both counters are scaled by
+# what they read for the calibration copy of known size.  The record carries
+# a digest of the kernel sources; once a kernel has changed, traffic is null.
+KERNEL_SOURCES = ("kp_modeprod.hip", "kp_vector.hip", "kp_common.h", "kp_internal.h")
+VEC_KERNELS = {"stencil_dot": "kp::k_zm<0>", "update_ur": "kp::k_zm<1>",
+               "dot_rz": "kp::k_dot_rz", "update_p": "kp::k_update_p"}
+PRODUCT_ORDER = {3: ("modeprod_x_fwd", "modeprod_y_fwd", "modeprod_z_fwd", "modeprod_x_bwd",
+                     "modeprod_y_bwd", "modeprod_z_bwd"),
+                 2: ("modeprod_x_fwd", "modeprod_y_fwd", "modeprod_x_bwd", "modeprod_y_bwd")}
+
+
+def traffic_path(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2501_03377_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def launch_identity(cls, prec, grid, batch, tuning):
+    """The profiler's name (and, for mode products, total threads) of the
+    kernel that a class launches with the given tile choices."""
+    if cls in VEC_KERNELS:
+        return VEC_KERNELS[cls]
+    from paper_2501_03377_amd.kpcg import kp_tile_shape, PREC
+    nx, ny, nz = grid
+    dim = 3 if nz > 1 else 2
+    q = PRODUCT_ORDER[dim].index(cls)
+    K = grid["xyz".index(cls.split("_")[1])]
+    rows = nx * ny * nz // K
+    tc = {"f64": "double", "f32": "float", "bf16": "__bf16"}[prec]
+    ti = "double" if q == 0 else tc
+    to = "double" if q == 2 * dim - 1 else tc
+    vec = K % (8 if prec == "bf16" else 4) == 0
+    if vec:
+        rc, (wn, wm, wc) = kp_tile_shape(tuning[q], PREC[prec])
+        if rc != 0:
+            return None
+    else:
+        wn, wm, wc = 4, 2, 2
+    blocks = -(-rows // (64 * wm)) * -(-K // (16 * wn * wc)) * batch
+    pid = {"f64": 0, "f32": 1, "bf16": 2}[prec]
+    return (f"kp::mp_kernel<{pid}, {ti}, {to}, {wn}, {wm}, {wc}, {'true' if vec else 'false'}>"
+            f"|{blocks * 256 * wc}")
+
+
+def ingest_traffic(workload, fetch_dir, write_dir, command):
+    """Averages FETCH_SIZE and WRITE_SIZE per kernel over the dispatches of two
+    counter runs and writes the traffic record of the workload."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        acc, copy_max = {}, 0.0
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                copy_max = max(copy_max, v)
+                continue
+            key = f"{name}|{r['Grid_Size']}" if "mp_kernel" in name else name
+            t = acc.setdefault(key, [0.0, 0])
+            t[0] += v
+            t[1] += 1
+        return {k: t[0] / t[1] for k, t in acc.items()}, copy_max
+
+    fetch, copy_fetch = read(fetch_dir, "FETCH_SIZE")
+    write, copy_write = read(write_dir, "WRITE_SIZE")
+    rec = {"workload": workload, "digest": kernel_digest(), "command": command,
+           "copy_bytes": COPY_CAL_BYTES, "copy_fetch_kib": copy_fetch, "copy_write_kib": copy_write,
+           "kernels": {k: {"fetch_kib": fetch[k], "write_kib": write.get(k)} for k in sorted(fetch)}}
+    with open(traffic_path(workload), "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
+def measured_traffic(workload, identity):
+    """HBM bytes per launch of a kernel from the workload's traffic record, or
+    None when there is no record, the kernel is not in it or has changed."""
+    try:
+        with open(traffic_path(workload)) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = rec["kernels"].get(identity) if identity else None
+    if k is None or rec.get("digest") != kernel_digest() or k.get("write_kib") is None:
+        return None
+    if not rec["copy_fetch_kib"] or not rec["copy_write_kib"]:
+        return None
+    return (k["fetch_kib"] * rec["copy_bytes"] / rec["copy_fetch_kib"]
+            + k["write_kib"] * rec["copy_bytes"] / rec["copy_write_kib"])
+
+
 def log(msg):
     """Progress on stderr (stdout carries only the JSON line)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -178,10 +283,18 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison runs in the other precisions (for profiler runs)")
+    ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "workload into its traffic record under profiles/, then exit")
+    ap.add_argument("--ingest-command", default="", help="the profiler command, for the record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB three times, the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     args = ap.parse_args()
+    if args.ingest_traffic:
+        rec = ingest_traffic(args.workload, *args.ingest_traffic, args.ingest_command)
+        print(f"wrote {traffic_path(args.workload)}: {len(rec['kernels'])} kernels")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent solves shard across GPUs without communication).", file=sys.stderr)
@@ -253,12 +366,20 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     kind, _ = solve_work(dom, wl["grid"], res)
     d = kernels[dom]
+    ident = launch_identity(dom, prec, wl["grid"], batch, m["tuning"])
+    traffic = measured_traffic(args.workload, ident)
     if kind == "flop":
         roof = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": PEAK[prec],
-                "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": None, "kernel": dom}
+                "unit": "TFLOP/s", "frac": d["frac_peak"], "traffic": traffic, "kernel": dom}
     else:
         roof = {"bound": "hbm", "achieved": d.get("GBs"), "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": d.get("frac_peak"), "traffic": None, "kernel": dom}
+                "unit": "GB/s", "frac": d.get("frac_peak"), "traffic": traffic, "kernel": dom}
+    roof["launch"] = ident
+    if traffic is not None:
+        kind_, work = solve_work(dom, wl["grid"], res, prec == "bf16")
+        if kind_ == "byte":
+            per_launch = work * steps / d["launches"]
+            roof["traffic_over_algorithmic"] = round(traffic / per_launch, 3)
 
     its = [r["iterations"] for r in res]
     out = {

@@ -186,6 +186,14 @@ int kp_plan_autotune(kp_plan* plan, int batch, int reps, int* chosen);
  * KP_EINVAL for unknown ids), e.g. from a cache of earlier autotune runs. */
 int kp_plan_get_tuning(const kp_plan* plan, int* cfg, int n);
 int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
+/* Shape of tile configuration `id` for precision `prec` (kp_prec): column
+ * fragments per wave (wn), row fragments per wave (wm) and column wave groups
+ * (wc) of 16 x 16; a block has 4*wc waves and covers 64*wm rows and
+ * 16*wn*wc columns of the GEMM.  Host only, no GPU needed.  Returns KP_OK, or
+ * KP_EINVAL if the id is unknown or not compiled for that precision.  A
+ * product whose contracted length is not a multiple of 4 (8 in BF16) runs
+ * one fixed shape (wn 4, wm 2, wc 2) whatever the choice. */
+int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
 
 /* Per-kernel timing (the library's tracing facility).  When enabled, every
  * kernel launch of the plan is bracketed by HIP events on the plan's stream

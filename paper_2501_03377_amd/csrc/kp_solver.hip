@@ -624,6 +624,13 @@ int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
   return 2 * p->g.dim;
 }
 
+int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
+  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_BF16) return KP_EINVAL;
+  if (!mp_config_allowed(id, prec)) return KP_EINVAL;
+  mp_config(id, wn, wm, wc);
+  return KP_OK;
+}
+
 int kp_plan_set_tuning(kp_plan* p, const int* cfg, int n) {
   if (!p || !cfg || n != 2 * p->g.dim) return KP_EINVAL;
   for (int q = 0; q < n; ++q)

@@ -38,6 +38,7 @@ EXPORTS = (
     "kp_apply_laplacian", "kp_apply_pinv", "kp_solve", "kp_strerror", "kp_version",
     "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
     "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
+    "kp_tile_shape",
 )
 KERNEL_CLASSES = 14
 
@@ -91,6 +92,8 @@ def _load():
         "kp_plan_get_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_set_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_graph_count": (i, [vp]),
+        "kp_tile_shape": (i, [i, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -204,6 +207,14 @@ def kp_plan_set_tuning(handle, cfg):
 
 def kp_plan_graph_count(handle):
     return _lib.kp_plan_graph_count(handle)
+
+
+def kp_tile_shape(cfg_id, prec):
+    """(status, (wn, wm, wc)) of a tile configuration for a precision code."""
+    wn, wm, wc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    rc = _lib.kp_tile_shape(int(cfg_id), int(prec), ctypes.byref(wn), ctypes.byref(wm),
+                            ctypes.byref(wc))
+    return rc, (wn.value, wm.value, wc.value)
 
 
 # ------------------------------------------------------------ torch layer ----
