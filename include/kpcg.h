@@ -215,6 +215,79 @@ const char* kp_kernel_class_name(int cls);
  * turned out to be unavailable (solves then launch kernels directly). */
 int kp_plan_graph_count(const kp_plan* plan);
 
+/* ------------------------------------------------------------ serving ----
+ * A request server on one GPU for streams of independent solves of mixed
+ * grids, boundary conditions and tolerances (the serving layer is this
+ * library's, not the paper's; every request is one Algorithm 1 solve).  It
+ * keeps a cache of plans (the packed eigenbases and
+ * eigenvalues of Algs. 4-5, per grid, boundary triple and precision) under an
+ * HBM budget, admits a request only when its plan and workspace fit (evicting
+ * idle plans least recently used first), and runs `workers` host threads,
+ * each with its own HIP stream.  A worker that becomes free takes the oldest
+ * queued request together with every queued request of the same plan,
+ * tolerance, iteration limit and flags, up to `max_batch`, and solves them as
+ * one batch with kp_solve (continuous batching at solve granularity: a slot
+ * is refilled as soon as its previous batch completes).  Batched and single
+ * solves give bitwise identical results.
+ *
+ * Timestamps are seconds on the server's monotonic clock (kp_server_now). */
+typedef struct kp_server kp_server;   /* opaque */
+
+enum kp_mem { KP_MEM_DEVICE = 0, KP_MEM_HOST = 1 };
+
+typedef struct {
+  int64_t id;             /* caller's tag, returned in the completion */
+  int nx, ny, nz;         /* grid; nz = 1 for 2D */
+  int bc[3];              /* kp_bc per axis */
+  int prec;               /* kp_prec of the preconditioner */
+  double tol;             /* stopping tolerance, as kp_solve */
+  int max_iter;           /* as kp_solve */
+  int flags;              /* as kp_solve (KP_FLAG_NO_GRAPH ignored) */
+  int mem;                /* kp_mem: where eta and u live */
+  const double* eta;      /* nx*ny*nz doubles; must stay valid and unchanged
+                             until the request's completion is returned */
+  double* u;              /* nx*ny*nz doubles written before completion, or
+                             NULL to discard the solution */
+} kp_request;
+
+typedef struct {
+  int64_t id;
+  int32_t status;         /* kp_status of this right-hand side */
+  int32_t iterations;
+  int32_t batch;          /* size of the batch it was solved in */
+  int32_t worker;
+  double rel_res, true_rel_res, err_est;
+  double t_submit, t_start, t_end;   /* server clock, seconds */
+} kp_completion;
+
+typedef struct {
+  int64_t submitted, completed, batches, plans_created, plans_evicted, rejected;
+  int32_t plans_cached, queued;
+  size_t hbm_used, hbm_high_water, hbm_budget;
+} kp_server_stats;
+
+/* Starts a server on the current HIP device.  hbm_budget: bytes the server
+ * may hold in plans, workspaces and batch staging buffers (0 = no limit);
+ * workers >= 1 host threads; max_batch >= 1 right-hand sides per batch.
+ * Returns KP_OK, KP_EINVAL, KP_ENOMEM or KP_EHIP. */
+int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_batch);
+/* Queues a request (the descriptor is copied; eta and u are used later, see
+ * kp_request).  Never blocks on the GPU.  Returns KP_OK or KP_EINVAL (bad
+ * grid, boundary code, precision, tolerance, flags or null eta). */
+int kp_server_submit(kp_server* srv, const kp_request* req);
+/* Moves up to `max` completions to `out` (host array), waiting up to
+ * timeout_s seconds for the first one; returns how many (0 on timeout), or
+ * KP_EINVAL.  A request the budget can never hold completes with status
+ * KP_ENOMEM. */
+int kp_server_poll(kp_server* srv, kp_completion* out, int max, double timeout_s);
+/* Seconds on the server's clock. */
+double kp_server_now(const kp_server* srv);
+/* Counters and HBM use (out: host).  Returns KP_OK or KP_EINVAL. */
+int kp_server_stats_get(kp_server* srv, kp_server_stats* out);
+/* Finishes every queued request, stops the workers and frees every plan and
+ * buffer; completions not polled are dropped. */
+void kp_server_destroy(kp_server* srv);
+
 /* Human-readable name of a status code. */
 const char* kp_strerror(int status);
 

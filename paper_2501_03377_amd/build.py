@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libkpcg.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("KPCG_ARCH", "gfx950")
 
-SOURCES = ["kp_basis.cpp", "kp_vector.hip", "kp_modeprod.hip", "kp_solver.hip"]
+SOURCES = ["kp_basis.cpp", "kp_vector.hip", "kp_modeprod.hip", "kp_solver.hip", "kp_server.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # never emit packed FP32 arithmetic (v_pk_*_f32)
@@ -49,7 +49,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

@@ -1,0 +1,398 @@
+// Request server: a plan cache under an HBM budget, admission control and
+// worker threads that batch queued solves of the same plan (kp_server_* in
+// kpcg.h).  Every solve is kp_solve, i.e. Algorithm 1 with the
+// pseudoinverse preconditioner of Algs. 4-7; this file only schedules them.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/kpcg.h"
+
+namespace {
+
+struct PlanKey {
+  int nx, ny, nz, bc[3], prec;
+  bool operator==(const PlanKey& o) const {
+    return nx == o.nx && ny == o.ny && nz == o.nz && bc[0] == o.bc[0] && bc[1] == o.bc[1] &&
+           bc[2] == o.bc[2] && prec == o.prec;
+  }
+};
+
+PlanKey key_of(const kp_request& r) {
+  PlanKey k{r.nx, r.ny, r.nz, {r.bc[0], r.bc[1], r.nz > 1 ? r.bc[2] : 0}, r.prec};
+  return k;
+}
+
+// Requests that may share one kp_solve call.
+bool same_batch(const kp_request& a, const kp_request& b) {
+  return key_of(a) == key_of(b) && a.tol == b.tol && a.max_iter == b.max_iter &&
+         a.flags == b.flags;
+}
+
+struct Pending {
+  kp_request r;
+  double t_submit;
+};
+
+struct PlanEntry {
+  PlanKey key;
+  kp_plan* plan = nullptr;
+  bool busy = false;
+  uint64_t last = 0;     // use tick, for LRU eviction
+  size_t bytes = 0;      // resident operators + workspace at max_batch
+};
+
+struct Worker {
+  std::thread th;
+  hipStream_t stream = nullptr;
+  double* stage = nullptr;    // device: eta batch then u batch
+  size_t stage_bytes = 0;
+  std::vector<kp_result> res;
+};
+
+}  // namespace
+
+struct kp_server {
+  int device = 0;
+  size_t budget = 0;
+  int max_batch = 1;
+  std::chrono::steady_clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work;    // queue changed, memory freed, or stop
+  std::condition_variable cv_done;    // completions available
+  std::deque<Pending> queue;
+  std::deque<kp_completion> done;
+  std::vector<PlanEntry*> plans;
+  std::vector<Worker> workers;
+  size_t used = 0, high = 0;
+  int running = 0;        // workers holding a plan for a batch
+  uint64_t tick = 0;
+  kp_server_stats st{};
+  bool stop = false;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+size_t vec_bytes(const kp_request& r) { return (size_t)r.nx * r.ny * r.nz * sizeof(double); }
+
+void complete(kp_server* s, const Pending& p, int status, const kp_result* res, int batch,
+              int worker, double t_start, double t_end) {
+  kp_completion c{};
+  c.id = p.r.id;
+  c.status = status;
+  c.batch = batch;
+  c.worker = worker;
+  c.t_submit = p.t_submit;
+  c.t_start = t_start;
+  c.t_end = t_end;
+  if (res) {
+    c.iterations = res->iterations;
+    c.rel_res = res->rel_res;
+    c.true_rel_res = res->true_rel_res;
+    c.err_est = res->err_est;
+  }
+  s->done.push_back(c);
+  s->st.completed += 1;
+  if (status == KP_ENOMEM) s->st.rejected += 1;
+}
+
+void account(kp_server* s, long long delta) {
+  s->used = (size_t)((long long)s->used + delta);
+  s->high = std::max(s->high, s->used);
+}
+
+// Frees idle plans, least recently used first, until `need` more bytes fit the
+// budget.  Called with the lock held; returns the plans to destroy (after
+// unlocking) or sets *fits = false.
+std::vector<kp_plan*> make_room(kp_server* s, size_t need, bool* fits) {
+  std::vector<kp_plan*> victims;
+  *fits = true;
+  if (s->budget == 0) return victims;
+  while (s->used + need > s->budget) {
+    PlanEntry* lru = nullptr;
+    for (PlanEntry* e : s->plans)
+      if (!e->busy && (!lru || e->last < lru->last)) lru = e;
+    if (!lru) { *fits = false; break; }
+    victims.push_back(lru->plan);
+    account(s, -(long long)lru->bytes);
+    s->plans.erase(std::find(s->plans.begin(), s->plans.end(), lru));
+    delete lru;
+    s->st.plans_evicted += 1;
+  }
+  return victims;
+}
+
+void destroy_plans(std::vector<kp_plan*>& v) {
+  for (kp_plan* p : v) kp_plan_destroy(p);
+  v.clear();
+}
+
+void worker_main(kp_server* s, int w) {
+  (void)hipSetDevice(s->device);
+  Worker& me = s->workers[w];
+  me.res.resize(s->max_batch);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+    if (s->queue.empty()) break;   // stopping and drained
+
+    // the oldest request and every queued request that can share its solve
+    std::vector<Pending> batch;
+    batch.push_back(s->queue.front());
+    s->queue.pop_front();
+    for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
+      if (same_batch(it->r, batch[0].r)) {
+        batch.push_back(*it);
+        it = s->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    const int b = (int)batch.size();
+    const kp_request& r0 = batch[0].r;
+    const PlanKey key = key_of(r0);
+    const size_t vb = vec_bytes(r0);
+    const size_t stage_need = 2 * vb * (size_t)s->max_batch;
+
+    // acquire an idle plan of this key, or make one within the budget
+    PlanEntry* entry = nullptr;
+    std::vector<kp_plan*> victims;
+    int fail = KP_OK;
+    for (;;) {
+      for (PlanEntry* e : s->plans)
+        if (!e->busy && e->key == key) { entry = e; break; }
+      if (entry) entry->busy = true;   // not evictable while we make room
+      size_t need = me.stage_bytes >= stage_need ? 0 : stage_need - me.stage_bytes;
+      kp_plan* fresh = nullptr;
+      size_t fresh_bytes = 0;
+      if (!entry) {
+        lk.unlock();
+        destroy_plans(victims);
+        int rc = kp_plan_create(&fresh, key.nx, key.ny, key.nz, key.bc, key.prec, s->max_batch,
+                                me.stream);
+        if (rc == KP_OK)
+          fresh_bytes = kp_plan_resident_bytes(fresh) + kp_plan_workspace_bytes(fresh, s->max_batch);
+        lk.lock();
+        if (rc != KP_OK) { fail = rc; break; }
+        need += fresh_bytes;
+      }
+      bool fits = false;
+      std::vector<kp_plan*> v = make_room(s, need, &fits);
+      victims.insert(victims.end(), v.begin(), v.end());
+      if (fits) {
+        if (fresh) {
+          entry = new PlanEntry();
+          entry->key = key;
+          entry->plan = fresh;
+          entry->bytes = fresh_bytes;
+          entry->busy = true;
+          s->plans.push_back(entry);
+          account(s, (long long)fresh_bytes);
+          s->st.plans_created += 1;
+        }
+        if (me.stage_bytes < stage_need) account(s, (long long)(stage_need - me.stage_bytes));
+        break;
+      }
+      // does not fit: wait until a running batch releases its plan (which
+      // makes it evictable), or reject when no batch is running
+      if (entry) entry->busy = false;
+      entry = nullptr;
+      if (fresh) {
+        lk.unlock();
+        kp_plan_destroy(fresh);
+        lk.lock();
+      }
+      if (s->running == 0) { fail = KP_ENOMEM; break; }
+      s->cv_work.wait(lk);
+    }
+    if (fail != KP_OK) {
+      lk.unlock();
+      destroy_plans(victims);
+      lk.lock();
+      const double t = s->now();
+      for (const Pending& p : batch) complete(s, p, fail, nullptr, b, w, t, t);
+      s->cv_done.notify_all();
+      s->cv_work.notify_all();
+      continue;
+    }
+    entry->last = ++s->tick;
+    s->running += 1;
+    s->st.batches += 1;
+    lk.unlock();
+    destroy_plans(victims);
+
+    // ---- run the batch on this worker's stream (no lock held) ----
+    const double t_start = s->now();
+    int rc = KP_OK;
+    if (me.stage_bytes < stage_need) {
+      if (me.stage) (void)hipFree(me.stage);
+      me.stage = nullptr;
+      me.stage_bytes = 0;
+      if (hipMalloc((void**)&me.stage, stage_need) == hipSuccess) me.stage_bytes = stage_need;
+      else rc = KP_ENOMEM;
+    }
+    const size_t n = vb / sizeof(double);
+    double* eta_b = me.stage;
+    double* u_b = me.stage + n * (size_t)s->max_batch;
+    const double* eta = eta_b;
+    if (rc == KP_OK) {
+      kp_plan_set_stream(entry->plan, me.stream);
+      if (b == 1 && r0.mem == KP_MEM_DEVICE) {
+        eta = r0.eta;      // read in place
+      } else {
+        for (int i = 0; i < b && rc == KP_OK; ++i) {
+          const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyHostToDevice
+                                                                : hipMemcpyDeviceToDevice;
+          if (hipMemcpyAsync(eta_b + n * i, batch[i].r.eta, vb, k, me.stream) != hipSuccess)
+            rc = KP_EHIP;
+        }
+      }
+    }
+    if (rc == KP_OK) {
+      // the solution always goes to the worker's buffer, so captured
+      // iteration graphs are reused from batch to batch
+      rc = kp_solve(entry->plan, eta, u_b, b, r0.tol, r0.max_iter, r0.flags & ~KP_FLAG_NO_GRAPH,
+                    me.res.data(), nullptr);
+      if (rc >= 0) {
+        for (int i = 0; i < b; ++i) {
+          if (!batch[i].r.u) continue;
+          const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyDeviceToHost
+                                                                : hipMemcpyDeviceToDevice;
+          if (hipMemcpyAsync(batch[i].r.u, u_b + n * i, vb, k, me.stream) != hipSuccess)
+            rc = KP_EHIP;
+        }
+        if (hipStreamSynchronize(me.stream) != hipSuccess) rc = KP_EHIP;
+      }
+    }
+    const double t_end = s->now();
+
+    lk.lock();
+    for (int i = 0; i < b; ++i) {
+      const bool per_rhs = rc >= 0;
+      complete(s, batch[i], per_rhs ? me.res[i].status : rc, per_rhs ? &me.res[i] : nullptr, b,
+               w, t_start, t_end);
+    }
+    entry->busy = false;
+    entry->last = ++s->tick;
+    s->running -= 1;
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
+}
+
+bool valid_request(const kp_request* r) {
+  if (!r || !r->eta) return false;
+  if (r->nx < 3 || r->ny < 3 || !(r->nz == 1 || r->nz >= 3)) return false;
+  if ((double)r->nx * r->ny * r->nz >= 2147483648.0) return false;
+  for (int a = 0; a < (r->nz > 1 ? 3 : 2); ++a)
+    if (r->bc[a] < KP_BC_P || r->bc[a] > KP_BC_ND) return false;
+  if (r->prec < KP_PREC_F64 || r->prec > KP_PREC_BF16) return false;
+  if (!(r->tol > 0.0) || !std::isfinite(r->tol)) return false;
+  if (r->max_iter < 1 || r->max_iter > 1000000) return false;
+  if (r->flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH))
+    return false;
+  if (r->mem != KP_MEM_DEVICE && r->mem != KP_MEM_HOST) return false;
+  if (r->mem == KP_MEM_DEVICE && (((uintptr_t)r->eta & 15u) || ((uintptr_t)r->u & 15u)))
+    return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_batch) {
+  if (!out || workers < 1 || workers > 64 || max_batch < 1 || max_batch > 65535) return KP_EINVAL;
+  *out = nullptr;
+  kp_server* s = new kp_server();
+  if (hipGetDevice(&s->device) != hipSuccess) { delete s; return KP_EHIP; }
+  s->budget = hbm_budget;
+  s->max_batch = max_batch;
+  s->t0 = std::chrono::steady_clock::now();
+  s->workers.resize(workers);
+  for (Worker& w : s->workers) {
+    if (hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking) != hipSuccess) {
+      for (Worker& v : s->workers)
+        if (v.stream) (void)hipStreamDestroy(v.stream);
+      delete s;
+      return KP_EHIP;
+    }
+  }
+  for (int i = 0; i < workers; ++i) s->workers[i].th = std::thread(worker_main, s, i);
+  *out = s;
+  return KP_OK;
+}
+
+int kp_server_submit(kp_server* s, const kp_request* r) {
+  if (!s || !valid_request(r)) return KP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return KP_EINVAL;
+    s->queue.push_back(Pending{*r, s->now()});
+    s->st.submitted += 1;
+  }
+  s->cv_work.notify_all();   // also wakes a worker waiting for memory; all re-check
+  return KP_OK;
+}
+
+int kp_server_poll(kp_server* s, kp_completion* out, int max, double timeout_s) {
+  if (!s || !out || max < 1 || !(timeout_s >= 0.0)) return KP_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && timeout_s > 0.0)
+    s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                        [&] { return !s->done.empty(); });
+  int n = 0;
+  while (n < max && !s->done.empty()) {
+    out[n++] = s->done.front();
+    s->done.pop_front();
+  }
+  return n;
+}
+
+double kp_server_now(const kp_server* s) { return s ? s->now() : 0.0; }
+
+int kp_server_stats_get(kp_server* s, kp_server_stats* out) {
+  if (!s || !out) return KP_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  out->plans_cached = (int32_t)s->plans.size();
+  out->queued = (int32_t)s->queue.size();
+  out->hbm_used = s->used;
+  out->hbm_high_water = s->high;
+  out->hbm_budget = s->budget;
+  return KP_OK;
+}
+
+void kp_server_destroy(kp_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (Worker& w : s->workers)
+    if (w.th.joinable()) w.th.join();
+  for (PlanEntry* e : s->plans) {
+    kp_plan_destroy(e->plan);
+    delete e;
+  }
+  for (Worker& w : s->workers) {
+    if (w.stage) (void)hipFree(w.stage);
+    if (w.stream) (void)hipStreamDestroy(w.stream);
+  }
+  delete s;
+}
+
+}  // extern "C"

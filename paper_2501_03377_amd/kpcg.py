@@ -38,7 +38,8 @@ EXPORTS = (
     "kp_apply_laplacian", "kp_apply_pinv", "kp_solve", "kp_strerror", "kp_version",
     "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
     "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
-    "kp_tile_shape",
+    "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
+    "kp_server_stats_get", "kp_server_destroy",
 )
 KERNEL_CLASSES = 14
 
@@ -63,6 +64,57 @@ class KpError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
         super().__init__(f"{where}: {kp_strerror(status)} ({status})")
+
+
+class KpRequest(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("bc", ctypes.c_int * 3),
+        ("prec", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("flags", ctypes.c_int),
+        ("mem", ctypes.c_int),
+        ("eta", ctypes.c_void_p),
+        ("u", ctypes.c_void_p),
+    ]
+
+
+class KpCompletion(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("worker", ctypes.c_int32),
+        ("rel_res", ctypes.c_double),
+        ("true_rel_res", ctypes.c_double),
+        ("err_est", ctypes.c_double),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_end", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class KpServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("batches", ctypes.c_int64), ("plans_created", ctypes.c_int64),
+        ("plans_evicted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+        ("plans_cached", ctypes.c_int32), ("queued", ctypes.c_int32),
+        ("hbm_used", ctypes.c_size_t), ("hbm_high_water", ctypes.c_size_t),
+        ("hbm_budget", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+KP_MEM_DEVICE, KP_MEM_HOST = 0, 1
 
 
 def _load():
@@ -94,6 +146,12 @@ def _load():
         "kp_plan_graph_count": (i, [vp]),
         "kp_tile_shape": (i, [i, i, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(ctypes.c_int)]),
+        "kp_server_create": (i, [ctypes.POINTER(vp), sz, i, i]),
+        "kp_server_submit": (i, [vp, ctypes.POINTER(KpRequest)]),
+        "kp_server_poll": (i, [vp, ctypes.POINTER(KpCompletion), i, d]),
+        "kp_server_now": (d, [vp]),
+        "kp_server_stats_get": (i, [vp, ctypes.POINTER(KpServerStats)]),
+        "kp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -215,6 +273,36 @@ def kp_tile_shape(cfg_id, prec):
     rc = _lib.kp_tile_shape(int(cfg_id), int(prec), ctypes.byref(wn), ctypes.byref(wm),
                             ctypes.byref(wc))
     return rc, (wn.value, wm.value, wc.value)
+
+
+def kp_server_create(hbm_budget, workers, max_batch):
+    handle = ctypes.c_void_p()
+    rc = _lib.kp_server_create(ctypes.byref(handle), int(hbm_budget), int(workers), int(max_batch))
+    return rc, handle
+
+
+def kp_server_submit(handle, req):
+    return _lib.kp_server_submit(handle, ctypes.byref(req))
+
+
+def kp_server_poll(handle, max_n, timeout_s):
+    out = (KpCompletion * max_n)()
+    n = _lib.kp_server_poll(handle, out, int(max_n), float(timeout_s))
+    return n, [out[k].as_dict() for k in range(max(n, 0))]
+
+
+def kp_server_now(handle):
+    return _lib.kp_server_now(handle)
+
+
+def kp_server_stats_get(handle):
+    st = KpServerStats()
+    rc = _lib.kp_server_stats_get(handle, ctypes.byref(st))
+    return rc, st.as_dict()
+
+
+def kp_server_destroy(handle):
+    _lib.kp_server_destroy(handle)
 
 
 # ------------------------------------------------------------ torch layer ----
@@ -360,3 +448,81 @@ class Plan:
         if rc < 0 and raise_on_error:
             raise KpError(rc, "kp_solve")
         return u, [r.as_dict() for r in results], hist, rc
+
+
+class Server:
+    """Request server (kp_server_*): plan cache under an HBM budget, worker
+    threads with their own streams, batching of queued requests that share a
+    plan.  eta / u are float64 CUDA tensors (device requests) or numpy arrays
+    (host requests) shaped (nz, ny, nx) or (ny, nx); they are kept alive here
+    until their completion has been polled."""
+
+    def __init__(self, hbm_budget=0, workers=4, max_batch=8):
+        _torch().cuda.current_device()
+        rc, self._h = kp_server_create(hbm_budget, workers, max_batch)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_server_create")
+        self._live = {}
+
+    def submit(self, req_id, eta, bcs, tol=1e-10, prec="f32", max_iter=50, flags=0, u=None):
+        torch = _torch()
+        shape = tuple(eta.shape)
+        if len(shape) == 3:
+            nz, ny, nx = shape
+        elif len(shape) == 2:
+            (ny, nx), nz = shape, 1
+        else:
+            raise ValueError("eta must be (nz, ny, nx) or (ny, nx)")
+        on_dev = isinstance(eta, torch.Tensor)
+        if on_dev:
+            if eta.dtype != torch.float64 or not eta.is_cuda or not eta.is_contiguous():
+                raise ValueError("device eta must be a contiguous float64 CUDA tensor")
+            if u is not None and (tuple(u.shape) != shape or u.dtype != torch.float64
+                                  or not u.is_cuda or not u.is_contiguous()):
+                raise ValueError("u must match eta")
+            eptr, uptr = eta.data_ptr(), (u.data_ptr() if u is not None else None)
+        else:
+            eta = np.ascontiguousarray(eta, dtype=np.float64)
+            if u is not None and (u.shape != shape or u.dtype != np.float64
+                                  or not u.flags["C_CONTIGUOUS"]):
+                raise ValueError("u must match eta")
+            eptr, uptr = eta.ctypes.data, (u.ctypes.data if u is not None else None)
+        bcs = tuple(bcs) + ("D",) * (3 - len(bcs))
+        req = KpRequest(id=int(req_id), nx=nx, ny=ny, nz=nz,
+                        bc=(ctypes.c_int * 3)(*[BC[b] for b in bcs]), prec=PREC[prec],
+                        tol=float(tol), max_iter=int(max_iter), flags=int(flags),
+                        mem=KP_MEM_DEVICE if on_dev else KP_MEM_HOST, eta=eptr, u=uptr)
+        self._live[int(req_id)] = (eta, u)
+        rc = kp_server_submit(self._h, req)
+        if rc != KP_OK:
+            self._live.pop(int(req_id), None)
+            raise KpError(rc, "kp_server_submit")
+
+    def poll(self, max_n=256, timeout=0.1):
+        n, done = kp_server_poll(self._h, max_n, timeout)
+        if n < 0:
+            raise KpError(n, "kp_server_poll")
+        for c in done:
+            self._live.pop(c["id"], None)
+        return done
+
+    def now(self):
+        return kp_server_now(self._h)
+
+    def stats(self):
+        rc, st = kp_server_stats_get(self._h)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_server_stats_get")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            kp_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

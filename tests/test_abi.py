@@ -71,3 +71,36 @@ def test_smallest_eigenvalue_accuracy():
     _, lam = kp_basis_1d(512, "DN")
     exact = 4 * math.sin(math.pi / (2 * (2 * 512 + 1))) ** 2
     assert abs(lam[0] - exact) / exact < 1e-15
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors of the ABI structs have the C compiler's offsets
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2501_03377_amd import kpcg
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    structs = {"kp_result": kpcg.KpResult, "kp_request": kpcg.KpRequest,
+               "kp_completion": kpcg.KpCompletion, "kp_server_stats": kpcg.KpServerStats}
+    lines = ['#include <cstdio>', '#include <cstddef>',
+             f'#include "{os.path.join(ROOT, "include", "kpcg.h")}"', 'int main() {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cxx, "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)

@@ -1,0 +1,113 @@
+"""The request server (kp_server_*): results against the oracle, bitwise
+equality of batched and solo solves, HBM admission with eviction, and
+rejection of requests the budget cannot hold."""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import oracle_solve, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _drain(srv, n, timeout=60.0):
+    import time
+    done, t0 = {}, time.time()
+    while len(done) < n:
+        for c in srv.poll(max_n=64, timeout=0.5):
+            done[c["id"]] = c
+        assert time.time() - t0 < timeout, f"only {len(done)} of {n} completions"
+    return done
+
+
+def test_server_results_match_oracle():
+    import torch
+    from paper_2501_03377_amd import Server
+    cases = [((12, 20, 24), ("P", "P", "DN"), "f64", 1e-10, "dev"),
+             ((16, 18, 20), ("N", "N", "N"), "f32", 1e-10, "host"),
+             ((20, 16), ("D", "N"), "f64", 1e-12, "dev"),
+             ((10, 12, 14), ("D", "ND", "P"), "bf16", 1e-8, "host"),
+             ((24, 24, 24), ("DN", "D", "N"), "f32", 1e-8, "dev")]
+    srv = Server(hbm_budget=0, workers=2, max_batch=4)
+    try:
+        outs, etas = {}, {}
+        for k, (shape, bcs, prec, tol, where) in enumerate(cases):
+            eta = synth.charge_field(shape, ncharges=50, seed=900 + k)
+            etas[k] = eta
+            if where == "dev":
+                e, u = to_dev(eta), torch.empty(shape, dtype=torch.float64, device="cuda")
+            else:
+                e, u = eta, np.empty(shape)
+            outs[k] = u
+            srv.submit(k, e, bcs, tol=tol, prec=prec, u=u,
+                       flags=2 if prec == "bf16" else 0)   # flexible beta for BF16
+        done = _drain(srv, len(cases))
+        for k, (shape, bcs, prec, tol, where) in enumerate(cases):
+            c = done[k]
+            assert c["status"] == 0, c
+            u = to_host(outs[k]) if where == "dev" else outs[k]
+            err = rel(u, oracle_solve(etas[k], bcs))
+            assert err <= (1e-10 if prec == "f64" else tol), (k, err, c)
+            assert c["t_submit"] <= c["t_start"] <= c["t_end"]
+        st = srv.stats()
+        assert st["completed"] == len(cases) and st["plans_created"] == len(cases)
+    finally:
+        srv.close()
+
+
+def test_server_batches_match_solo_bitwise():
+    # one worker, requests queued while it is busy: they are solved in
+    # batches; the same requests solved one at a time give identical bits
+    import torch
+    from paper_2501_03377_amd import Server
+    shape, bcs = (16, 20, 24), ("P", "N", "D")
+    etas = [synth.charge_field(shape, ncharges=80, seed=1200 + k) for k in range(7)]
+
+    def run(together):
+        srv = Server(hbm_budget=0, workers=1, max_batch=4)
+        us, batches = [], []
+        try:
+            for k, eta in enumerate(etas):
+                u = torch.empty(shape, dtype=torch.float64, device="cuda")
+                us.append(u)
+                srv.submit(k, to_dev(eta), bcs, tol=1e-10, prec="f32", u=u)
+                if not together:
+                    batches.append(_drain(srv, 1)[k]["batch"])
+            if together:
+                batches = [c["batch"] for c in _drain(srv, len(etas)).values()]
+            return [to_host(u) for u in us], batches
+        finally:
+            srv.close()
+
+    mixed, b_mixed = run(True)
+    solo, b_solo = run(False)
+    assert max(b_mixed) > 1 and max(b_solo) == 1
+    for a, b in zip(mixed, solo):
+        assert np.array_equal(a, b)
+
+
+def test_server_evicts_idle_plans_and_rejects_oversize():
+    from paper_2501_03377_amd import Server
+    from paper_2501_03377_amd import Plan
+    shape = (24, 24, 24)
+    probe = Plan(24, 24, 24, ("P", "P", "P"), prec="f32", max_batch=2)
+    one = probe.resident_bytes + probe.workspace_bytes + 2 * 2 * 8 * 24 ** 3
+    probe.close()
+    # room for one plan of this size and its staging, not for two
+    srv = Server(hbm_budget=int(one * 1.5), workers=1, max_batch=2)
+    try:
+        keys = [("P", "P", "P"), ("D", "D", "D"), ("N", "N", "N"), ("P", "P", "P")]
+        for k, bcs in enumerate(keys):
+            srv.submit(k, synth.charge_field(shape, ncharges=40, seed=1300 + k), bcs, tol=1e-8)
+            c = _drain(srv, 1)[k]
+            assert c["status"] == 0, c
+        st = srv.stats()
+        assert st["plans_evicted"] >= 3 and st["plans_cached"] == 1
+        assert st["hbm_high_water"] <= st["hbm_budget"]
+        # a grid whose plan alone exceeds the budget completes with KP_ENOMEM
+        srv.submit(99, synth.charge_field((96, 96, 96), ncharges=40, seed=1399), ("P",) * 3)
+        c = _drain(srv, 1)[99]
+        assert c["status"] == -2 and srv.stats()["rejected"] == 1
+    finally:
+        srv.close()
