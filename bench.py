@@ -272,10 +272,188 @@ def cpu_baseline(wl, eta, budget_s=25.0):
     }
 
 
+def serving_bench(args):
+    """Request-stream benchmark of the server (one JSON line).
+
+    2000 seeded requests (synth.serving_requests): grid uniform from five
+    sizes, one boundary condition per axis from {P, D, N, DN}, tol from
+    {1e-8, 1e-10}, inter-arrival gaps exponential.  Each request's field is
+    one of 8 charge fields per grid size held in HBM before timing (10^4
+    charges + N(0, 1e-3) noise, zero mean).  HBM budget 200 GB for plans,
+    workspaces and staging.  Phases: closed loop (every request queued at
+    once) gives the saturated throughput mu; open loop at 0.8 mu (Poisson
+    arrivals, latency = completion - arrival on the server clock) gives
+    p50 / p99, also at 0.5, 1.0 and 1.2 mu; 50 sampled requests are replayed
+    one at a time (alone) and compared with their in-mix results and
+    latencies; the same closed loop with the FP64 preconditioner."""
+    import threading
+    import torch
+    import synth
+    from paper_2501_03377_amd import Server, KP_FLAG_FLEX_BETA
+
+    prec = args.prec or "f32"
+    count = args.requests
+    reqs = synth.serving_requests(count=count, seed=4)
+    grids = synth.SERVING_GRIDS
+    torch.cuda.set_device(0)
+    log(f"serving: {count} requests, generating 8 fields per grid size")
+    pools = {}
+    for gi, (nx, ny, nz) in enumerate(grids):
+        pools[(nx, ny, nz)] = [
+            torch.from_numpy(synth.charge_field((nz, ny, nx), ncharges=10_000, noise_std=1e-3,
+                                                seed=40_000 + 8 * gi + k)).cuda()
+            for k in range(8)]
+    rng = np.random.default_rng(44)
+    sample = sorted(rng.choice(count, size=min(50, count), replace=False).tolist())
+    flags = KP_FLAG_FLEX_BETA if prec == "bf16" else 0
+    budget = int(200e9)
+
+    def eta_of(r):
+        return pools[tuple(r["grid"])][r["field_seed"] % 8]
+
+    def drain(srv, n):
+        done = {}
+        while len(done) < n:
+            for c in srv.poll(max_n=512, timeout=1.0):
+                done[c["id"]] = c
+        return done
+
+    def closed_loop(srv, p, outs=None):
+        t0 = srv.now()
+        for r in reqs:
+            srv.submit(r["id"], eta_of(r), r["bcs"], tol=r["tol"], prec=p, flags=flags,
+                       u=(outs or {}).get(r["id"]))
+        done = drain(srv, len(reqs))
+        t1 = max(c["t_end"] for c in done.values())
+        return done, len(reqs) / (t1 - t0)
+
+    def open_loop(srv, p, rate, outs=None):
+        arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
+        t0 = srv.now() + 0.05
+
+        def submitter():
+            for r, ta in zip(reqs, arrivals):
+                delay = t0 + ta - srv.now()
+                if delay > 0:
+                    time.sleep(delay)
+                srv.submit(r["id"], eta_of(r), r["bcs"], tol=r["tol"], prec=p, flags=flags,
+                           u=(outs or {}).get(r["id"]))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = drain(srv, len(reqs))
+        th.join()
+        lat = np.array([c["t_end"] - c["t_submit"] for c in done.values()])
+        t_first = min(c["t_submit"] for c in done.values())
+        t_last = max(c["t_end"] for c in done.values())
+        return done, {"rate_offered": rate, "solves_per_s": len(reqs) / (t_last - t_first),
+                      "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                      "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                      "mean_batch": float(np.mean([c["batch"] for c in done.values()]))}
+
+    srv = Server(hbm_budget=budget, workers=args.workers, max_batch=args.max_batch)
+    try:
+        log("closed loop (cold plan cache)")
+        done_cold, mu_cold = closed_loop(srv, prec)
+        log("closed loop (warm plan cache)")
+        done_mu, mu = closed_loop(srv, prec)
+        bad = [c for c in done_mu.values() if c["status"] != 0]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed, first: {bad[0]}; "
+                               f"server: {srv.last_error()}")
+        outs = {i: torch.empty_like(eta_of(reqs[i])) for i in sample}
+        levels = {}
+        for frac in ([0.8] + ([0.5, 1.0, 1.2] if args.sweep else [])):
+            log(f"open loop at {frac} mu")
+            d, lv = open_loop(srv, prec, frac * mu, outs if frac == 0.8 else None)
+            levels[str(frac)] = lv
+            if frac == 0.8:
+                mix = d
+        mix_u = {i: outs[i].cpu().numpy() for i in sample}
+        log("alone replay of the sampled requests")
+        alone_lat, same = [], 0
+        for i in sample:
+            r = reqs[i]
+            u = torch.empty_like(eta_of(r))
+            srv.submit(i, eta_of(r), r["bcs"], tol=r["tol"], prec=prec, flags=flags, u=u)
+            c = drain(srv, 1)[i]
+            alone_lat.append(c["t_end"] - c["t_submit"])
+            same += int(np.array_equal(u.cpu().numpy(), mix_u[i]))
+        mix_lat = [mix[i]["t_end"] - mix[i]["t_submit"] for i in sample]
+        st = srv.stats()
+    finally:
+        srv.close()
+
+    comp = {}
+    if not args.no_compare:
+        log("closed loop, FP64 preconditioner")
+        srv = Server(hbm_budget=budget, workers=args.workers, max_batch=args.max_batch)
+        try:
+            closed_loop(srv, "f64")
+            _, mu64 = closed_loop(srv, "f64")
+            comp["f64"] = {"solves_per_s": mu64}
+        finally:
+            srv.close()
+
+    lv = levels["0.8"]
+    out = {
+        "metric": METRIC, "value": mu, "unit": "solves/s", "n_gpus": 1,
+        "steps": count, "warmup": count, "ms_per_step": 1e3 / mu, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16"}[prec], "data": "synthetic",
+        "config": {"workload": f"serving: {count} requests, grids {list(map(list, grids))}, "
+                               "BC per axis from P/D/N/DN, tol 1e-8 or 1e-10, Poisson arrivals, "
+                               f"HBM budget 200 GB, {prec.upper()} preconditioner; value = "
+                               "saturated closed-loop throughput (warm plan cache)",
+                   "workers": args.workers, "max_batch": args.max_batch},
+        "p50_ms": lv["p50_ms"], "p99_ms": lv["p99_ms"],
+        "serving": {"mu_cold": mu_cold, "mu": mu, "open_loop": levels,
+                    "hbm_high_water_GB": st["hbm_high_water"] / 1e9,
+                    "plans_created": st["plans_created"], "plans_evicted": st["plans_evicted"],
+                    "batches": st["batches"], "rejected": st["rejected"],
+                    "alone_vs_mix": {"requests": len(sample), "bitwise_equal": same,
+                                     "alone_p50_ms": float(np.median(alone_lat) * 1e3),
+                                     "mix_p50_ms": float(np.median(mix_lat) * 1e3)}},
+        "compare": comp,
+    }
+    if "f64" in comp:
+        out["speedup_vs_fp64"] = mu / comp["f64"]["solves_per_s"]
+    if not args.no_cpu_baseline:
+        # the oracle on the sampled requests, smallest grids first, within the budget
+        import oracle
+        from threadpoolctl import threadpool_info
+        log("oracle on a sample of the requests")
+        order = sorted(sample, key=lambda i: np.prod(reqs[i]["grid"]))
+        t_all, errs, n = time.perf_counter(), [], 0
+        for i in order:
+            r = reqs[i]
+            H = eta_of(r).cpu().numpy().T
+            res = oracle.pcg(H, r["bcs"], precond=oracle.PinvPreconditioner(H.shape, r["bcs"]))
+            sol = res.u.T
+            errs.append(float(np.linalg.norm(mix_u[i] - sol) / np.linalg.norm(sol)))
+            n += 1
+            if time.perf_counter() - t_all > 12.5:
+                break
+        dt = time.perf_counter() - t_all
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        out["cpu_baseline"] = {"value": n / dt, "unit": "solves/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"{n} of the 50 sampled requests, smallest grids first "
+                                         "(LAPACK eigh plan + Algorithm 1 to true residual "
+                                         "<= 1e-14, FP64 numpy)"}
+        out["rel_err_vs_oracle"] = max(errs)
+        out["rel_err_over_tol"] = max(e / reqs[i]["tol"] for e, i in zip(errs, order))
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="single256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="single256", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--requests", type=int, default=2000, help="serving: stream length")
+    ap.add_argument("--workers", type=int, default=4, help="serving: worker threads")
+    ap.add_argument("--max-batch", type=int, default=4, help="serving: largest batch")
+    ap.add_argument("--sweep", action="store_true", help="serving: also 0.5, 1.0, 1.2 mu")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default=None, choices=["f32", "f64", "bf16"])
@@ -299,6 +477,10 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent solves shard across GPUs without communication).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        serving_bench(args)
+        return
 
     import torch
     from paper_2501_03377_amd import Plan, KP_FLAG_FLEX_BETA

@@ -284,9 +284,18 @@ int kp_server_poll(kp_server* srv, kp_completion* out, int max, double timeout_s
 double kp_server_now(const kp_server* srv);
 /* Counters and HBM use (out: host).  Returns KP_OK or KP_EINVAL. */
 int kp_server_stats_get(kp_server* srv, kp_server_stats* out);
+/* Description of the most recent failed batch (the HIP call and error, or
+ * the failing step), "" if none.  Owned by the server, valid until the next
+ * call of this function on it. */
+const char* kp_server_last_error(kp_server* srv);
 /* Finishes every queued request, stops the workers and frees every plan and
  * buffer; completions not polled are dropped. */
 void kp_server_destroy(kp_server* srv);
+
+/* Text of the HIP call and error behind the last KP_EHIP (or allocation
+ * failure) returned to the calling host thread; "" if none.  The string is
+ * owned by the library and valid until the thread's next call. */
+const char* kp_last_error(void);
 
 /* Human-readable name of a status code. */
 const char* kp_strerror(int status);

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -15,6 +16,10 @@
 #include <vector>
 
 #include "../../include/kpcg.h"
+
+namespace kp {
+std::mutex& api_mutex();   // kp_solver.hip: serialises allocations with graph capture
+}
 
 namespace {
 
@@ -42,12 +47,17 @@ struct Pending {
   double t_submit;
 };
 
+// A plan instance belongs to one worker, which binds its own workspace to
+// it: a plan then keeps its captured graphs from batch to batch, and the
+// cache holds only the packed operators of each plan.
 struct PlanEntry {
   PlanKey key;
+  int owner = 0;         // worker
   kp_plan* plan = nullptr;
   bool busy = false;
   uint64_t last = 0;     // use tick, for LRU eviction
-  size_t bytes = 0;      // resident operators + workspace at max_batch
+  size_t bytes = 0;      // resident operators
+  int64_t ws_epoch = -1; // owner's workspace generation the plan is bound to
 };
 
 struct Worker {
@@ -55,6 +65,9 @@ struct Worker {
   hipStream_t stream = nullptr;
   double* stage = nullptr;    // device: eta batch then u batch
   size_t stage_bytes = 0;
+  void* ws = nullptr;         // solver workspace shared by this worker's plans
+  size_t ws_bytes = 0;
+  int64_t ws_epoch = 0;       // bumped whenever ws is reallocated
   std::vector<kp_result> res;
 };
 
@@ -77,6 +90,8 @@ struct kp_server {
   uint64_t tick = 0;
   kp_server_stats st{};
   bool stop = false;
+  char last_error[256] = "";      // most recent failed batch
+  char last_error_out[256] = "";  // copy handed to the caller
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -166,15 +181,15 @@ void worker_main(kp_server* s, int w) {
     const size_t vb = vec_bytes(r0);
     const size_t stage_need = 2 * vb * (size_t)s->max_batch;
 
-    // acquire an idle plan of this key, or make one within the budget
+    // acquire this worker's plan of this key, or make one within the budget
     PlanEntry* entry = nullptr;
     std::vector<kp_plan*> victims;
+    size_t ws_need = 0;
     int fail = KP_OK;
     for (;;) {
       for (PlanEntry* e : s->plans)
-        if (!e->busy && e->key == key) { entry = e; break; }
+        if (e->owner == w && e->key == key) { entry = e; break; }
       if (entry) entry->busy = true;   // not evictable while we make room
-      size_t need = me.stage_bytes >= stage_need ? 0 : stage_need - me.stage_bytes;
       kp_plan* fresh = nullptr;
       size_t fresh_bytes = 0;
       if (!entry) {
@@ -182,19 +197,30 @@ void worker_main(kp_server* s, int w) {
         destroy_plans(victims);
         int rc = kp_plan_create(&fresh, key.nx, key.ny, key.nz, key.bc, key.prec, s->max_batch,
                                 me.stream);
-        if (rc == KP_OK)
-          fresh_bytes = kp_plan_resident_bytes(fresh) + kp_plan_workspace_bytes(fresh, s->max_batch);
+        if (rc == KP_OK) {
+          fresh_bytes = kp_plan_resident_bytes(fresh);
+          ws_need = kp_plan_workspace_bytes(fresh, s->max_batch);
+        }
         lk.lock();
-        if (rc != KP_OK) { fail = rc; break; }
-        need += fresh_bytes;
+        if (rc != KP_OK) {
+          fail = rc;
+          snprintf(s->last_error, sizeof s->last_error, "kp_plan_create: status %d %s", rc,
+                   kp_last_error());
+          break;
+        }
+      } else {
+        ws_need = kp_plan_workspace_bytes(entry->plan, s->max_batch);
       }
+      const size_t grow = (me.stage_bytes < stage_need ? stage_need - me.stage_bytes : 0) +
+                          (me.ws_bytes < ws_need ? ws_need - me.ws_bytes : 0);
       bool fits = false;
-      std::vector<kp_plan*> v = make_room(s, need, &fits);
+      std::vector<kp_plan*> v = make_room(s, grow + fresh_bytes, &fits);
       victims.insert(victims.end(), v.begin(), v.end());
       if (fits) {
         if (fresh) {
           entry = new PlanEntry();
           entry->key = key;
+          entry->owner = w;
           entry->plan = fresh;
           entry->bytes = fresh_bytes;
           entry->busy = true;
@@ -202,7 +228,7 @@ void worker_main(kp_server* s, int w) {
           account(s, (long long)fresh_bytes);
           s->st.plans_created += 1;
         }
-        if (me.stage_bytes < stage_need) account(s, (long long)(stage_need - me.stage_bytes));
+        account(s, (long long)grow);   // the buffers grow before the solve
         break;
       }
       // does not fit: wait until a running batch releases its plan (which
@@ -236,12 +262,29 @@ void worker_main(kp_server* s, int w) {
     // ---- run the batch on this worker's stream (no lock held) ----
     const double t_start = s->now();
     int rc = KP_OK;
+    const char* failed = nullptr;   // failing step outside kp_solve
     if (me.stage_bytes < stage_need) {
+      std::lock_guard<std::mutex> alk(kp::api_mutex());
       if (me.stage) (void)hipFree(me.stage);
       me.stage = nullptr;
       me.stage_bytes = 0;
       if (hipMalloc((void**)&me.stage, stage_need) == hipSuccess) me.stage_bytes = stage_need;
-      else rc = KP_ENOMEM;
+      else { rc = KP_ENOMEM; failed = "hipMalloc of the batch staging buffer"; }
+    }
+    if (rc == KP_OK && me.ws_bytes < ws_need) {
+      std::lock_guard<std::mutex> alk(kp::api_mutex());
+      if (me.ws) (void)hipFree(me.ws);
+      me.ws = nullptr;
+      me.ws_bytes = 0;
+      me.ws_epoch += 1;
+      if (hipMalloc(&me.ws, ws_need) == hipSuccess) me.ws_bytes = ws_need;
+      else { rc = KP_ENOMEM; failed = "hipMalloc of the worker workspace"; }
+    }
+    if (rc == KP_OK && entry->ws_epoch != me.ws_epoch) {
+      // rebinding drops the plan's captured graphs (they point into the old buffer)
+      rc = kp_plan_set_workspace(entry->plan, me.ws, me.ws_bytes);
+      if (rc == KP_OK) entry->ws_epoch = me.ws_epoch;
+      else failed = "kp_plan_set_workspace";
     }
     const size_t n = vb / sizeof(double);
     double* eta_b = me.stage;
@@ -255,8 +298,10 @@ void worker_main(kp_server* s, int w) {
         for (int i = 0; i < b && rc == KP_OK; ++i) {
           const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyHostToDevice
                                                                 : hipMemcpyDeviceToDevice;
-          if (hipMemcpyAsync(eta_b + n * i, batch[i].r.eta, vb, k, me.stream) != hipSuccess)
+          if (hipMemcpyAsync(eta_b + n * i, batch[i].r.eta, vb, k, me.stream) != hipSuccess) {
             rc = KP_EHIP;
+            failed = "hipMemcpyAsync of a right-hand side";
+          }
         }
       }
     }
@@ -270,15 +315,25 @@ void worker_main(kp_server* s, int w) {
           if (!batch[i].r.u) continue;
           const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyDeviceToHost
                                                                 : hipMemcpyDeviceToDevice;
-          if (hipMemcpyAsync(batch[i].r.u, u_b + n * i, vb, k, me.stream) != hipSuccess)
+          if (hipMemcpyAsync(batch[i].r.u, u_b + n * i, vb, k, me.stream) != hipSuccess) {
             rc = KP_EHIP;
+            failed = "hipMemcpyAsync of a solution";
+          }
         }
-        if (hipStreamSynchronize(me.stream) != hipSuccess) rc = KP_EHIP;
+        if (hipStreamSynchronize(me.stream) != hipSuccess) {
+          rc = KP_EHIP;
+          failed = "hipStreamSynchronize after the solution copies";
+        }
       }
     }
     const double t_end = s->now();
+    char why[256] = "";
+    if (rc < 0)
+      snprintf(why, sizeof why, "batch of %d on worker %d: %s (status %d)", b, w,
+               failed ? failed : kp_last_error(), rc);
 
     lk.lock();
+    if (why[0]) std::memcpy(s->last_error, why, sizeof why);
     for (int i = 0; i < b; ++i) {
       const bool per_rhs = rc >= 0;
       complete(s, batch[i], per_rhs ? me.res[i].status : rc, per_rhs ? &me.res[i] : nullptr, b,
@@ -375,6 +430,13 @@ int kp_server_stats_get(kp_server* s, kp_server_stats* out) {
   return KP_OK;
 }
 
+const char* kp_server_last_error(kp_server* s) {
+  if (!s) return "";
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memcpy(s->last_error_out, s->last_error, sizeof s->last_error);
+  return s->last_error_out;
+}
+
 void kp_server_destroy(kp_server* s) {
   if (!s) return;
   {
@@ -390,6 +452,7 @@ void kp_server_destroy(kp_server* s) {
   }
   for (Worker& w : s->workers) {
     if (w.stage) (void)hipFree(w.stage);
+    if (w.ws) (void)hipFree(w.ws);
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   delete s;

@@ -10,7 +10,9 @@
 #include <utility>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -162,13 +164,41 @@ Layout layout_for(const kp_plan* p, int batch) {
   return L;
 }
 
-bool ok(hipError_t e) { return e == hipSuccess; }
+}  // namespace
+
+// Serialises graph capture against the calls that invalidate a capture in
+// progress on another host thread (device and pinned allocations and frees,
+// synchronous copies, stream, event and graph creation and destruction).
+// Shared with the request server, whose worker threads solve concurrently.
+namespace kp {
+std::mutex& api_mutex() {
+  static std::mutex m;
+  return m;
+}
+}  // namespace kp
+using kp::api_mutex;
+
+namespace {
+
+// The HIP call behind the last KP_EHIP (or KP_ENOMEM from an allocation) of
+// this host thread, for kp_last_error.
+thread_local char t_last_error[256] = "";
+
+bool ok_at(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  snprintf(t_last_error, sizeof t_last_error, "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
+  return false;
+}
+#define ok(e) ok_at((e), #e)
 
 int ensure_workspace(kp_plan* p) {
   if (p->ws) return KP_OK;
   const size_t need = layout_for(p, p->max_batch).total;
   void* ptr = nullptr;
-  if (!ok(hipMalloc(&ptr, need))) return KP_ENOMEM;
+  {
+    std::lock_guard<std::mutex> lk(api_mutex());
+    if (!ok(hipMalloc(&ptr, need))) return KP_ENOMEM;
+  }
   p->ws = ptr;
   p->ws_bytes = need;
   p->ws_owned = true;
@@ -179,6 +209,7 @@ int ensure_workspace(kp_plan* p) {
 // reading it needs no copy kernel.
 int ensure_hist(kp_plan* p, size_t doubles) {
   if (p->hist_cap >= doubles) return KP_OK;
+  std::lock_guard<std::mutex> lk(api_mutex());
   if (p->hist) (void)hipHostFree(p->hist);
   p->hist = nullptr;
   p->hist_dev = nullptr;
@@ -209,6 +240,7 @@ void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int b
 }
 
 void clear_graphs(kp_plan* p) {
+  std::lock_guard<std::mutex> lk(api_mutex());
   for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
   p->graphs.clear();
 }
@@ -270,6 +302,7 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     mp_pack(Qt.data(), na, prec, host.data() + offB[a]);
     std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
   }
+  std::lock_guard<std::mutex> alk(api_mutex());   // held until the plan is complete
   if (!ok(hipMalloc(&p->resident, bytes))) { delete p; return KP_ENOMEM; }
   p->resident_bytes = bytes;
   if (!ok(hipMemcpy(p->resident, host.data(), bytes, hipMemcpyHostToDevice))) {
@@ -321,6 +354,7 @@ void kp_plan_destroy(kp_plan* p) {
   else (void)hipDeviceSynchronize();
   if (p->own) (void)hipStreamSynchronize(p->own);
   clear_graphs(p);
+  std::lock_guard<std::mutex> lk(api_mutex());
   if (p->own) (void)hipStreamDestroy(p->own);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ws_owned && p->ws) (void)hipFree(p->ws);
@@ -342,6 +376,7 @@ int kp_plan_set_workspace(kp_plan* p, void* dev, size_t bytes) {
   if (bytes < layout_for(p, p->max_batch).total) return KP_ENOMEM;
   if (p->ws_owned && p->ws) {
     (void)hipStreamSynchronize(p->stream);
+    std::lock_guard<std::mutex> lk(api_mutex());
     (void)hipFree(p->ws);
   }
   p->ws = dev;
@@ -441,6 +476,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
       }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::lock_guard<std::mutex> lk(api_mutex());
     bool okc = ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     if (okc) {
       body();
@@ -562,6 +598,8 @@ const char* kp_strerror(int s) {
 }
 
 const char* kp_version(void) { return "kpcg 0.1 (gfx950)"; }
+
+const char* kp_last_error(void) { return t_last_error; }
 
 int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
   if (!p || batch < 1 || batch > p->max_batch || reps < 1 || reps > 1000) return KP_EINVAL;

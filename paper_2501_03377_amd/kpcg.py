@@ -39,7 +39,7 @@ EXPORTS = (
     "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
     "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
-    "kp_server_stats_get", "kp_server_destroy",
+    "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
 )
 KERNEL_CLASSES = 14
 
@@ -152,6 +152,8 @@ def _load():
         "kp_server_now": (d, [vp]),
         "kp_server_stats_get": (i, [vp, ctypes.POINTER(KpServerStats)]),
         "kp_server_destroy": (None, [vp]),
+        "kp_server_last_error": (ctypes.c_char_p, [vp]),
+        "kp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -170,6 +172,10 @@ def kp_strerror(status):
 
 def kp_version():
     return _lib.kp_version().decode()
+
+
+def kp_last_error():
+    return _lib.kp_last_error().decode()
 
 
 def kp_basis_1d(n, bc):
@@ -508,6 +514,9 @@ class Server:
 
     def now(self):
         return kp_server_now(self._h)
+
+    def last_error(self):
+        return _lib.kp_server_last_error(self._h).decode()
 
     def stats(self):
         rc, st = kp_server_stats_get(self._h)

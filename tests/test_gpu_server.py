@@ -92,10 +92,12 @@ def test_server_evicts_idle_plans_and_rejects_oversize():
     from paper_2501_03377_amd import Plan
     shape = (24, 24, 24)
     probe = Plan(24, 24, 24, ("P", "P", "P"), prec="f32", max_batch=2)
-    one = probe.resident_bytes + probe.workspace_bytes + 2 * 2 * 8 * 24 ** 3
+    resident = probe.resident_bytes
+    one = resident + probe.workspace_bytes + 2 * 2 * 8 * 24 ** 3
     probe.close()
-    # room for one plan of this size and its staging, not for two
-    srv = Server(hbm_budget=int(one * 1.5), workers=1, max_batch=2)
+    # the worker's workspace and staging plus one plan's operators fit, a
+    # second plan's operators do not
+    srv = Server(hbm_budget=one + resident // 2, workers=1, max_batch=2)
     try:
         keys = [("P", "P", "P"), ("D", "D", "D"), ("N", "N", "N"), ("P", "P", "P")]
         for k, bcs in enumerate(keys):
