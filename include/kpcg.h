@@ -48,9 +48,14 @@ enum kp_bc { KP_BC_P = 0, KP_BC_D = 1, KP_BC_N = 2, KP_BC_DN = 3, KP_BC_ND = 4 }
 /* Arithmetic of the preconditioner's mode products.  Vectors, residuals,
  * inner products and the solution are FP64 in every mode.  F32 uses FP32
  * matrix cores; BF16 uses BF16 matrix cores with FP32 accumulation and a
- * per-right-hand-side power-of-two input scale; the Hadamard factor of
- * eq. (4.6) is always applied in at least FP32. */
-enum kp_prec { KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2 };
+ * per-right-hand-side power-of-two input scale; BF16X6 reaches FP32 accuracy
+ * on the BF16 matrix cores: both operands are split into three BF16 terms
+ * (x = x1 + x2 + x3, each the round-to-nearest remainder of the previous)
+ * and the six products xi*bj with i + j <= 4 (1-based) are accumulated in
+ * FP32, the dropped terms being below 2^-24 relative; intermediates are FP32
+ * and the input scale is as for BF16.  The Hadamard factor of eq. (4.6) is
+ * always applied in at least FP32. */
+enum kp_prec { KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2, KP_PREC_BF16X6 = 3 };
 
 enum kp_status {
   KP_OK = 0,

@@ -62,6 +62,22 @@ template <> struct MT<PREC_BF16> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// FP32-accurate products on the BF16 matrix cores: a chunk holds the three
+// BF16 terms of 8 values (x = x1 + x2 + x3); step s accumulates the product
+// of data term split_a(s) and operator term split_b(s), the six pairs with
+// i + j <= 2 (0-based), largest first.
+constexpr int split_a(int s) { return (s == 2 || s == 4) ? 1 : (s == 5 ? 2 : 0); }
+constexpr int split_b(int s) { return (s == 1 || s == 4) ? 1 : (s == 3 ? 2 : 0); }
+template <> struct MT<PREC_BF16X6> {
+  using tc = float; using acc = f4;
+  static constexpr int CH = 8, NV = 3, STEPS = 6;
+  struct chunk { bf8 p[3]; };
+  static __device__ __forceinline__ acc mma(const chunk& a, const chunk& b, acc c, int s) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[split_a(s)], b.p[split_b(s)], c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
 // Block = WR x WC waves (WR = 4 row groups, WC column groups); each wave owns
 // WM row fragments x WN column fragments of 16 x 16.
 constexpr int WR = 4;
@@ -109,7 +125,22 @@ __device__ __forceinline__ typename MT<PREC>::chunk cvt_raw(const XRaw<PREC, Ti>
                                                            bool scaled) {
   using M = MT<PREC>;
   typename M::chunk c;
-  if constexpr (std::is_same<Ti, typename M::tc>::value) {
+  if constexpr (PREC == PREC_BF16X6) {
+    // three round-to-nearest BF16 terms; each remainder is exact in FP32
+#pragma unroll
+    for (int s = 0; s < M::CH; ++s) {
+      float f;
+      if constexpr (sizeof(Ti) == 8) f = (float)(scaled ? x.v[s] * scale : x.v[s]);
+      else f = x.v[s];
+      const __bf16 t1 = (__bf16)f;
+      const float r1 = f - (float)t1;
+      const __bf16 t2 = (__bf16)r1;
+      const float r2 = r1 - (float)t2;
+      c.p[0][s] = t1;
+      c.p[1][s] = t2;
+      c.p[2][s] = (__bf16)r2;
+    }
+  } else if constexpr (std::is_same<Ti, typename M::tc>::value) {
     __builtin_memcpy(&c, &x, sizeof(c));
   } else {
 #pragma unroll
@@ -126,14 +157,11 @@ __device__ __forceinline__ typename MT<PREC>::chunk load_b(const u4* __restrict_
                                                           int c, int CB) {
   using M = MT<PREC>;
   typename M::chunk b;
-  if constexpr (M::NV == 1) {
-    const u4 u = l[g * CB + c];
-    __builtin_memcpy(&b, &u, 16);
-  } else {
-    const u4 u0 = l[(g * 2 + 0) * CB + c];
-    const u4 u1 = l[(g * 2 + 1) * CB + c];
-    __builtin_memcpy(&b.v[0], &u0, 16);
-    __builtin_memcpy(&b.v[2], &u1, 16);
+  static_assert(sizeof(b) == 16 * M::NV, "a chunk is NV 16-byte units");
+#pragma unroll
+  for (int h = 0; h < M::NV; ++h) {
+    const u4 u = l[(g * M::NV + h) * CB + c];
+    __builtin_memcpy(reinterpret_cast<char*>(&b) + 16 * h, &u, 16);
   }
   return b;
 }
@@ -179,7 +207,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   constexpr int UPT = (SUNITS + NT - 1) / NT; // units per thread per stage
   // operator fragments read per group: the largest divisor of WN whose
   // fragments take at most 32 VGPRs
-  constexpr int JG = group_size(WN, PREC == PREC_F64 ? 4 : 8);
+  constexpr int JG = group_size(WN, (PREC == PREC_F64 || PREC == PREC_BF16X6) ? 4 : 8);
   // data ring depth: KS k-blocks, halved while the raw data would take more
   // than 64 VGPRs (the FP64 sources of the first product are twice as wide)
   constexpr int RAWV = CH * (int)sizeof(Ti) / 4;
@@ -229,22 +257,25 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   const int cmax = npk - c0;                  // packed columns left for this block
   const int nst = (nkb + KS - 1) / KS;
 
-  // loads stage `sg` of the operator into breg (zeros past the end)
+  // Loads stage `sg` of the operator into breg.  Every load is issued
+  // unconditionally, with clamped indices, so that the compiler counts the
+  // same loads in flight on every path and waits only for the ones it needs:
+  // k-blocks past the end (last stage) and columns past the end (ragged last
+  // column chunk) only feed accumulators that are never stored, and threads
+  // past the stage size repeat the last unit (the same value to the same
+  // LDS address).
 #define KP_LOAD_STAGE(sg)                                                                  \
   _Pragma("unroll") for (int q = 0; q < UPT; ++q) {                                       \
-    const int su = tid + q * NT;                                                           \
-    if (FULL || su < SUNITS) {                                                             \
-      const int kk = su / UNITS, u = su % UNITS, c = u % CB, gh = u / CB;                  \
-      const int kbg = (sg) * KS + kk;                                                      \
-      breg[q] = (c < cmax && kbg < nkb)                                                    \
-                    ? bsrc[((int64_t)kbg * 4 * NV + gh) * npk + c]                         \
-                    : (u4){0u, 0u, 0u, 0u};                                                \
-    }                                                                                      \
+    const int su = FULL ? tid + q * NT : min(tid + q * NT, SUNITS - 1);                    \
+    const int kk = su / UNITS, u = su % UNITS, gh = u / CB;                                \
+    const int c = min(u % CB, cmax - 1);                                                   \
+    const int kbg = min((sg) * KS + kk, nkb - 1);                                          \
+    breg[q] = bsrc[((int64_t)kbg * 4 * NV + gh) * npk + c];                                \
   }
 #define KP_STORE_STAGE(bf)                                                                 \
   _Pragma("unroll") for (int q = 0; q < UPT; ++q) {                                       \
-    const int su = tid + q * NT;                                                           \
-    if (FULL || su < SUNITS) lds[bf][su] = breg[q];                                        \
+    const int su = FULL ? tid + q * NT : min(tid + q * NT, SUNITS - 1);                    \
+    lds[bf][su] = breg[q];                                                                 \
   }
 
   KP_LOAD_STAGE(0)
@@ -260,8 +291,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
 
   for (int sg = 0; sg < nst; ++sg) {
     const int buf = sg & 1;
-    const bool more = sg + 1 < nst;
-    if (more) { KP_LOAD_STAGE(sg + 1) }
+    KP_LOAD_STAGE(sg + 1)   // past the last stage: a harmless reload
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const int kb = sg * KS + kk;
@@ -293,7 +323,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
       for (int i = 0; i < WM; ++i)
         xq[slot][i] = load_raw<PREC, Ti, VEC>(xrow[i], (rok[i] && kn < nkb) ? k0 : K, K);
     }
-    if (more) { KP_STORE_STAGE(buf ^ 1) }
+    KP_STORE_STAGE(buf ^ 1)   // the buffer not read in this stage
     __syncthreads();
   }
 #undef KP_LOAD_STAGE
@@ -391,6 +421,7 @@ bool mp_config_allowed(int id, int prec) {
   if (id < 0 || id >= kNumCfgs) return false;
   if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || id >= 15);
   if (prec == PREC_BF16) return id != 16;
+  if (prec == PREC_BF16X6) return !(id == 3 || id == 7 || id == 11 || id >= 15);
   return true;
 }
 
@@ -415,8 +446,10 @@ int mp_default_config(int K, int prec) {
   return prec == PREC_F64 ? 13 : 15;   // widest: 256 (FP64) or 512 columns per block
 }
 
-static int chunk_k(int prec) { return prec == PREC_BF16 ? 32 : 16; }
+static bool bf16_mfma(int prec) { return prec == PREC_BF16 || prec == PREC_BF16X6; }
+static int chunk_k(int prec) { return bf16_mfma(prec) ? 32 : 16; }
 static int elem_size(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+static int split_terms(int prec) { return prec == PREC_BF16X6 ? 3 : 1; }
 
 static void packed_geometry(int K, int prec, int* npk, int* nkb) {
   *npk = ((K + 15) / 16) * 16;
@@ -426,35 +459,58 @@ static void packed_geometry(int K, int prec, int* npk, int* nkb) {
 size_t mp_packed_bytes(int K, int prec) {
   int npk, nkb;
   packed_geometry(K, prec, &npk, &nkb);
-  return (size_t)nkb * chunk_k(prec) * npk * elem_size(prec);
+  return (size_t)nkb * chunk_k(prec) * npk * elem_size(prec) * split_terms(prec);
+}
+
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+static double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return (double)f;
 }
 
 // Packs B (K x K, row-major, FP64) into the fragment order read by mp_kernel,
 // converted to the compute type (round to nearest even).  Zero padding.
+// BF16X6 packs the three BF16 terms of every entry (b = b1 + b2 + b3, each
+// the round-to-nearest remainder of the previous, from the FP64 value) as
+// three consecutive 16-byte units.
 void mp_pack(const double* B, int K, int prec, void* dst) {
   int npk, nkb;
   packed_geometry(K, prec, &npk, &nkb);
-  const int KBk = chunk_k(prec), es = elem_size(prec);
-  const int CH = prec == PREC_BF16 ? 8 : 4;
-  const int NV = (CH * es) / 16, per = 16 / es;
-  const size_t total = (size_t)nkb * KBk * npk;
+  const int KBk = chunk_k(prec), es = elem_size(prec), T = split_terms(prec);
+  const int CH = bf16_mfma(prec) ? 8 : 4;
+  const int NV = (CH * es) / 16 * T, per = 16 / es;
+  const size_t total = (size_t)nkb * KBk * npk * T;
   for (size_t e = 0; e < total * es; ++e) ((unsigned char*)dst)[e] = 0;
   for (int k = 0; k < K; ++k)
     for (int n = 0; n < K; ++n) {
       const int kb = k / KBk, rem = k % KBk, g = rem / CH, s = rem % CH;
       const int h = (s * es) / 16, w = s % per;
-      const size_t idx = ((((size_t)kb * 4 + g) * NV + h) * npk + n) * per + w;
       const double v = B[(size_t)k * K + n];
+      if (T == 3) {
+        double r = v;
+        for (int t = 0; t < 3; ++t) {
+          const uint16_t b = bf16_rne((float)r);
+          const size_t idx = ((((size_t)kb * 4 + g) * NV + t) * npk + n) * per + w;
+          ((uint16_t*)dst)[idx] = b;
+          r -= bf16_value(b);
+        }
+        continue;
+      }
+      const size_t idx = ((((size_t)kb * 4 + g) * NV + h) * npk + n) * per + w;
       if (es == 8) {
         ((double*)dst)[idx] = v;
       } else if (es == 4) {
         ((float*)dst)[idx] = (float)v;
       } else {
-        const float f = (float)v;
-        uint32_t u;
-        __builtin_memcpy(&u, &f, 4);
-        u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
-        ((uint16_t*)dst)[idx] = (uint16_t)(u >> 16);
+        ((uint16_t*)dst)[idx] = bf16_rne((float)v);
       }
     }
 }
@@ -483,7 +539,7 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
                       hipStream_t s) {
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
-  const int CH = PREC == PREC_BF16 ? 8 : 4;
+  const int CH = MT<PREC>::CH;
   trace_begin(cls, s);
   if (K % CH != 0) {
     // rows too ragged for 16-byte loads: one scalar-load tile serves every
@@ -521,7 +577,7 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
       KP_CASE(17, 8, 4, 2)
       default: KP_CASE(13, 8, 1, 2)
     }
-  } else {
+  } else if constexpr (PREC == PREC_BF16) {
     switch (cfg) {
       KP_COMMON_CASES
       KP_CASE(3, 4, 4, 1)
@@ -529,6 +585,11 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
       KP_CASE(11, 4, 4, 2)
       KP_CASE(15, 16, 1, 2)
       KP_CASE(17, 8, 4, 2)
+      default: KP_CASE(13, 8, 1, 2)
+    }
+  } else {
+    switch (cfg) {
+      KP_COMMON_CASES
       default: KP_CASE(13, 8, 1, 2)
     }
   }
@@ -602,6 +663,7 @@ void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch
   switch (op.prec) {
     case PREC_F64: product_t<PREC_F64>(op, q, in, out, batch, s); break;
     case PREC_F32: product_t<PREC_F32>(op, q, in, out, batch, s); break;
+    case PREC_BF16X6: product_t<PREC_BF16X6>(op, q, in, out, batch, s); break;
     default: product_t<PREC_BF16>(op, q, in, out, batch, s); break;
   }
 }
@@ -611,6 +673,7 @@ void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T
   switch (op.prec) {
     case PREC_F64: pinv_apply_t<PREC_F64>(op, R, Z, T0, T1, batch, st, s); break;
     case PREC_F32: pinv_apply_t<PREC_F32>(op, R, Z, T0, T1, batch, st, s); break;
+    case PREC_BF16X6: pinv_apply_t<PREC_BF16X6>(op, R, Z, T0, T1, batch, st, s); break;
     default: pinv_apply_t<PREC_BF16>(op, R, Z, T0, T1, batch, st, s); break;
   }
 }

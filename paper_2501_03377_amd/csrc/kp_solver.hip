@@ -139,7 +139,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2); }
+size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_BF16 ? 2 : 4); }
 
 struct Layout {
   size_t R, P, W, Z, T0, T1, part, st, total;
@@ -259,7 +259,7 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   if (!out || !bc) return KP_EINVAL;
   *out = nullptr;
   if (nx < 3 || ny < 3 || !(nz >= 3 || nz == 1)) return KP_EINVAL;
-  if (prec < 0 || prec > 2 || max_batch < 1) return KP_EINVAL;
+  if (prec < PREC_F64 || prec > PREC_BF16X6 || max_batch < 1) return KP_EINVAL;
   const int dim = nz == 1 ? 2 : 3;
   for (int a = 0; a < dim; ++a)
     if (bc[a] < 0 || bc[a] > 4) return KP_EINVAL;
@@ -511,7 +511,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   p->last_u = u;
   int done_iters = 0;
   int chunk = p->expect_iters > 0 ? p->expect_iters
-              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_F32 ? 2 : 8)));
+              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_BF16 ? 8 : 2)));
   bool first = true;
   while (true) {
     const int n = std::min(chunk, max_iter - done_iters);
@@ -611,7 +611,7 @@ int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
   char* base = (char*)p->ws;
   hipStream_t s = p->stream;
   const size_t vb = (size_t)p->g.N * batch * 8;
-  const size_t tb = (size_t)p->g.N * batch * (p->prec == PREC_F64 ? 8 : (p->prec == PREC_F32 ? 4 : 2));
+  const size_t tb = (size_t)p->g.N * batch * elem_bytes(p->prec);
   // defined contents for timing (values do not change the work)
   if (!ok(hipMemsetAsync(base + L.R, 0, vb, s)) || !ok(hipMemsetAsync(base + L.T0, 0, tb, s)) ||
       !ok(hipMemsetAsync(base + L.T1, 0, tb, s)))
@@ -663,7 +663,7 @@ int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
 }
 
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
-  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_BF16) return KP_EINVAL;
+  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_BF16X6) return KP_EINVAL;
   if (!mp_config_allowed(id, prec)) return KP_EINVAL;
   mp_config(id, wn, wm, wc);
   return KP_OK;

@@ -59,10 +59,11 @@ def test_stencil_random_large(shape, bcs):
     assert np.max(np.abs(w[1] - 2 * ref)) <= 2e-13 * np.max(np.abs(ref))
 
 
-PINV_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16": 5e-2}
+PINV_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16": 5e-2, "bf16x6": 2e-4}
+PRECS = ["f64", "f32", "bf16", "bf16x6"]
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("shape,bcs", [
     ((5, 4, 3), ("D", "N", "P")),
     ((7, 70, 67), ("P", "DN", "ND")),
@@ -81,7 +82,7 @@ def test_pinv_parity(shape, bcs, prec):
     assert err <= PINV_TOL[prec], err
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_pinv_all_bc_triples_small(prec):
     rng = np.random.default_rng(4)
     shape = (4, 5, 6)
@@ -92,6 +93,25 @@ def test_pinv_all_bc_triples_small(prec):
         err = rel(z, oracle_pinv(r, bcs))
         assert err <= PINV_TOL[prec], (bcs, err)
         plan.close()
+
+
+@pytest.mark.parametrize("shape,bcs", [((33, 65, 130), ("P", "P", "DN")), ((64, 64), ("P", "N")),
+                                       ((40, 48, 64), ("N", "D", "P"))])
+def test_bf16x6_is_as_accurate_as_fp32(shape, bcs):
+    # three-term BF16 splits on the BF16 matrix cores reach FP32 accuracy: the
+    # error to the exact pseudoinverse is within a small factor of the FP32
+    # matrix-core result's and far below the plain BF16 one's
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(shape)
+    ref = oracle_pinv(r, bcs)
+    err = {}
+    for prec in ("f32", "bf16x6", "bf16"):
+        plan = _plan(shape, bcs, prec=prec)
+        err[prec] = rel(to_host(plan.apply_pinv(to_dev(r))), ref)
+        plan.close()
+    print("pinv errors", err)
+    assert err["bf16x6"] <= 4 * err["f32"] + 1e-12, err
+    assert err["bf16x6"] * 100 <= err["bf16"], err
 
 
 def test_pinv_batch_matches_single():
@@ -109,11 +129,12 @@ def test_pinv_batch_matches_single():
 # tile configurations compiled per precision (the others would spill)
 TILE_CONFIGS = {"f64": [c for c in range(18) if c not in (3, 7, 11, 15, 16, 17)],
                 "f32": list(range(18)),
-                "bf16": [c for c in range(18) if c != 16]}
+                "bf16": [c for c in range(18) if c != 16],
+                "bf16x6": [c for c in range(18) if c not in (3, 7, 11, 15, 16, 17)]}
 
 
 @pytest.mark.parametrize("shape", [(20, 36, 70), (24, 40, 72)])
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_tile_shapes_are_bitwise_identical(prec, shape):
     # every tile shape sums over k in the same order, so the result does not
     # depend on the autotuner's choice; (20, 36, 70) has rows too ragged for

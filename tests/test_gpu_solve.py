@@ -53,7 +53,7 @@ def test_all_bc_pairs_2d_f64():
         assert rc == 0 and err <= 1e-10, (bcs, rc, err)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16x6"])
 @pytest.mark.parametrize("shape,bcs", [
     ((33, 67, 130), ("P", "P", "DN")),
     ((40, 40, 40), ("N", "N", "N")),
@@ -81,12 +81,19 @@ def test_2d_64x64_dirichlet_blobs_f64():
     assert res[0]["rel_res"] <= 1e-12 and res[0]["true_rel_res"] <= 1e-12
 
 
-def test_full_size_256x256x128_ppdn_f32():
-    # 256 x 256 x 128, (P, P, DN), 1e4 charges + N(0, 1e-3), FP32 MFMA, tol 1e-10
-    eta = synth.charge_field((128, 256, 256), seed=2)
-    u, res, hist, rc = _solve(eta, ("P", "P", "DN"), prec="f32", tol=1e-10)
-    err = rel(u, oracle_solve(eta, ("P", "P", "DN")))
-    print("256x256x128", res[0], err)
+_FULL = {}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x6"])
+def test_full_size_256x256x128_ppdn(prec):
+    # 256 x 256 x 128, (P, P, DN), 1e4 charges + N(0, 1e-3), tol 1e-10, with
+    # the FP32 and the split-BF16 preconditioner
+    if "eta" not in _FULL:
+        _FULL["eta"] = synth.charge_field((128, 256, 256), seed=2)
+        _FULL["sol"] = oracle_solve(_FULL["eta"], ("P", "P", "DN"))
+    u, res, hist, rc = _solve(_FULL["eta"], ("P", "P", "DN"), prec=prec, tol=1e-10)
+    err = rel(u, _FULL["sol"])
+    print("256x256x128", prec, res[0], err)
     assert rc == 0 and err <= 1e-10
 
 
