@@ -175,6 +175,38 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
 int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol, int max_iter,
              int flags, kp_result* results, double* res_hist);
 
+/* Right-hand side of a problem with non-homogeneous boundary data
+ * (Sec. 3.4.2): rhs = eta plus, for every non-periodic axis end, its
+ * prescribed value added to each cell next to that face -- at a Dirichlet
+ * end the potential of the boundary node (L u = h + i_1 u_B), at a Neumann
+ * end the outward normal derivative e of the potential, defined by the ghost
+ * node u_0 = u_1 + e (L u = h + i_1 e); cells on edges and corners receive
+ * every face they touch.  Solving kp_solve with rhs then gives the potential
+ * of the non-homogeneous problem.
+ *   eta, rhs  device, batch grids (rhs may equal eta: in place; otherwise
+ *             they must not overlap)
+ *   faces     host, [batch][dim][2] doubles: value at the beginning and at
+ *             the end of each axis (x, y, z); entries of periodic axes must
+ *             be 0; NULL means homogeneous data (rhs = eta)
+ * Enqueued on the plan's stream (the face data is copied first and the call
+ * waits for that copy).  Returns KP_OK, KP_EINVAL (bad pointer, size,
+ * alignment, overlap, non-finite or periodic face data), KP_ENOMEM, KP_EHIP. */
+int kp_assemble_rhs(kp_plan* plan, const double* eta, double* rhs, int batch,
+                    const double* faces);
+
+/* Electric field eps = -grad u (Sec. 1) by second-order central differences
+ * at the grid points, eps_a = -(u_{+1} - u_{-1}) / 2 along axis a (unit
+ * spacing); a neighbour outside the grid is the periodic wrap, the
+ * prescribed potential at a Dirichlet end, or the boundary cell plus the
+ * prescribed outward derivative at a Neumann end (faces as for
+ * kp_assemble_rhs; NULL: homogeneous).
+ *   u    device, batch grids
+ *   eps  device, batch * dim grids, [rhs][component x, y(, z)][grid]; must
+ *        not overlap u
+ * Enqueued on the plan's stream.  Returns KP_OK, KP_EINVAL, KP_ENOMEM or
+ * KP_EHIP. */
+int kp_field(kp_plan* plan, const double* u, double* eps, int batch, const double* faces);
+
 /* Autotuner for the preconditioner's mode products.  Every product of
  * Algs. 6-7 is one GEMM; several tile shapes are compiled (waves per block,
  * rows and columns per wave).  For each product of this plan the call times

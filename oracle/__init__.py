@@ -23,6 +23,8 @@ Modules
   pcg        Algorithm 1 with the null-space centering of eq. (3.6) and
              Remark 4.1, iterated to stagnation of the true residual.
   dense      Moore-Penrose solution of the assembled Kronecker-sum system.
+  bcdata     right-hand side update for non-homogeneous Dirichlet / Neumann
+             data (Sec. 3.4.2) and the field eps = -grad u (Sec. 1).
 
 Parity status: every function here is pinned by tests/test_oracle_*.py against
 closed forms, brute force on tiny grids, invariants or numbers the paper
@@ -34,10 +36,11 @@ from .laplacian import (BCS, bc_corners, laplacian_1d, laplacian_1d_sparse,
 from .pinv import pinv_init, pinv_apply, PinvPreconditioner
 from .pcg import pcg, solve, PCGResult
 from .dense import dense_pinv_solve
+from .bcdata import assemble_rhs, field
 
 __all__ = [
     "BCS", "bc_corners", "laplacian_1d", "laplacian_1d_sparse",
     "apply_minus_laplacian", "kronecker_sum", "is_singular",
     "pinv_init", "pinv_apply", "PinvPreconditioner",
-    "pcg", "solve", "PCGResult", "dense_pinv_solve",
+    "pcg", "solve", "PCGResult", "dense_pinv_solve", "assemble_rhs", "field",
 ]

@@ -46,6 +46,11 @@ struct Geom {
 // Vector-kernel launchers (kp_vector.hip).  `part` holds NSLOTS x G block
 // partials per right-hand side; G is vec_blocks(N, batch).
 int vec_blocks(int64_t N, int batch);
+// Boundary data (Sec. 3.4.2) and the field eps = -grad u; faces is a device
+// array [rhs][axis][end] (null: homogeneous for the field).
+void launch_face_updates(const Geom& g, double* h, const double* faces, int batch, hipStream_t s);
+void launch_field(const Geom& g, const double* u, double* eps, const double* faces, int batch,
+                  hipStream_t s);
 bool zgrid_fits(const Geom& g);
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);

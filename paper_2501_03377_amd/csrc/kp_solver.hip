@@ -123,6 +123,8 @@ struct kp_plan {
   bool graphs_ok = true;              // cleared if capture is unavailable
   const void* last_eta = nullptr;     // buffers of the previous solve: when a solve
   const void* last_u = nullptr;       // repeats them, the whole solve is one graph
+  double* faces_dev = nullptr;        // boundary data of kp_assemble_rhs / kp_field
+  size_t faces_cap = 0;               // doubles
 };
 
 namespace {
@@ -237,6 +239,34 @@ void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int b
   } else {
     pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, s);
   }
+}
+
+// Checks host boundary data [batch][dim][2] (finite; zero on periodic axes)
+// and copies it to the plan's device buffer, ordered on the plan's stream.
+int stage_faces(kp_plan* p, const double* faces, int batch, const double** out) {
+  const int dim = p->g.dim;
+  const size_t n = (size_t)batch * dim * 2;
+  for (int b = 0; b < batch; ++b)
+    for (int a = 0; a < dim; ++a)
+      for (int e = 0; e < 2; ++e) {
+        const double v = faces[((size_t)b * dim + a) * 2 + e];
+        if (!std::isfinite(v) || (p->g.bc[a] == BC_P && v != 0.0)) return KP_EINVAL;
+      }
+  if (p->faces_cap < n) {
+    std::lock_guard<std::mutex> lk(api_mutex());
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->faces_dev) (void)hipFree(p->faces_dev);
+    p->faces_dev = nullptr;
+    p->faces_cap = 0;
+    if (!ok(hipMalloc((void**)&p->faces_dev, n * sizeof(double)))) return KP_ENOMEM;
+    p->faces_cap = n;
+  }
+  if (!ok(hipMemcpyAsync(p->faces_dev, faces, n * sizeof(double), hipMemcpyHostToDevice,
+                         p->stream)) ||
+      !ok(hipStreamSynchronize(p->stream)))
+    return KP_EHIP;
+  *out = p->faces_dev;
+  return KP_OK;
 }
 
 void clear_graphs(kp_plan* p) {
@@ -361,6 +391,7 @@ void kp_plan_destroy(kp_plan* p) {
   if (p->hist) (void)hipHostFree(p->hist);
   if (p->resident) (void)hipFree(p->resident);
   if (p->st_host) (void)hipHostFree(p->st_host);
+  if (p->faces_dev) (void)hipFree(p->faces_dev);
   delete p;
 }
 
@@ -582,6 +613,41 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   }
   if (max_it > 0) p->expect_iters = max_it;
   return worst;
+}
+
+int kp_assemble_rhs(kp_plan* p, const double* eta, double* rhs, int batch, const double* faces) {
+  if (!p || !eta || !rhs || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!aligned16(eta) || !aligned16(rhs)) return KP_EINVAL;
+  const size_t vbytes = (size_t)p->g.N * batch * 8;
+  if (eta != rhs && overlap(eta, rhs, vbytes)) return KP_EINVAL;
+  const double* fdev = nullptr;
+  if (faces) {
+    const int rc = stage_faces(p, faces, batch, &fdev);
+    if (rc != KP_OK) return rc;
+  }
+  (void)hipGetLastError();
+  if (eta != rhs &&
+      !ok(hipMemcpyAsync(rhs, eta, vbytes, hipMemcpyDeviceToDevice, p->stream)))
+    return KP_EHIP;
+  if (fdev) launch_face_updates(p->g, rhs, fdev, batch, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int kp_field(kp_plan* p, const double* u, double* eps, int batch, const double* faces) {
+  if (!p || !u || !eps || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!aligned16(u) || !aligned16(eps)) return KP_EINVAL;
+  const size_t ub = (size_t)p->g.N * batch * 8;
+  const char* a = (const char*)u;
+  const char* e = (const char*)eps;
+  if (a < e + ub * p->g.dim && e < a + ub) return KP_EINVAL;   // u and eps overlap
+  const double* fdev = nullptr;
+  if (faces) {
+    const int rc = stage_faces(p, faces, batch, &fdev);
+    if (rc != KP_OK) return rc;
+  }
+  (void)hipGetLastError();
+  launch_field(p->g, u, eps, fdev, batch, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
 }
 
 const char* kp_strerror(int s) {

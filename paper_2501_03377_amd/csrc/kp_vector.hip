@@ -8,6 +8,8 @@
 // results are bitwise reproducible run to run (no floating-point atomics).
 #include <math.h>
 
+#include <algorithm>
+
 #include "kp_common.h"
 #include "kp_internal.h"
 
@@ -632,6 +634,87 @@ void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int 
                      (double*)nullptr, (double*)nullptr, (const double*)nullptr, (double*)nullptr,
                      (const RhsState*)nullptr);
   trace_end(KC_STENCIL, s);
+}
+
+
+// ------------------------------------------------ boundary data and field ----
+// Non-homogeneous boundary data (Sec. 3.4.2): a prescribed value on one face
+// is added to every cell next to that face.  One launch per face, in stream
+// order, so cells on an edge or corner sum their faces deterministically.
+// faces: [rhs][axis][end] doubles.
+__global__ __launch_bounds__(VT) void k_face_add(Geom g, double* __restrict__ h,
+                                                 const double* __restrict__ faces, int axis,
+                                                 int end) {
+  const int rhs = blockIdx.y;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int na = axis == 0 ? nx : (axis == 1 ? ny : nz);
+  const int fixed = end ? na - 1 : 0;
+  const uint32_t cells = (uint32_t)(g.N / na);
+  const double v = faces[((int64_t)rhs * g.dim + axis) * 2 + end];
+  double* hr = h + (int64_t)rhs * g.N;
+  for (uint32_t c = blockIdx.x * VT + threadIdx.x; c < cells; c += gridDim.x * VT) {
+    int i, j, k;
+    if (axis == 0) { i = fixed; j = c % ny; k = c / ny; }
+    else if (axis == 1) { i = c % nx; j = fixed; k = c / nx; }
+    else { i = c % nx; j = c / nx; k = fixed; }
+    hr[i + (int64_t)nx * (j + (int64_t)ny * k)] += v;
+  }
+}
+
+// eps = -grad u (Sec. 1) by central differences at the grid points; the
+// neighbour outside the grid follows the ghost rule of the axis end:
+// periodic wrap, the prescribed potential at a Dirichlet end, the boundary
+// cell plus the prescribed outward derivative at a Neumann end (faces may be
+// null: homogeneous data).  eps: [rhs][component][grid].
+__global__ __launch_bounds__(VT) void k_field(Geom g, const double* __restrict__ u,
+                                              double* __restrict__ eps,
+                                              const double* __restrict__ faces) {
+  const int rhs = blockIdx.y;
+  const int nx = g.nx, ny = g.ny;
+  const double* ur = u + (int64_t)rhs * g.N;
+  for (uint32_t idx = blockIdx.x * VT + threadIdx.x; idx < (uint32_t)g.N;
+       idx += gridDim.x * VT) {
+    const int i = idx % nx, j = (idx / nx) % ny, k = idx / ((uint32_t)nx * ny);
+    const double c = ur[idx];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= g.dim) break;
+      const int pos = a == 0 ? i : (a == 1 ? j : k);
+      const int n = a == 0 ? nx : (a == 1 ? ny : g.nz);
+      const uint32_t stride = a == 0 ? 1u : (a == 1 ? (uint32_t)nx : (uint32_t)nx * ny);
+      const int bc = g.bc[a];
+      const double f0 = faces ? faces[((int64_t)rhs * g.dim + a) * 2 + 0] : 0.0;
+      const double f1 = faces ? faces[((int64_t)rhs * g.dim + a) * 2 + 1] : 0.0;
+      double lo, hi;
+      if (pos > 0) lo = ur[idx - stride];
+      else if (bc == BC_P) lo = ur[idx + (uint32_t)(n - 1) * stride];
+      else if (bc == BC_D || bc == BC_DN) lo = f0;     // Dirichlet node at the beginning
+      else lo = c + f0;                                // Neumann ghost at the beginning
+      if (pos < n - 1) hi = ur[idx + stride];
+      else if (bc == BC_P) hi = ur[idx - (uint32_t)(n - 1) * stride];
+      else if (bc == BC_D || bc == BC_ND) hi = f1;     // Dirichlet node at the end
+      else hi = c + f1;                                // Neumann ghost at the end
+      eps[((int64_t)rhs * g.dim + a) * g.N + idx] = -(hi - lo) * 0.5;
+    }
+  }
+}
+
+void launch_face_updates(const Geom& g, double* h, const double* faces, int batch,
+                         hipStream_t s) {
+  for (int a = 0; a < g.dim; ++a) {
+    if (g.bc[a] == BC_P) continue;
+    const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+    const int64_t cells = g.N / na;
+    const int G = (int)std::min<int64_t>((cells + VT - 1) / VT, 1024);
+    for (int end = 0; end < 2; ++end)
+      hipLaunchKernelGGL(k_face_add, dim3(G, batch), dim3(VT), 0, s, g, h, faces, a, end);
+  }
+}
+
+void launch_field(const Geom& g, const double* u, double* eps, const double* faces, int batch,
+                  hipStream_t s) {
+  const int G = (int)std::min<int64_t>((g.N + VT - 1) / VT, 4096);
+  hipLaunchKernelGGL(k_field, dim3(G, batch), dim3(VT), 0, s, g, u, eps, faces);
 }
 
 }  // namespace kp

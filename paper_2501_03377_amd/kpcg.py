@@ -40,6 +40,7 @@ EXPORTS = (
     "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
+    "kp_assemble_rhs", "kp_field",
 )
 KERNEL_CLASSES = 14
 
@@ -63,7 +64,9 @@ class KpResult(ctypes.Structure):
 class KpError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
-        super().__init__(f"{where}: {kp_strerror(status)} ({status})")
+        detail = kp_last_error() if status in (-2, -3) else ""
+        super().__init__(f"{where}: {kp_strerror(status)} ({status})"
+                         + (f" [{detail}]" if detail else ""))
 
 
 class KpRequest(ctypes.Structure):
@@ -118,6 +121,11 @@ KP_MEM_DEVICE, KP_MEM_HOST = 0, 1
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname as the system one
+    # this library links.  Imported first, its copy satisfies the library's
+    # dependency and the process has one runtime; loaded the other way round,
+    # torch pulls in a second copy and one of the two finds no device.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2501_03377_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
@@ -153,6 +161,8 @@ def _load():
         "kp_server_stats_get": (i, [vp, ctypes.POINTER(KpServerStats)]),
         "kp_server_destroy": (None, [vp]),
         "kp_server_last_error": (ctypes.c_char_p, [vp]),
+        "kp_assemble_rhs": (i, [vp, vp, vp, i, pd]),
+        "kp_field": (i, [vp, vp, vp, i, pd]),
         "kp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -441,6 +451,39 @@ class Plan:
         if rc != KP_OK:
             raise KpError(rc, "kp_apply_pinv")
         return Z
+
+    def _faces(self, faces, batch):
+        if faces is None:
+            return None, None
+        dim = 3 if self.dims[2] > 1 else 2
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(faces, dtype=np.float64),
+                                                 (batch, dim, 2)))
+        return f, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def assemble_rhs(self, eta, faces=None, out=None):
+        """eta plus the boundary-data update of kp_assemble_rhs; faces is
+        (dim, 2) or (batch, dim, 2): [axis][beginning, end]."""
+        batch = self._check(eta, "eta")
+        rhs = out if out is not None else _torch().empty_like(eta)
+        f, fp = self._faces(faces, batch)
+        rc = _lib.kp_assemble_rhs(self._h, eta.data_ptr(), rhs.data_ptr(), batch, fp)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_assemble_rhs")
+        return rhs
+
+    def field(self, u, faces=None, out=None):
+        """eps = -grad u, shaped (dim,) + grid (with a leading batch axis for
+        a batch)."""
+        torch = _torch()
+        batch = self._check(u, "u")
+        dim = 3 if self.dims[2] > 1 else 2
+        shape = ((batch,) if u.dim() > len(self.shape) else ()) + (dim,) + self.shape
+        eps = out if out is not None else torch.empty(shape, dtype=torch.float64, device=u.device)
+        f, fp = self._faces(faces, batch)
+        rc = _lib.kp_field(self._h, u.data_ptr(), eps.data_ptr(), batch, fp)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_field")
+        return eps
 
     def solve(self, eta, tol=1e-10, max_iter=50, flags=0, out=None, raise_on_error=True):
         """Returns (u, results, history, status); results is a list of dicts,
