@@ -175,6 +175,27 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
 int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol, int max_iter,
              int flags, kp_result* results, double* res_hist);
 
+/* Preconditioner of kp_solve and kp_apply_preconditioner (Sec. 4.3).
+ *   KP_PRECOND_PINV    the Moore-Penrose pseudoinverse (Sec. 4.3.3), default
+ *   KP_PRECOND_JACOBI  Jacobi(p, omega) (Sec. 4.3.1, Algs. 2-3): `steps` = p
+ *                      steps of the weighted Jacobi iteration on L x = R from
+ *                      x_0 = 0, splitting D_omega = omega D (eqs. 4.1-4.4);
+ *                      p >= 1, omega >= 1 (the paper's experiment uses
+ *                      p = 3, omega = 1.3); solves with it stop on the
+ *                      relative residual alone (M(R) is no error estimate)
+ * (KP_FLAG_NO_PRECOND still selects M = I per solve.)  Jacobi needs one more
+ * FP64 grid of workspace per right-hand side (kp_plan_workspace_bytes
+ * follows the current choice); a library-owned workspace is reallocated, a
+ * caller-provided one that is too small gives KP_ENOMEM and leaves the
+ * choice unchanged.  Returns KP_OK, KP_EINVAL or KP_ENOMEM. */
+enum kp_precond { KP_PRECOND_PINV = 0, KP_PRECOND_JACOBI = 1 };
+int kp_plan_set_preconditioner(kp_plan* plan, int kind, int steps, double omega);
+
+/* Z = M(R) with the plan's preconditioner (pinv or Jacobi); device
+ * pointers, batch grids each, not overlapping; enqueued on the plan's
+ * stream.  Returns KP_OK, KP_EINVAL, KP_ENOMEM or KP_EHIP. */
+int kp_apply_preconditioner(kp_plan* plan, const double* R, double* Z, int batch);
+
 /* Right-hand side of a problem with non-homogeneous boundary data
  * (Sec. 3.4.2): rhs = eta plus, for every non-periodic axis end, its
  * prescribed value added to each cell next to that face -- at a Dirichlet
@@ -238,7 +259,7 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
  * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
  * products of Algs. 6-7, ...).  Timing adds two event records per launch;
  * while it is on, kp_solve launches every kernel directly (no graph replay). */
-#define KP_KERNEL_CLASSES 14
+#define KP_KERNEL_CLASSES 15
 int kp_plan_set_profiling(kp_plan* plan, int enable);
 /* Synchronises the plan's stream, then returns the accumulated milliseconds
  * and launch count of one class.  KP_EINVAL for a bad class. */

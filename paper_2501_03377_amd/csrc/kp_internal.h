@@ -51,6 +51,9 @@ int vec_blocks(int64_t N, int batch);
 void launch_face_updates(const Geom& g, double* h, const double* faces, int batch, hipStream_t s);
 void launch_field(const Geom& g, const double* u, double* eps, const double* faces, int batch,
                   hipStream_t s);
+// Jacobi(p, omega) preconditioner (Sec. 4.3.1, Algs. 2-3); J is FP64 scratch.
+void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, double omega,
+                   const RhsState* st, int batch, int G, hipStream_t s);
 bool zgrid_fits(const Geom& g);
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
@@ -93,6 +96,7 @@ enum KernelClass {
   KC_MP_Y_BWD,
   KC_MP_Z_BWD,
   KC_COPY,          // Z = R when M = I
+  KC_JACOBI,        // Jacobi(p, omega) preconditioner steps
   KC_COUNT
 };
 

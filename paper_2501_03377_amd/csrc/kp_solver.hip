@@ -123,6 +123,9 @@ struct kp_plan {
   bool graphs_ok = true;              // cleared if capture is unavailable
   const void* last_eta = nullptr;     // buffers of the previous solve: when a solve
   const void* last_u = nullptr;       // repeats them, the whole solve is one graph
+  int pc_kind = KP_PRECOND_PINV;      // preconditioner of kp_solve / kp_apply_preconditioner
+  int jac_p = 3;                      // Jacobi(p, omega) parameters
+  double jac_omega = 1.3;
   double* faces_dev = nullptr;        // boundary data of kp_assemble_rhs / kp_field
   size_t faces_cap = 0;               // doubles
 };
@@ -144,7 +147,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_BF16 ? 2 : 4); }
 
 struct Layout {
-  size_t R, P, W, Z, T0, T1, part, st, total;
+  size_t R, P, W, Z, T0, T1, J, part, st, total;
 };
 
 Layout layout_for(const kp_plan* p, int batch) {
@@ -159,6 +162,7 @@ Layout layout_for(const kp_plan* p, int batch) {
   L.Z = take(N * 8);
   L.T0 = take(N * elem_bytes(p->prec));
   L.T1 = take(N * elem_bytes(p->prec));
+  L.J = p->pc_kind == KP_PRECOND_JACOBI ? take(N * 8) : 0;   // Jacobi ping-pong buffer
   (void)G;
   L.part = take((size_t)batch * NSLOTS * 8192 * 8);   // GMAX partials per slot
   L.st = take((size_t)batch * sizeof(RhsState));
@@ -236,6 +240,9 @@ void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int b
   char* base = (char*)p->ws;
   if (flags & KP_FLAG_NO_PRECOND) {
     launch_copy(p->g, R, Z, st, batch, vec_blocks(p->g.N, batch), s);
+  } else if (p->pc_kind == KP_PRECOND_JACOBI) {
+    launch_jacobi(p->g, R, Z, (double*)(base + L.J), p->jac_p, p->jac_omega, st, batch,
+                  vec_blocks(p->g.N, batch), s);
   } else {
     pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, s);
   }
@@ -457,6 +464,9 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   // With M = I the preconditioned residual is R itself, which is no error
   // estimate: stop on the residual alone.
   if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
+  // Jacobi(p, omega) approximates L^{-1} too loosely for M(R) to estimate
+  // the error either
+  if (p->pc_kind == KP_PRECOND_JACOBI) flags |= KP_FLAG_RESIDUAL_ONLY;
   int rc = ensure_workspace(p);
   if (rc != KP_OK) return rc;
   const int hs = max_iter + 1;
@@ -613,6 +623,44 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   }
   if (max_it > 0) p->expect_iters = max_it;
   return worst;
+}
+
+int kp_plan_set_preconditioner(kp_plan* p, int kind, int steps, double omega) {
+  if (!p || (kind != KP_PRECOND_PINV && kind != KP_PRECOND_JACOBI)) return KP_EINVAL;
+  if (kind == KP_PRECOND_JACOBI &&
+      (steps < 1 || steps > 10000 || !(omega >= 1.0) || !std::isfinite(omega)))
+    return KP_EINVAL;
+  const int old_kind = p->pc_kind;
+  p->pc_kind = kind;
+  const size_t need = layout_for(p, p->max_batch).total;
+  if (p->ws && p->ws_bytes < need) {
+    if (!p->ws_owned) { p->pc_kind = old_kind; return KP_ENOMEM; }   // caller's buffer too small
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->own) (void)hipStreamSynchronize(p->own);
+    std::lock_guard<std::mutex> lk(api_mutex());
+    (void)hipFree(p->ws);
+    p->ws = nullptr;          // reallocated at the next use
+    p->ws_bytes = 0;
+  }
+  if (kind == KP_PRECOND_JACOBI) {
+    p->jac_p = steps;
+    p->jac_omega = omega;
+  }
+  clear_graphs(p);
+  return KP_OK;
+}
+
+int kp_apply_preconditioner(kp_plan* p, const double* R, double* Z, int batch) {
+  if (!p || !R || !Z || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!aligned16(R) || !aligned16(Z)) return KP_EINVAL;
+  if (overlap(R, Z, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  const Layout L = layout_for(p, batch);
+  TraceScope scope(p);
+  (void)hipGetLastError();
+  precondition(p, L, R, Z, batch, 0, nullptr, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
 }
 
 int kp_assemble_rhs(kp_plan* p, const double* eta, double* rhs, int batch, const double* faces) {
@@ -777,7 +825,7 @@ const char* kp_kernel_class_name(int cls) {
   static const char* names[KC_COUNT] = {
       "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
       "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
-      "modeprod_y_bwd", "modeprod_z_bwd", "copy"};
+      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
 }
 

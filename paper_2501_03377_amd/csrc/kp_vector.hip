@@ -252,7 +252,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 constexpr int STX = 64, RY = 4, STY = RY * (VT / 64);
 constexpr int NXCD = 8;
 
-enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP };
+enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC };
 
 struct ZGrid {
   int ntx, ntiles;    // tiles along x, tiles per plane
@@ -266,6 +266,14 @@ __device__ __forceinline__ double ghost_lo(int bc, double c) {
 }
 __device__ __forceinline__ double ghost_hi(int bc, double c) {
   return (bc == BC_N || bc == BC_DN) ? c : 0.0;
+}
+
+// diagonal entry of L_n at position pos (eq. 3.1): the corners alpha, beta
+// at the ends, 2 inside and on periodic axes
+__device__ __forceinline__ double diag_1d(int pos, int n, int bc) {
+  if (pos == 0) return (bc == BC_N || bc == BC_ND) ? 1.0 : 2.0;
+  if (pos == n - 1) return (bc == BC_N || bc == BC_DN) ? 1.0 : 2.0;
+  return 2.0;
 }
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -287,13 +295,17 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 // ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2
 // ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U
 // ZM_LAP:  W = L P only
+// ZM_JAC:  one Jacobi(omega) step on L x = R (Sec. 4.3.1): P is x_{j-1}, W
+//          receives x_j = x_{j-1} + (R - L x_{j-1}) / (omega d), d the
+//          diagonal of L (eq. 4.4: sum of the 1D diagonals, corners of
+//          eq. 3.1 at the ends)
 template <int MODE>
 __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __restrict__ P,
                                            double* __restrict__ W, double* __restrict__ R,
                                            double* __restrict__ U, const double* __restrict__ eta,
-                                           double* part, const RhsState* st) {
+                                           double* part, const RhsState* st, double omega) {
   const int rhs = blockIdx.y;
-  if (MODE != ZM_TRUE && MODE != ZM_LAP && st[rhs].done) return;
+  if (MODE != ZM_TRUE && MODE != ZM_LAP && st && st[rhs].done) return;
   const int b = blockIdx.x;
   const int w = (b % NXCD) * zg.share + b / NXCD;   // XCD-aware work item
   const bool wok = w < zg.nwork;
@@ -364,13 +376,15 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     }
     double ea[RY], eb[RY];
     const uint32_t pbase = (uint32_t)k * plane;
-    if (MODE == ZM_UR || MODE == ZM_TRUE) {
+    if (MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const int64_t idx = off + pbase + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
         if (MODE == ZM_UR) {
           ea[r] = R[idx];
           eb[r] = U[idx];
+        } else if (MODE == ZM_JAC) {
+          ea[r] = R[idx];
         } else {
           ea[r] = eta[idx];
         }
@@ -412,6 +426,10 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           const double rr = (ea[r] - mean) - wv;
           a0 += rr * rr;
           a1 += cc;
+        } else if (MODE == ZM_JAC) {
+          const double d = diag_1d(i, nx, bcx) + diag_1d(y0 + r, ny, bcy) +
+                           (three ? diag_1d(k, nz, bcz) : 0.0);
+          W[idx] = cc + (ea[r] - wv) / (omega * d);
         } else {
           W[idx] = wv;
         }
@@ -427,7 +445,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     hhi = nhi;
     hed = ned;
   }
-  if (MODE == ZM_LAP) return;
+  if (MODE == ZM_LAP || MODE == ZM_JAC) return;
   if (MODE == ZM_UR) {
     double v[3] = {a0, a1, a2};
     const int sl[3] = {S_SUM, S_SQ, S_AUX};
@@ -590,14 +608,14 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
   trace_begin(KC_STENCIL, s);
   hipLaunchKernelGGL(k_zm<ZM_PW>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
                      (flags & F_FLEX_BETA) ? W : (double*)nullptr, (double*)nullptr,
-                     (double*)nullptr, (const double*)nullptr, part, (const RhsState*)st);
+                     (double*)nullptr, (const double*)nullptr, part, (const RhsState*)st, 0.0);
   trace_end(KC_STENCIL, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_alpha, dim3(batch), dim3(VT), 0, s, g, part, st, Gz);
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_UR, s);
   hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
-                     R, U, (const double*)nullptr, part, (const RhsState*)st);
+                     R, U, (const double*)nullptr, part, (const RhsState*)st, 0.0);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,
@@ -613,7 +631,7 @@ void launch_finish(const Geom& g, const double* eta, double* U, double* part, Rh
   trace_begin(KC_FINISH, s);
   hipLaunchKernelGGL(k_zm<ZM_TRUE>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
                      (const double*)U, (double*)nullptr, (double*)nullptr, (double*)nullptr, eta,
-                     part, (const RhsState*)st);
+                     part, (const RhsState*)st, 0.0);
   hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, Gz, mirror);
   if (g.singular) hipLaunchKernelGGL(k_center_u, dim3(G, batch), dim3(VT), 0, s, g, U, st, G);
   trace_end(KC_FINISH, s);
@@ -632,10 +650,43 @@ void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int 
   trace_begin(KC_STENCIL, s);
   hipLaunchKernelGGL(k_zm<ZM_LAP>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, P, W,
                      (double*)nullptr, (double*)nullptr, (const double*)nullptr, (double*)nullptr,
-                     (const RhsState*)nullptr);
+                     (const RhsState*)nullptr, 0.0);
   trace_end(KC_STENCIL, s);
 }
 
+
+
+// First Jacobi step from x_0 = 0: x_1 = R / (omega d).
+__global__ __launch_bounds__(VT) void k_jac_first(Geom g, const double* __restrict__ R,
+                                                  double* __restrict__ X, double omega,
+                                                  const RhsState* st, int G) {
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int64_t off = (int64_t)rhs * g.N;
+  const int nx = g.nx, ny = g.ny;
+  for (uint32_t idx = blockIdx.x * VT + threadIdx.x; idx < (uint32_t)g.N; idx += G * VT) {
+    const int i = idx % nx, j = (idx / nx) % ny, k = idx / ((uint32_t)nx * ny);
+    const double d = diag_1d(i, nx, g.bc[0]) + diag_1d(j, ny, g.bc[1]) +
+                     (g.dim == 3 ? diag_1d(k, g.nz, g.bc[2]) : 0.0);
+    X[off + idx] = R[off + idx] / (omega * d);
+  }
+}
+
+// Jacobi(p, omega) preconditioner (Algs. 2-3): p steps from x_0 = 0,
+// alternating between Z and J so that x_p lands in Z.
+void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, double omega,
+                   const RhsState* st, int batch, int G, hipStream_t s) {
+  double* buf[2] = {Z, J};
+  const ZGrid z = zgrid_for(g);
+  trace_begin(KC_JACOBI, s);
+  hipLaunchKernelGGL(k_jac_first, dim3(G, batch), dim3(VT), 0, s, g, R, buf[(p - 1) % 2], omega,
+                     st, G);
+  for (int j = 2; j <= p; ++j)
+    hipLaunchKernelGGL(k_zm<ZM_JAC>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
+                       (const double*)buf[(p - j + 1) % 2], buf[(p - j) % 2], (double*)R,
+                       (double*)nullptr, (const double*)nullptr, (double*)nullptr, st, omega);
+  trace_end(KC_JACOBI, s);
+}
 
 // ------------------------------------------------ boundary data and field ----
 // Non-homogeneous boundary data (Sec. 3.4.2): a prescribed value on one face

@@ -40,9 +40,9 @@ EXPORTS = (
     "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
-    "kp_assemble_rhs", "kp_field",
+    "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
 )
-KERNEL_CLASSES = 14
+KERNEL_CLASSES = 15
 
 
 class KpResult(ctypes.Structure):
@@ -163,6 +163,8 @@ def _load():
         "kp_server_last_error": (ctypes.c_char_p, [vp]),
         "kp_assemble_rhs": (i, [vp, vp, vp, i, pd]),
         "kp_field": (i, [vp, vp, vp, i, pd]),
+        "kp_plan_set_preconditioner": (i, [vp, i, i, d]),
+        "kp_apply_preconditioner": (i, [vp, vp, vp, i]),
         "kp_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -459,6 +461,21 @@ class Plan:
         f = np.ascontiguousarray(np.broadcast_to(np.asarray(faces, dtype=np.float64),
                                                  (batch, dim, 2)))
         return f, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def set_preconditioner(self, kind="pinv", steps=3, omega=1.3):
+        """'pinv' (default) or 'jacobi' with p = steps and omega."""
+        code = {"pinv": 0, "jacobi": 1}[kind]
+        rc = _lib.kp_plan_set_preconditioner(self._h, code, int(steps), float(omega))
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_set_preconditioner")
+
+    def apply_preconditioner(self, R, out=None):
+        batch = self._check(R, "R")
+        Z = out if out is not None else _torch().empty_like(R)
+        rc = _lib.kp_apply_preconditioner(self._h, R.data_ptr(), Z.data_ptr(), batch)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_apply_preconditioner")
+        return Z
 
     def assemble_rhs(self, eta, faces=None, out=None):
         """eta plus the boundary-data update of kp_assemble_rhs; faces is

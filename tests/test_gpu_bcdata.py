@@ -119,3 +119,44 @@ def test_periodic_face_data_is_rejected():
         plan.assemble_rhs(x, [[1.0, 0.0], [0.0, 0.0], [0.0, 0.0]])
     with pytest.raises(KpError):
         plan.field(x, [[0.0, 0.0], [np.nan, 0.0], [0.0, 0.0]])
+
+
+# ------------------------------------------------------------- Jacobi(p, w) ----
+@pytest.mark.parametrize("shape,bcs,steps,omega", [((5, 6, 7), ("N", "DN", "P"), 1, 1.0),
+                                                   ((33, 70, 67), ("D", "ND", "P"), 3, 1.3),
+                                                   ((40, 64), ("N", "D"), 4, 1.7),
+                                                   ((24, 20, 36), ("P", "P", "P"), 5, 2.0)])
+def test_jacobi_preconditioner_parity(shape, bcs, steps, omega):
+    from oracle.jacobi import jacobi_apply, jacobi_init
+    rng = np.random.default_rng(80)
+    r = rng.standard_normal(shape)
+    plan = _plan(shape, bcs)
+    plan.set_preconditioner("jacobi", steps, omega)
+    z = to_host(plan.apply_preconditioner(to_dev(r)))
+    O, Dinv = jacobi_init(r.T.shape, bcs, omega)
+    ref = jacobi_apply(r.T, O, Dinv, steps).T
+    assert rel(z, ref) <= 1e-14, rel(z, ref)
+
+
+def test_jacobi_solves_match_the_oracle_and_rank_as_in_the_paper():
+    # PCG with Jacobi(3, 1.3) reaches the oracle's solution; it needs more
+    # iterations than the pseudoinverse and fewer than plain CG
+    from paper_2501_03377_amd import KP_FLAG_NO_PRECOND
+    shape, bcs = (16, 24, 20), ("D", "N", "P")
+    eta = synth.charge_field(shape, ncharges=60, seed=4)
+    ref = oracle.solve(eta.T, bcs).u.T
+    plan = _plan(shape, bcs)
+    u_p, res_p, _, rc = plan.solve(to_dev(eta), tol=1e-10)
+    assert rc == 0
+    u_cg, res_cg, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=1000, flags=KP_FLAG_NO_PRECOND)
+    assert rc == 0
+    plan.set_preconditioner("jacobi", 3, 1.3)
+    u_j, res_j, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=1000)
+    assert rc == 0
+    for u in (u_p, u_cg, u_j):
+        assert rel(to_host(u), ref) <= 1e-8
+    it = (res_p[0]["iterations"], res_j[0]["iterations"], res_cg[0]["iterations"])
+    assert it[0] <= 3 < it[1] < it[2], it
+    plan.set_preconditioner("pinv")
+    u_p2, _, _, rc = plan.solve(to_dev(eta), tol=1e-10)
+    assert rc == 0 and np.array_equal(to_host(u_p2), to_host(u_p))
