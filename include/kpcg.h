@@ -266,6 +266,21 @@ int kp_plan_set_profiling(kp_plan* plan, int enable);
 int kp_plan_profile(kp_plan* plan, int cls, double* total_ms, int64_t* launches);
 /* Clears the accumulated timings. */
 int kp_plan_profile_reset(kp_plan* plan);
+/* Average duration of one kernel of class `cls` (milliseconds), measured
+ * as `reps` back-to-back launches between two HIP events on the plan's
+ * stream after one warm-up launch: the duration a kernel profiler reports
+ * per dispatch, without the launch gaps and event records that per-launch
+ * tracing adds.  Classes: the six (2D: four) mode products of Algs. 6-7 with
+ * the plan's current tile choices, and the stencil, update_ur, dot_rz and
+ * update_p kernels of Alg. 1.  The launch is the one an iteration on `batch`
+ * right-hand sides makes (flags: 0 or KP_FLAG_FLEX_BETA, which adds the
+ * flexible beta's extra operand), on workspace data: a fixed pseudo-random
+ * pattern, each product reading what the previous products of one
+ * application produce from it, every right-hand side running.  It overwrites
+ * the workspace (never the caller's buffers) and synchronises the plan's
+ * stream.  Returns KP_OK, KP_EINVAL (bad class for the plan's dimension,
+ * batch, reps outside 1..100000 or other flags), KP_ENOMEM or KP_EHIP. */
+int kp_plan_time_kernel(kp_plan* plan, int cls, int batch, int flags, int reps, double* avg_ms);
 /* Name of a kernel class, "unknown" when out of range. */
 const char* kp_kernel_class_name(int cls);
 

@@ -34,6 +34,9 @@ void mp_pack(const double* B, int K, int prec, void* dst);
 
 void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T1, int batch,
                 const RhsState* st, hipStream_t s);
+// Product q alone, with the buffers and arguments pinv_apply gives it.
+void pinv_step(const PinvOps& op, int q, const double* R, double* Z, void* T0, void* T1,
+               int batch, const RhsState* st, hipStream_t s);
 
 // Grid geometry and boundary conditions of one plan.
 struct Geom {
@@ -55,6 +58,15 @@ void launch_field(const Geom& g, const double* u, double* eps, const double* fac
 void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, double omega,
                    const RhsState* st, int batch, int G, hipStream_t s);
 bool zgrid_fits(const Geom& g);
+// Timing support: fills n doubles with a fixed pseudo-random pattern in
+// [-1, 1), marks batch states as running with finite scalars, and launches
+// the one kernel of a vector class (stencil, update_ur, dot_rz, update_p)
+// as an iteration does; false for other classes.
+void launch_fill(double* x, int64_t n, uint64_t seed, hipStream_t s);
+void launch_timing_states(RhsState* st, int batch, hipStream_t s);
+bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R, double* U,
+                         double* Z, double* part, const RhsState* st, int batch, int G,
+                         int flags, hipStream_t s);
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,

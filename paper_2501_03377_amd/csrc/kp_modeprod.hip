@@ -600,36 +600,41 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
 
 // Z = M(R) for `batch` right-hand sides.  R and Z are FP64 grids in the
 // natural layout; T0 and T1 are scratch grids in the compute type.
+// Product q of one application (Algs. 6-7) with the solver's buffers: R ->
+// T0 -> T1 -> T0 ... -> Z.  The first product scales its input per
+// right-hand side and the last unscales its output (not in FP64); the last
+// forward one carries the Hadamard factor.
+template <int PREC>
+static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, void* T0,
+                        void* T1, int batch, const RhsState* st, hipStream_t s) {
+  using tc = typename MT<PREC>::tc;
+  const int scl = (PREC == PREC_F64) ? 0 : 1;
+  const int dim = op.dim, ax = q % dim, last = 2 * dim - 1;
+  const bool fwd = q < dim;
+  void* T[2] = {T0, T1};
+  const void* in = q == 0 ? (const void*)R : (const void*)T[(q - 1) % 2];
+  void* out = q == last ? (void*)Z : T[q % 2];
+  const int cls = fwd ? (ax == 0 ? KC_MP_X_FWD : (ax == 1 ? KC_MP_Y_FWD : KC_MP_Z_FWD))
+                      : (ax == 0 ? KC_MP_X_BWD : (ax == 1 ? KC_MP_Y_BWD : KC_MP_Z_BWD));
+  if (q == 0) {
+    launch_mp<PREC, double, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, scl, 0, nullptr,
+                                nullptr, nullptr, 1, s);
+  } else if (q == last) {
+    launch_mp<PREC, tc, double>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, scl, nullptr,
+                                nullptr, nullptr, 1, s);
+  } else if (q == dim - 1) {
+    launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, op.lam[0],
+                            dim == 3 ? op.lam[1] : nullptr, op.lam[dim - 1], op.n[0], s);
+  } else {
+    launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, s);
+  }
+}
+
 template <int PREC>
 static void pinv_apply_t(const PinvOps& op, const double* R, double* Z, void* T0, void* T1,
                          int batch, const RhsState* st, hipStream_t s) {
-  using tc = typename MT<PREC>::tc;
-  const int scl = (PREC == PREC_F64) ? 0 : 1;
-  const int nx = op.n[0];
-  const int* c = op.cfg;
-  if (op.dim == 3) {
-    launch_mp<PREC, double, tc>(KC_MP_X_FWD, c[0], op, 0, true, R, T0, batch, st, scl, 0, nullptr,
-                                nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, tc>(KC_MP_Y_FWD, c[1], op, 1, true, T0, T1, batch, st, 0, 0, nullptr,
-                            nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, tc>(KC_MP_Z_FWD, c[2], op, 2, true, T1, T0, batch, st, 0, 0, op.lam[0],
-                            op.lam[1], op.lam[2], nx, s);
-    launch_mp<PREC, tc, tc>(KC_MP_X_BWD, c[3], op, 0, false, T0, T1, batch, st, 0, 0, nullptr,
-                            nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, tc>(KC_MP_Y_BWD, c[4], op, 1, false, T1, T0, batch, st, 0, 0, nullptr,
-                            nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, double>(KC_MP_Z_BWD, c[5], op, 2, false, T0, Z, batch, st, 0, scl,
-                                nullptr, nullptr, nullptr, 1, s);
-  } else {
-    launch_mp<PREC, double, tc>(KC_MP_X_FWD, c[0], op, 0, true, R, T0, batch, st, scl, 0, nullptr,
-                                nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, tc>(KC_MP_Y_FWD, c[1], op, 1, true, T0, T1, batch, st, 0, 0, op.lam[0],
-                            nullptr, op.lam[1], nx, s);
-    launch_mp<PREC, tc, tc>(KC_MP_X_BWD, c[2], op, 0, false, T1, T0, batch, st, 0, 0, nullptr,
-                            nullptr, nullptr, 1, s);
-    launch_mp<PREC, tc, double>(KC_MP_Y_BWD, c[3], op, 1, false, T0, Z, batch, st, 0, scl,
-                                nullptr, nullptr, nullptr, 1, s);
-  }
+  for (int q = 0; q < 2 * op.dim; ++q) pinv_step_t<PREC>(op, q, R, Z, T0, T1, batch, st, s);
 }
 
 // Launches product q of the preconditioner alone (autotuning): q < dim are the
@@ -665,6 +670,16 @@ void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch
     case PREC_F32: product_t<PREC_F32>(op, q, in, out, batch, s); break;
     case PREC_BF16X6: product_t<PREC_BF16X6>(op, q, in, out, batch, s); break;
     default: product_t<PREC_BF16>(op, q, in, out, batch, s); break;
+  }
+}
+
+void pinv_step(const PinvOps& op, int q, const double* R, double* Z, void* T0, void* T1,
+               int batch, const RhsState* st, hipStream_t s) {
+  switch (op.prec) {
+    case PREC_F64: pinv_step_t<PREC_F64>(op, q, R, Z, T0, T1, batch, st, s); break;
+    case PREC_F32: pinv_step_t<PREC_F32>(op, q, R, Z, T0, T1, batch, st, s); break;
+    case PREC_BF16X6: pinv_step_t<PREC_BF16X6>(op, q, R, Z, T0, T1, batch, st, s); break;
+    default: pinv_step_t<PREC_BF16>(op, q, R, Z, T0, T1, batch, st, s); break;
   }
 }
 

@@ -770,6 +770,74 @@ int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
   return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
 }
 
+int kp_plan_time_kernel(kp_plan* p, int cls, int batch, int flags, int reps, double* avg_ms) {
+  if (!p || !avg_ms || batch < 1 || batch > p->max_batch || reps < 1 || reps > 100000 ||
+      (flags & ~KP_FLAG_FLEX_BETA))
+    return KP_EINVAL;
+  const int dim = p->g.dim;
+  int q = -1;
+  switch (cls) {
+    case KC_MP_X_FWD: q = 0; break;
+    case KC_MP_Y_FWD: q = 1; break;
+    case KC_MP_Z_FWD: q = dim == 3 ? 2 : -2; break;
+    case KC_MP_X_BWD: q = dim; break;
+    case KC_MP_Y_BWD: q = dim + 1; break;
+    case KC_MP_Z_BWD: q = dim == 3 ? 5 : -2; break;
+    case KC_STENCIL: case KC_UPDATE_UR: case KC_DOT_RZ: case KC_UPDATE_P: break;
+    default: q = -2;
+  }
+  if (q == -2) return KP_EINVAL;
+  (void)hipGetLastError();
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  if (p->own) (void)hipStreamSynchronize(p->own);
+  const Layout L = layout_for(p, batch);
+  char* base = (char*)p->ws;
+  hipStream_t s = p->stream;
+  const int G = vec_blocks(p->g.N, batch);
+  const int64_t n = p->g.N * (int64_t)batch;
+  double* R = (double*)(base + L.R);
+  double* P = (double*)(base + L.P);
+  double* W = (double*)(base + L.W);
+  double* Z = (double*)(base + L.Z);
+  double* part = (double*)(base + L.part);
+  RhsState* st = (RhsState*)(base + L.st);
+  void* T0 = base + L.T0;
+  void* T1 = base + L.T1;
+  Tracer* saved = g_tracer;
+  g_tracer = nullptr;
+  // defined, non-trivial data; every right-hand side running
+  launch_fill(R, n, 1, s);
+  launch_fill(P, n, 2, s);
+  launch_fill(W, n, 3, s);
+  launch_fill(Z, n, 4, s);
+  launch_timing_states(st, batch, s);
+  // a product's input is the previous product's output, as in a solve
+  for (int k = 0; k < q; ++k) pinv_step(p->op, k, R, Z, T0, T1, batch, st, s);
+  auto once = [&]() {
+    if (q >= 0) pinv_step(p->op, q, R, Z, T0, T1, batch, st, s);
+    else launch_vector_class(cls, p->g, P, W, R, Z, Z, part, st, batch, G, flags, s);
+  };
+  once();   // warm-up
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!ok(hipEventCreate(&e0)) || !ok(hipEventCreate(&e1))) {
+    g_tracer = saved;
+    return KP_EHIP;
+  }
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) once();
+  (void)hipEventRecord(e1, s);
+  rc = ok(hipEventSynchronize(e1)) ? KP_OK : KP_EHIP;
+  float ms = 0.f;
+  if (rc == KP_OK && !ok(hipEventElapsedTime(&ms, e0, e1))) rc = KP_EHIP;
+  g_tracer = saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == KP_OK && !ok(hipGetLastError())) rc = KP_EHIP;
+  if (rc == KP_OK) *avg_ms = (double)ms / reps;
+  return rc;
+}
+
 int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
   if (!p || !cfg || n < 2 * p->g.dim) return KP_EINVAL;
   for (int q = 0; q < 2 * p->g.dim; ++q) cfg[q] = p->op.cfg[q];

@@ -768,4 +768,69 @@ void launch_field(const Geom& g, const double* u, double* eps, const double* fac
   hipLaunchKernelGGL(k_field, dim3(G, batch), dim3(VT), 0, s, g, u, eps, faces);
 }
 
+// ------------------------------------------------------------- timing ----
+// splitmix64's output function of the index (Steele, Lea, Flood 2014) as a
+// fixed pattern of doubles in [-1, 1).
+__global__ __launch_bounds__(VT) void k_fill(double* __restrict__ x, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+    uint64_t z = (uint64_t)i + seed * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+  }
+}
+
+__global__ void k_timing_states(RhsState* st, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  RhsState s = {};
+  s.h2 = 1.0;
+  s.rho = 1.0;
+  s.alpha = 0.5;
+  s.beta = 0.5;
+  s.scale = 1.0;
+  s.inv_scale = 1.0;
+  s.done = RUNNING;
+  st[b] = s;
+}
+
+void launch_fill(double* x, int64_t n, uint64_t seed, hipStream_t s) {
+  const int64_t want = (n + VT - 1) / VT;
+  const int blocks = (int)(want < 4096 ? (want < 1 ? 1 : want) : 4096);
+  hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(VT), 0, s, x, n, seed);
+}
+
+void launch_timing_states(RhsState* st, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_timing_states, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch);
+}
+
+bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R, double* U,
+                         double* Z, double* part, const RhsState* st, int batch, int G,
+                         int flags, hipStream_t s) {
+  const ZGrid z = zgrid_for(g);
+  const dim3 zgrid(z.nblocks, batch), grid(G, batch);
+  const bool flex = (flags & F_FLEX_BETA) != 0;
+  switch (cls) {
+    case KC_STENCIL:
+      hipLaunchKernelGGL(k_zm<ZM_PW>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
+                         flex ? W : (double*)nullptr, (double*)nullptr, (double*)nullptr,
+                         (const double*)nullptr, part, st, 0.0);
+      return true;
+    case KC_UPDATE_UR:
+      hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
+                         (double*)nullptr, R, U, (const double*)nullptr, part, st, 0.0);
+      return true;
+    case KC_DOT_RZ:
+      hipLaunchKernelGGL(k_dot_rz, grid, dim3(VT), 0, s, g, (const double*)R, (const double*)Z,
+                         flex ? (const double*)W : nullptr, part, st, G);
+      return true;
+    case KC_UPDATE_P:
+      hipLaunchKernelGGL(k_update_p, grid, dim3(VT), 0, s, g, (const double*)Z, P, st, G, 0);
+      return true;
+    default:
+      return false;
+  }
+}
+
 }  // namespace kp

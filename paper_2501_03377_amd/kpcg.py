@@ -37,7 +37,7 @@ EXPORTS = (
     "kp_plan_resident_bytes", "kp_plan_set_workspace", "kp_plan_set_stream",
     "kp_apply_laplacian", "kp_apply_pinv", "kp_solve", "kp_strerror", "kp_version",
     "kp_plan_set_profiling", "kp_plan_profile", "kp_plan_profile_reset", "kp_kernel_class_name",
-    "kp_plan_autotune", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
+    "kp_plan_autotune", "kp_plan_time_kernel", "kp_plan_get_tuning", "kp_plan_set_tuning", "kp_plan_graph_count",
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
@@ -149,6 +149,7 @@ def _load():
         "kp_plan_profile_reset": (i, [vp]),
         "kp_kernel_class_name": (ctypes.c_char_p, [i]),
         "kp_plan_autotune": (i, [vp, i, i, ctypes.POINTER(ctypes.c_int)]),
+        "kp_plan_time_kernel": (i, [vp, i, i, i, i, pd]),
         "kp_plan_get_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_set_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_graph_count": (i, [vp]),
@@ -268,6 +269,13 @@ def kp_plan_autotune(handle, batch, reps):
     chosen = (ctypes.c_int * 6)()
     rc = _lib.kp_plan_autotune(handle, int(batch), int(reps), chosen)
     return rc, list(chosen)
+
+
+def kp_plan_time_kernel(handle, cls, batch, flags, reps):
+    ms = ctypes.c_double()
+    rc = _lib.kp_plan_time_kernel(handle, int(cls), int(batch), int(flags), int(reps),
+                                  ctypes.byref(ms))
+    return rc, ms.value
 
 
 def kp_plan_get_tuning(handle):
@@ -422,6 +430,17 @@ class Plan:
         rc = kp_plan_set_profiling(self._h, enable)
         if rc != KP_OK:
             raise KpError(rc, "kp_plan_set_profiling")
+
+    def time_kernel(self, cls, batch=1, flags=0, reps=100):
+        """Average milliseconds of one launch of a kernel class (name or
+        number), `reps` launches back to back on workspace data."""
+        if isinstance(cls, str):
+            names = [kp_kernel_class_name(c) for c in range(KERNEL_CLASSES)]
+            cls = names.index(cls)
+        rc, ms = kp_plan_time_kernel(self._h, cls, batch, flags, reps)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_time_kernel")
+        return ms
 
     def profile(self):
         """{class name: (total_ms, launches)} accumulated since the last reset."""

@@ -168,3 +168,41 @@ def test_autotune_keeps_results():
     after = to_host(plan.apply_pinv(to_dev(r)))
     assert np.array_equal(before, after)
     assert rel(after, oracle_pinv(r, ("P", "P", "DN"))) <= PINV_TOL["f32"]
+
+
+@pytest.mark.parametrize("shape,bcs,prec", [((16, 48, 96), ("P", "P", "DN"), "f32"),
+                                            ((40, 64), ("N", "D"), "bf16")])
+def test_kernel_timing_call(shape, bcs, prec):
+    # every supported class times, unsupported ones are rejected, and the
+    # call leaves the caller's buffers and later solves untouched
+    from paper_2501_03377_amd import KpError, KP_FLAG_FLEX_BETA
+    from paper_2501_03377_amd.kpcg import KERNEL_CLASSES, kp_kernel_class_name
+    import synth
+    eta = synth.charge_field(shape, ncharges=30, seed=9)
+    plan = _plan(shape, bcs, prec=prec, max_batch=2)
+    e = to_dev(eta)
+    flags = KP_FLAG_FLEX_BETA if prec == "bf16" else 0
+    u1, _, _, rc = plan.solve(e, tol=1e-10, flags=flags)
+    assert rc == 0
+    u1 = to_host(u1)
+    dim = len(shape)
+    timed = set()
+    for c in range(KERNEL_CLASSES):
+        name = kp_kernel_class_name(c)
+        ok = (name.startswith("modeprod") and (dim == 3 or "_z_" not in name)) or \
+            name in ("stencil_dot", "update_ur", "dot_rz", "update_p")
+        if ok:
+            ms = plan.time_kernel(c, batch=2, flags=flags, reps=3)
+            assert 0.0 < ms < 100.0, (name, ms)
+            timed.add(name)
+        else:
+            with pytest.raises(KpError):
+                plan.time_kernel(c, batch=1, reps=1)
+    assert len(timed) == 2 * dim + 4
+    with pytest.raises(KpError):
+        plan.time_kernel("update_ur", batch=3)          # beyond max_batch
+    with pytest.raises(KpError):
+        plan.time_kernel("update_ur", flags=1)          # only the flexible-beta flag
+    assert np.array_equal(to_host(e), eta)
+    u2, _, _, rc = plan.solve(e, tol=1e-10, flags=flags)
+    assert rc == 0 and np.array_equal(to_host(u2), u1)
