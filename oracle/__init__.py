@@ -25,6 +25,10 @@ Modules
   dense      Moore-Penrose solution of the assembled Kronecker-sum system.
   bcdata     right-hand side update for non-homogeneous Dirichlet / Neumann
              data (Sec. 3.4.2) and the field eps = -grad u (Sec. 1).
+  jacobi     Jacobi(p, omega) preconditioner (Sec. 4.3.1, Algs. 2-3).
+  diagnostics  convergence descriptors of Experiment 5.4 (true residual,
+             kappa_s, null-space component) and the Hestenes-Stiefel error
+             estimate that Remark 4.2 points to.
 
 Parity status: every function here is pinned by tests/test_oracle_*.py against
 closed forms, brute force on tiny grids, invariants or numbers the paper
@@ -37,10 +41,12 @@ from .pinv import pinv_init, pinv_apply, PinvPreconditioner
 from .pcg import pcg, solve, PCGResult
 from .dense import dense_pinv_solve
 from .bcdata import assemble_rhs, field
+from .diagnostics import iterate_descriptors, error_norm_proxy, hs_error_estimate
 
 __all__ = [
     "BCS", "bc_corners", "laplacian_1d", "laplacian_1d_sparse",
     "apply_minus_laplacian", "kronecker_sum", "is_singular",
     "pinv_init", "pinv_apply", "PinvPreconditioner",
     "pcg", "solve", "PCGResult", "dense_pinv_solve", "assemble_rhs", "field",
+    "iterate_descriptors", "error_norm_proxy", "hs_error_estimate",
 ]

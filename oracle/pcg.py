@@ -26,6 +26,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from .diagnostics import iterate_descriptors
 from .laplacian import apply_minus_laplacian, is_singular
 from .pinv import PinvPreconditioner
 
@@ -48,6 +49,9 @@ class PCGResult:
     rec_rel_res: list = field(default_factory=list)      # ||R_s|| / ||H||
     removed_mean: float = 0.0
     h_norm: float = 0.0
+    # per iterate U_s: (true relative residual, kappa_s, null-space
+    # component, alpha_s rho_{s-1}) of Experiment 5.4 / Remark 4.2
+    diagnostics: list = field(default_factory=list)
 
 
 def pcg(eta, bcs, precond=None, true_tol=1e-14, stall=2, max_iter=20,
@@ -86,6 +90,7 @@ def pcg(eta, bcs, precond=None, true_tol=1e-14, stall=2, max_iter=20,
     P = Z.copy()                             # P_0
     res.true_rel_res.append(float(np.linalg.norm(H - apply_minus_laplacian(U, bcs))) / h_norm)
     res.rec_rel_res.append(float(np.linalg.norm(R)) / h_norm)
+    res.diagnostics.append(iterate_descriptors(U, H, bcs) + (0.0,))
 
     best = res.true_rel_res[0]
     no_progress = 0
@@ -96,6 +101,7 @@ def pcg(eta, bcs, precond=None, true_tol=1e-14, stall=2, max_iter=20,
         s += 1
         W = apply_minus_laplacian(P, bcs)    # W_s = -Delta(P_{s-1})
         alpha = rho / _inner(W, P)           # alpha_s
+        hs_term = alpha * rho                # alpha_s rho_{s-1}
         U = U + alpha * P                    # U_s
         R = R - alpha * W                    # R_s
         Z = apply_M(R)                       # Z_s
@@ -107,6 +113,7 @@ def pcg(eta, bcs, precond=None, true_tol=1e-14, stall=2, max_iter=20,
         true_rel = float(np.linalg.norm(H - apply_minus_laplacian(U, bcs))) / h_norm
         res.true_rel_res.append(true_rel)
         res.rec_rel_res.append(float(np.linalg.norm(R)) / h_norm)
+        res.diagnostics.append(iterate_descriptors(U, H, bcs) + (hs_term,))
 
         if fixed_iterations is not None:
             if s >= fixed_iterations:
