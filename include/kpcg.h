@@ -74,7 +74,12 @@ enum kp_flags {
                                Algorithm 1's rho_s/rho_{s-1}; for inexact
                                (low-precision) preconditioners */
   KP_FLAG_RESIDUAL_ONLY = 4,/* stop on the relative residual alone (see kp_solve) */
-  KP_FLAG_NO_GRAPH = 8      /* launch every kernel directly (no HIP graph replay) */
+  KP_FLAG_NO_GRAPH = 8,     /* launch every kernel directly (no HIP graph replay) */
+  KP_FLAG_DIAGNOSTICS = 16, /* record the convergence descriptors of every iterate
+                               (kp_plan_diagnostics); costs one stencil pass over
+                               U and eta per iteration, results are unchanged */
+  KP_FLAG_ANORM_STOP = 32   /* stop on an estimate of the L-norm error instead of
+                               the residual tests (see kp_solve) */
 };
 
 typedef struct kp_plan kp_plan;   /* opaque */
@@ -163,6 +168,13 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
  * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
  * set, also ||Z_s||/||U_s|| <= tol (Z_s = M(R_s) estimates the error of U_s).
+ * With KP_FLAG_ANORM_STOP the rule is instead the A-norm error estimate that
+ * Remark 4.2 recommends (Hestenes-Stiefel, as analysed by Strakos and Tichy):
+ * with t_j = alpha_j rho_{j-1}, iteration s >= d stops when
+ * sqrt((t_{s-d+1} + ... + t_s) / (t_1 + ... + t_s)) <= tol, d = 4, an
+ * estimate of ||U_{s-d} - u||_L / ||u||_L (U_s is returned, whose L-norm
+ * error is no larger).  It suits slowly converging preconditioners (Jacobi,
+ * M = I); with the pseudoinverse it costs d extra iterations.
  * Execution: the solve runs on a stream private to the plan, ordered after
  * earlier work on the plan's stream.  The first chunk of iterations (as many
  * as the previous solve on this plan needed) is captured once as a HIP graph
@@ -259,13 +271,37 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
  * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
  * products of Algs. 6-7, ...).  Timing adds two event records per launch;
  * while it is on, kp_solve launches every kernel directly (no graph replay). */
-#define KP_KERNEL_CLASSES 15
+#define KP_KERNEL_CLASSES 16
 int kp_plan_set_profiling(kp_plan* plan, int enable);
 /* Synchronises the plan's stream, then returns the accumulated milliseconds
  * and launch count of one class.  KP_EINVAL for a bad class. */
 int kp_plan_profile(kp_plan* plan, int cls, double* total_ms, int64_t* launches);
 /* Clears the accumulated timings. */
 int kp_plan_profile_reset(kp_plan* plan);
+/* Convergence descriptors of the plan's last kp_solve, which must have been
+ * made with KP_FLAG_DIAGNOSTICS (Experiment 5.4 and Remark 4.2).  For every
+ * right-hand side b and iterate s = 0 .. hs-1 (hs = that solve's max_iter + 1)
+ * out[(b*hs + s)*KP_DIAG_COLUMNS + c] receives, for U_s of Algorithm 1
+ * (before the exit centring of a singular problem), with eta_c the centred
+ * right-hand side (eq. 3.6):
+ *   0  true relative residual ||eta_c - L U_s|| / ||eta_c||
+ *   1  recursive relative residual ||R_s|| / ||eta_c|| (as res_hist)
+ *   2  kappa_s = U_s^T L U_s - 2 U_s^T eta_c; ||U_s - u||_L^2 = kappa_s + ||u||_L^2
+ *   3  the paper's L-norm-of-error proxy sqrt(kappa_s - min_j kappa_j), the
+ *      minimum over the recorded iterates of b
+ *   4  null-space component |sum U_s| / sqrt(N) (singular operators; else 0)
+ *   5  alpha_s rho_{s-1} (0 at s = 0): by the Hestenes-Stiefel identity the
+ *      decrease of ||U - u||_L^2 from iterate s-1 to s
+ *   6  Hestenes-Stiefel estimate of ||U_s - u||_L: the square root of column
+ *      5 summed over the next `delay` recorded iterates (a lower bound that
+ *      tightens as the error falls; fewer terms near the last iterate)
+ * Rows after a right-hand side's last iterate are NaN.  Host only, no GPU
+ * work.  Returns KP_OK, or KP_EINVAL if out is NULL, delay < 1, or (batch,
+ * hs) is not the shape of a last solve made with the flag.  The serving
+ * layer does not take the flag. */
+#define KP_DIAG_COLUMNS 7
+int kp_plan_diagnostics(const kp_plan* plan, double* out, int batch, int hs, int delay);
+
 /* Average duration of one kernel of class `cls` (milliseconds), measured
  * as `reps` back-to-back launches between two HIP events on the plan's
  * stream after one warm-up launch: the duration a kernel profiler reports

@@ -69,3 +69,17 @@ def hs_error_estimate(terms, delay):
     for s in range(len(t)):
         out[s] = np.sqrt(max(float(np.sum(t[s + 1:s + 1 + delay])), 0.0))
     return out
+
+
+def hs_stop_iteration(terms, tol, delay=4):
+    """The first iteration s >= delay at which the Hestenes-Stiefel estimate
+    of the relative L-norm error of U_{s-delay},
+        sqrt((terms[s-delay+1] + ... + terms[s]) / (terms[1] + ... + terms[s])),
+    is <= tol (its denominator estimates ||u||_L^2, since U_0 = 0); None if
+    no recorded iteration qualifies."""
+    t = np.asarray(terms, dtype=np.float64)
+    for s in range(delay, len(t)):
+        total = float(np.sum(t[1:s + 1]))
+        if total > 0.0 and np.sqrt(float(np.sum(t[s - delay + 1:s + 1])) / total) <= tol:
+            return s
+    return None

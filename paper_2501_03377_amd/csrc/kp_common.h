@@ -24,6 +24,9 @@ enum Done { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, ZERO_RHS =
 
 // Per right-hand-side scalar state of Algorithm 1, resident on the device so
 // that no iteration needs a host round trip.
+// Delay of the Hestenes-Stiefel error estimate that KP_FLAG_ANORM_STOP uses.
+constexpr int HS_DELAY = 4;
+
 struct RhsState {
   double h2;          // ||eta_c||^2
   double mean;        // mean removed from eta (singular operators, eq. 3.6)
@@ -44,10 +47,12 @@ struct RhsState {
   double umean;       // mean of U removed at exit (singular operators)
   double scale;       // power-of-two scale applied to the preconditioner input
   double inv_scale;   // its inverse, applied to the preconditioner output
+  double hs_sum;      // sum of alpha_j rho_{j-1}, j = 1..s (Hestenes-Stiefel terms)
+  double hs_ring[4];  // the last HS_DELAY of those terms, term j at j % HS_DELAY
   int iter;           // s
   int done;           // Done code
   int pinv_count;     // preconditioner applications so far
-  int pad;
+  int diag_iter;      // last iterate whose descriptors were recorded (-1: none)
 };
 
 // Reduction slots written by the vector and mode-product kernels, one block

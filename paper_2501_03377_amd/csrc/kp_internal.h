@@ -58,6 +58,12 @@ void launch_field(const Geom& g, const double* u, double* eps, const double* fac
 void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, double omega,
                    const RhsState* st, int batch, int G, hipStream_t s);
 bool zgrid_fits(const Geom& g);
+// Convergence descriptors of the current iterate U_s into row s of a
+// [batch][stride][DIAG_RAW] table (Experiment 5.4), for every right-hand
+// side whose iterate s is not yet recorded.
+constexpr int DIAG_RAW = 4;
+void launch_diag(const Geom& g, const double* eta, const double* U, double* part, RhsState* st,
+                 double* diag, int stride, int batch, hipStream_t s);
 // Timing support: fills n doubles with a fixed pseudo-random pattern in
 // [-1, 1), marks batch states as running with finite scalars, and launches
 // the one kernel of a vector class (stencil, update_ur, dot_rz, update_p)
@@ -86,6 +92,7 @@ enum {
   F_NO_PRECOND = 1,
   F_FLEX_BETA = 2,
   F_RESIDUAL_ONLY = 4,
+  F_ANORM_STOP = 32,
 };
 
 }  // namespace kp
@@ -109,6 +116,7 @@ enum KernelClass {
   KC_MP_Z_BWD,
   KC_COPY,          // Z = R when M = I
   KC_JACOBI,        // Jacobi(p, omega) preconditioner steps
+  KC_DIAG,          // convergence descriptors of the iterate (diagnostic solves)
   KC_COUNT
 };
 

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -95,6 +96,11 @@ struct kp_plan {
   double* hist = nullptr;       // residual history, pinned host memory mapped to the device
   double* hist_dev = nullptr;   // its device address
   size_t hist_cap = 0;          // doubles
+  double* diag = nullptr;       // descriptors of the iterates (KP_FLAG_DIAGNOSTICS), mapped
+  double* diag_dev = nullptr;   // like hist: [batch][hs][DIAG_RAW]
+  size_t diag_cap = 0;          // doubles
+  int diag_batch = 0;           // shape of the last solve's table (0: none)
+  int diag_hs = 0;
   RhsState* st_host = nullptr;  // pinned, mapped mirror of the state (written by the device)
   RhsState* st_dev = nullptr;   // its device address
   int expect_iters = 0;         // iterations the last solve needed (first chunk size)
@@ -108,10 +114,11 @@ struct kp_plan {
     double tol;
     const void* u;
     const void* hist;
+    const void* diag;   // descriptor table (nullptr without KP_FLAG_DIAGNOSTICS)
     const void* eta;    // whole-solve graphs only (nullptr for iteration chunks)
     bool operator==(const GraphKey& o) const {
       return batch == o.batch && n == o.n && flags == o.flags && hs == o.hs && tol == o.tol &&
-             u == o.u && hist == o.hist && eta == o.eta;
+             u == o.u && hist == o.hist && diag == o.diag && eta == o.eta;
     }
   };
   struct GraphEntry {
@@ -211,20 +218,24 @@ int ensure_workspace(kp_plan* p) {
   return KP_OK;
 }
 
-// Residual history in pinned host memory that the device writes directly, so
-// reading it needs no copy kernel.
-int ensure_hist(kp_plan* p, size_t doubles) {
-  if (p->hist_cap >= doubles) return KP_OK;
+// Pinned host memory that the device writes directly (residual history,
+// descriptor table), so reading it needs no copy kernel.
+int ensure_mapped(double** host, double** dev, size_t* cap, size_t doubles) {
+  if (*cap >= doubles) return KP_OK;
   std::lock_guard<std::mutex> lk(api_mutex());
-  if (p->hist) (void)hipHostFree(p->hist);
-  p->hist = nullptr;
-  p->hist_dev = nullptr;
-  p->hist_cap = 0;
-  if (!ok(hipHostMalloc((void**)&p->hist, doubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
+  if (*host) (void)hipHostFree(*host);
+  *host = nullptr;
+  *dev = nullptr;
+  *cap = 0;
+  if (!ok(hipHostMalloc((void**)host, doubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
     return KP_ENOMEM;
-  if (!ok(hipHostGetDevicePointer((void**)&p->hist_dev, p->hist, 0))) return KP_EHIP;
-  p->hist_cap = doubles;
+  if (!ok(hipHostGetDevicePointer((void**)dev, *host, 0))) return KP_EHIP;
+  *cap = doubles;
   return KP_OK;
+}
+
+int ensure_hist(kp_plan* p, size_t doubles) {
+  return ensure_mapped(&p->hist, &p->hist_dev, &p->hist_cap, doubles);
 }
 
 bool overlap(const void* a, const void* b, size_t bytes) {
@@ -396,6 +407,7 @@ void kp_plan_destroy(kp_plan* p) {
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ws_owned && p->ws) (void)hipFree(p->ws);
   if (p->hist) (void)hipHostFree(p->hist);
+  if (p->diag) (void)hipHostFree(p->diag);
   if (p->resident) (void)hipFree(p->resident);
   if (p->st_host) (void)hipHostFree(p->st_host);
   if (p->faces_dev) (void)hipFree(p->faces_dev);
@@ -456,7 +468,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
              int flags, kp_result* results, double* res_hist) {
   if (!p || !eta || !u || batch < 1 || batch > p->max_batch) return KP_EINVAL;
   if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 1000000) return KP_EINVAL;
-  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH))
+  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH |
+                KP_FLAG_DIAGNOSTICS | KP_FLAG_ANORM_STOP))
     return KP_EINVAL;
   if (!aligned16(eta) || !aligned16(u)) return KP_EINVAL;
   const size_t vbytes = (size_t)p->g.N * batch * 8;
@@ -472,6 +485,12 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   const int hs = max_iter + 1;
   rc = ensure_hist(p, (size_t)batch * hs);
   if (rc != KP_OK) return rc;
+  const bool diag = (flags & KP_FLAG_DIAGNOSTICS) != 0;
+  p->diag_batch = 0;
+  if (diag) {
+    rc = ensure_mapped(&p->diag, &p->diag_dev, &p->diag_cap, (size_t)batch * hs * DIAG_RAW);
+    if (rc != KP_OK) return rc;
+  }
   (void)hipGetLastError();
 
   const Layout L = layout_for(p, batch);
@@ -491,16 +510,25 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
 
   TraceScope scope(p);
   std::memset(p->hist, 0, (size_t)batch * hs * sizeof(double));   // no kernel writes it now
+  if (diag) {
+    std::fill(p->diag, p->diag + (size_t)batch * hs * DIAG_RAW,
+              std::numeric_limits<double>::quiet_NaN());
+    p->diag_batch = batch;
+    p->diag_hs = hs;
+  }
+  double* diag_dev = diag ? p->diag_dev : nullptr;
 
   // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
   auto head = [&]() {
     launch_init(p->g, eta, R, u, part, st, p->hist_dev, hs, batch, G, s);
+    if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
     precondition(p, L, R, Z, batch, flags, st, s);
     launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
   };
   auto iterations = [&](int n) {
     for (int q = 0; q < n; ++q) {
       launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
+      if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
       precondition(p, L, R, Z, batch, flags, st, s);
       launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
     }
@@ -559,7 +587,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     bool launched = false;
     if (first && use_graphs) {
       if (repeat) {
-        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, eta};
+        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
         const int gi = graph_for(key, [&]() { head(); iterations(n); tail(); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
@@ -567,7 +595,10 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
         }
       } else {
         head();
-        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, nullptr};
+        // (the iterations read eta only for the descriptors)
+        const kp_plan::GraphKey key{batch, n,        flags,   hs,
+                                    tol,   u,        p->hist_dev, diag_dev,
+                                    diag ? eta : nullptr};
         const int gi = graph_for(key, [&]() { iterations(n); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
@@ -623,6 +654,37 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   }
   if (max_it > 0) p->expect_iters = max_it;
   return worst;
+}
+
+int kp_plan_diagnostics(const kp_plan* p, double* out, int batch, int hs, int delay) {
+  if (!p || !out || p->diag_batch == 0 || batch != p->diag_batch || hs != p->diag_hs ||
+      delay < 1)
+    return KP_EINVAL;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int b = 0; b < batch; ++b) {
+    const double* raw = p->diag + (size_t)b * hs * DIAG_RAW;
+    const int last = std::min(p->st_host[b].diag_iter, hs - 1);   // rows 0..last recorded
+    double kmin = std::numeric_limits<double>::infinity();
+    for (int q = 0; q <= last; ++q) kmin = std::min(kmin, raw[q * DIAG_RAW + 1]);
+    for (int q = 0; q < hs; ++q) {
+      double* o = out + ((size_t)b * hs + q) * KP_DIAG_COLUMNS;
+      if (q > last) {
+        for (int c = 0; c < KP_DIAG_COLUMNS; ++c) o[c] = nan;
+        continue;
+      }
+      const double* r = raw + q * DIAG_RAW;
+      o[0] = r[0];
+      o[1] = p->hist[(size_t)b * hs + q];
+      o[2] = r[1];
+      o[3] = std::sqrt(std::max(r[1] - kmin, 0.0));
+      o[4] = r[2];
+      o[5] = r[3];
+      double acc = 0.0;
+      for (int j = q + 1; j <= std::min(q + delay, last); ++j) acc += raw[j * DIAG_RAW + 3];
+      o[6] = std::sqrt(std::max(acc, 0.0));
+    }
+  }
+  return KP_OK;
 }
 
 int kp_plan_set_preconditioner(kp_plan* p, int kind, int steps, double omega) {
@@ -893,7 +955,7 @@ const char* kp_kernel_class_name(int cls) {
   static const char* names[KC_COUNT] = {
       "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
       "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
-      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi"};
+      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi", "diagnostics"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
 }
 

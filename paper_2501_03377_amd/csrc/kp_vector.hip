@@ -105,6 +105,7 @@ __global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, Rhs
     RhsState s = {};
     s.mean = g.singular ? v[0] / (double)g.N : 0.0;
     s.scale = s.inv_scale = 1.0;
+    s.diag_iter = -1;
     st[rhs] = s;
   }
 }
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(VT) void k_fin_rho(Geom g, const double* part, RhsS
     return;
   }
   s.err_est = s.uu > 0.0 ? sqrt(zz / s.uu) : INFINITY;
-  if (!(flags & F_RESIDUAL_ONLY) && s.rel_res <= tol && s.err_est <= tol) {
+  if (!(flags & (F_RESIDUAL_ONLY | F_ANORM_STOP)) && s.rel_res <= tol && s.err_est <= tol) {
     s.done = CONVERGED;
     return;
   }
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 constexpr int STX = 64, RY = 4, STY = RY * (VT / 64);
 constexpr int NXCD = 8;
 
-enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC };
+enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC, ZM_DIAG };
 
 struct ZGrid {
   int ntx, ntiles;    // tiles along x, tiles per plane
@@ -299,13 +300,20 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 //          receives x_j = x_{j-1} + (R - L x_{j-1}) / (omega d), d the
 //          diagonal of L (eq. 4.4: sum of the 1D diagonals, corners of
 //          eq. 3.1 at the ends)
+// ZM_DIAG: P is the iterate U_s, h = eta - mean; partials ||h - L U||^2,
+//          sum U, <U, L U>, <U, h> (the descriptors of Experiment 5.4); runs
+//          only for a right-hand side whose iterate s is not yet recorded
 template <int MODE>
 __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __restrict__ P,
                                            double* __restrict__ W, double* __restrict__ R,
                                            double* __restrict__ U, const double* __restrict__ eta,
                                            double* part, const RhsState* st, double omega) {
   const int rhs = blockIdx.y;
-  if (MODE != ZM_TRUE && MODE != ZM_LAP && st && st[rhs].done) return;
+  if (MODE == ZM_DIAG) {
+    if (st[rhs].iter <= st[rhs].diag_iter) return;
+  } else if (MODE != ZM_TRUE && MODE != ZM_LAP && st && st[rhs].done) {
+    return;
+  }
   const int b = blockIdx.x;
   const int w = (b % NXCD) * zg.share + b / NXCD;   // XCD-aware work item
   const bool wok = w < zg.nwork;
@@ -334,7 +342,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   const int64_t off = (int64_t)rhs * g.N;
   const double* p = P + off;
   const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
-  const double mean = (MODE == ZM_TRUE) ? st[rhs].mean : 0.0;
+  const double mean = (MODE == ZM_TRUE || MODE == ZM_DIAG) ? st[rhs].mean : 0.0;
   const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
   // edge-load lanes: lane r < RY fetches the left edge of row r, lane 32 + r
   // the right edge
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     ed = eload ? p[base + erow] : 0.0;
   };
 
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   double pv[RY], cv[RY], nv[RY], nn[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = 0.0;
@@ -376,7 +384,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     }
     double ea[RY], eb[RY];
     const uint32_t pbase = (uint32_t)k * plane;
-    if (MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC) {
+    if (MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG) {
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         const int64_t idx = off + pbase + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
@@ -426,6 +434,13 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           const double rr = (ea[r] - mean) - wv;
           a0 += rr * rr;
           a1 += cc;
+        } else if (MODE == ZM_DIAG) {
+          const double h = ea[r] - mean;
+          const double rr = h - wv;
+          a0 += rr * rr;
+          a1 += cc;
+          a2 += cc * wv;
+          a3 += cc * h;
         } else if (MODE == ZM_JAC) {
           const double d = diag_1d(i, nx, bcx) + diag_1d(y0 + r, ny, bcy) +
                            (three ? diag_1d(k, nz, bcz) : 0.0);
@@ -454,6 +469,10 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     double v[2] = {a0, a1};
     const int sl[2] = {S_DOT, S_SUM};
     write_partials<2>(v, sl, part, rhs, b);
+  } else if (MODE == ZM_DIAG) {
+    double v[4] = {a0, a1, a2, a3};
+    const int sl[4] = {S_SQ, S_SUM, S_DOT, S_AUX};
+    write_partials<4>(v, sl, part, rhs, b);
   } else {
     double v[2] = {a0, a1};
     const int sl[2] = {S_SQ, S_SUM};
@@ -495,6 +514,11 @@ __global__ __launch_bounds__(VT) void k_fin_alpha(Geom g, const double* part, Rh
   if (!isfinite(v[0])) { s.done = NONFINITE; return; }
   if (!(v[0] > 0.0)) { s.done = BREAKDOWN; return; }
   s.alpha = s.rho / v[0];                                  // alpha_s
+  // alpha_s rho_{s-1}: the decrease of ||U - u||_L^2 in this iteration
+  // (Hestenes-Stiefel), for the A-norm stopping rule
+  const double t = s.alpha * s.rho;
+  s.hs_sum += t;
+  s.hs_ring[(s.iter + 1) % HS_DELAY] = t;
 }
 
 __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsState* st,
@@ -514,7 +538,17 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   s.rel_res = sqrt(v[1] / s.h2);
   if (hist) hist[(int64_t)rhs * hist_stride + s.iter] = s.rel_res;
   if (!isfinite(s.rel_res)) { s.done = NONFINITE; return; }
-  if ((flags & F_RESIDUAL_ONLY) && s.rel_res <= tol) { s.done = CONVERGED; return; }
+  if (flags & F_ANORM_STOP) {
+    // relative L-norm error of U_{s-d}, estimated by the last d terms over
+    // all of them (their sum estimates ||u||_L^2 from U_0 = 0)
+    if (s.iter >= HS_DELAY && s.hs_sum > 0.0) {
+      const double w = (s.hs_ring[0] + s.hs_ring[1]) + (s.hs_ring[2] + s.hs_ring[3]);
+      if (sqrt(w / s.hs_sum) <= tol) { s.done = CONVERGED; return; }
+    }
+  } else if ((flags & F_RESIDUAL_ONLY) && s.rel_res <= tol) {
+    s.done = CONVERGED;
+    return;
+  }
   set_scale(s, v[1], (double)g.N);
 }
 
@@ -766,6 +800,40 @@ void launch_field(const Geom& g, const double* u, double* eps, const double* fac
                   hipStream_t s) {
   const int G = (int)std::min<int64_t>((g.N + VT - 1) / VT, 4096);
   hipLaunchKernelGGL(k_field, dim3(G, batch), dim3(VT), 0, s, g, u, eps, faces);
+}
+
+// ---------------------------------------------------------- diagnostics ----
+// Descriptors of iterate U_s (Experiment 5.4) into row s of the table:
+// true relative residual, kappa_s = <U, L U> - 2 <U, h>, null-space
+// component |sum U| / sqrt(N) (singular operators; 0 otherwise) and the
+// Hestenes-Stiefel term alpha_s rho_{s-1} (0 at s = 0).
+__global__ __launch_bounds__(VT) void k_fin_diag(Geom g, const double* part, RhsState* st,
+                                                 double* diag, int stride, int G) {
+  const int rhs = blockIdx.x;
+  if (st[rhs].iter <= st[rhs].diag_iter) return;
+  double v[4];
+  const int sl[4] = {S_SQ, S_SUM, S_DOT, S_AUX};
+  read_partials<4>(part, rhs, sl, G, v);
+  if (threadIdx.x != 0) return;
+  RhsState& s = st[rhs];
+  double* row = diag + ((int64_t)rhs * stride + s.iter) * DIAG_RAW;
+  row[0] = s.h2 > 0.0 ? sqrt(v[0] / s.h2) : 0.0;
+  row[1] = v[2] - 2.0 * v[3];
+  row[2] = g.singular ? fabs(v[1]) / sqrt((double)g.N) : 0.0;
+  row[3] = s.iter > 0 ? s.alpha * s.rho : 0.0;
+  s.diag_iter = s.iter;
+}
+
+void launch_diag(const Geom& g, const double* eta, const double* U, double* part, RhsState* st,
+                 double* diag, int stride, int batch, hipStream_t s) {
+  const ZGrid z = zgrid_for(g);
+  trace_begin(KC_DIAG, s);
+  hipLaunchKernelGGL(k_zm<ZM_DIAG>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, U,
+                     (double*)nullptr, (double*)nullptr, (double*)nullptr, eta, part,
+                     (const RhsState*)st, 0.0);
+  hipLaunchKernelGGL(k_fin_diag, dim3(batch), dim3(VT), 0, s, g, part, st, diag, stride,
+                     z.nblocks);
+  trace_end(KC_DIAG, s);
 }
 
 // ------------------------------------------------------------- timing ----

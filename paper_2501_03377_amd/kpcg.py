@@ -30,6 +30,12 @@ KP_FLAG_NO_PRECOND = 1
 KP_FLAG_FLEX_BETA = 2
 KP_FLAG_RESIDUAL_ONLY = 4
 KP_FLAG_NO_GRAPH = 8
+KP_FLAG_DIAGNOSTICS = 16
+KP_FLAG_ANORM_STOP = 32
+KP_DIAG_COLUMNS = 7
+# Columns of kp_plan_diagnostics.
+DIAG_COLUMNS = ("true_rel_res", "rel_res", "kappa", "error_proxy", "null_component",
+                "hs_term", "hs_error_estimate")
 
 # Every symbol declared in include/kpcg.h.
 EXPORTS = (
@@ -41,8 +47,9 @@ EXPORTS = (
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
+    "kp_plan_diagnostics",
 )
-KERNEL_CLASSES = 15
+KERNEL_CLASSES = 16
 
 
 class KpResult(ctypes.Structure):
@@ -150,6 +157,7 @@ def _load():
         "kp_kernel_class_name": (ctypes.c_char_p, [i]),
         "kp_plan_autotune": (i, [vp, i, i, ctypes.POINTER(ctypes.c_int)]),
         "kp_plan_time_kernel": (i, [vp, i, i, i, i, pd]),
+        "kp_plan_diagnostics": (i, [vp, pd, i, i, i]),
         "kp_plan_get_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_set_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_graph_count": (i, [vp]),
@@ -276,6 +284,13 @@ def kp_plan_time_kernel(handle, cls, batch, flags, reps):
     rc = _lib.kp_plan_time_kernel(handle, int(cls), int(batch), int(flags), int(reps),
                                   ctypes.byref(ms))
     return rc, ms.value
+
+
+def kp_plan_diagnostics(handle, batch, hs, delay):
+    out = np.zeros((batch, hs, KP_DIAG_COLUMNS))
+    rc = _lib.kp_plan_diagnostics(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  int(batch), int(hs), int(delay))
+    return rc, out
 
 
 def kp_plan_get_tuning(handle):
@@ -530,9 +545,20 @@ class Plan:
         hist = np.zeros((batch, max_iter + 1))
         rc = kp_solve(self._h, eta.data_ptr(), u.data_ptr(), batch, tol, max_iter, flags,
                       results, hist)
+        self._last_shape = (batch, max_iter + 1)
         if rc < 0 and raise_on_error:
             raise KpError(rc, "kp_solve")
         return u, [r.as_dict() for r in results], hist, rc
+
+    def diagnostics(self, delay=4):
+        """Descriptors of every iterate of the last solve, which must have
+        used KP_FLAG_DIAGNOSTICS: a (batch, max_iter+1, 7) array with the
+        columns DIAG_COLUMNS (NaN after a right-hand side's last iterate)."""
+        batch, hs = getattr(self, "_last_shape", (0, 0))
+        rc, out = kp_plan_diagnostics(self._h, max(batch, 1), max(hs, 1), delay)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_plan_diagnostics")
+        return out
 
 
 class Server:

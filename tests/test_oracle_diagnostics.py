@@ -135,3 +135,30 @@ def test_plotted_proxy_passes_through_the_first_true_residual():
     curve = plotted_proxy(d[:, 1], d[1, 0])
     assert abs(curve[1] - (d[1, 0] + 2.0 ** -52)) <= 1e-15
     assert curve.min() == 2.0 ** -52
+
+
+@pytest.mark.parametrize("precond", [None, "jacobi"])
+def test_anorm_stopping_rule(precond):
+    # Remark 4.2's A-norm stopping: the rule first holds at s*, the returned
+    # U_{s*} meets the tolerance in the L-norm (dense check), the estimate is
+    # a lower bound on the error of U_{s*-d}, and the terms add up to ||u||_L^2
+    from oracle.diagnostics import hs_stop_iteration
+    shape, bcs = (12, 10, 9), ("D", "N", "D")
+    H = _field(shape, 18)
+    L = np.asarray(oracle.kronecker_sum(shape, bcs))
+    ustar = _vec(oracle.dense_pinv_solve(H, bcs))
+    unorm = np.sqrt(ustar @ L @ ustar)
+    M = JacobiPreconditioner(shape, bcs, 3, 1.3) if precond else None
+    tol, d = 1e-6, 4
+    r = oracle.pcg(H, bcs, precond=M, max_iter=300, stall=10**6, true_tol=0.0)
+    t = np.array(r.diagnostics)[:, 3]
+    s = hs_stop_iteration(t, tol, d)
+    assert s is not None and s > d
+    for q in range(d, s):
+        assert np.sqrt(t[q - d + 1:q + 1].sum() / t[1:q + 1].sum()) > tol
+    err = lambda q: np.sqrt(max((e := _vec(oracle.pcg(H, bcs, precond=M, fixed_iterations=q).u)
+                                 - ustar) @ L @ e, 0.0))
+    assert err(s) <= tol * unorm
+    est = np.sqrt(t[s - d + 1:s + 1].sum())
+    assert est <= err(s - d) * (1 + 1e-8)
+    assert abs(t[1:].sum() - unorm ** 2) <= 1e-8 * unorm ** 2
