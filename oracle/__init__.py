@@ -26,6 +26,8 @@ Modules
   bcdata     right-hand side update for non-homogeneous Dirichlet / Neumann
              data (Sec. 3.4.2) and the field eps = -grad u (Sec. 1).
   jacobi     Jacobi(p, omega) preconditioner (Sec. 4.3.1, Algs. 2-3).
+  lowrank    low-Kronecker-rank approximation of the pseudoinverse (Sec.
+             4.3.2, 2D only).
   diagnostics  convergence descriptors of Experiment 5.4 (true residual,
              kappa_s, null-space component) and the Hestenes-Stiefel error
              estimate that Remark 4.2 points to.
