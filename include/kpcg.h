@@ -195,13 +195,37 @@ int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol,
  *                      p >= 1, omega >= 1 (the paper's experiment uses
  *                      p = 3, omega = 1.3); solves with it stop on the
  *                      relative residual alone (M(R) is no error estimate)
+ *   KP_PRECOND_LOWRANK the low-Kronecker-rank approximation of the
+ *                      pseudoinverse (Sec. 4.3.2), 2D plans only: `steps` =
+ *                      the Kronecker rank r, 1 <= r <= min(KP_LOWRANK_MAX, nx,
+ *                      ny).  The best rank-r approximation G_r of the
+ *                      Hadamard pseudoinverse (eq. 4.7) is computed on the
+ *                      host at this call (kp_lowrank_table) and kept on the
+ *                      device (nx*ny doubles); the operator
+ *                      sum_rho M_{q,rho} (x) M_{n,rho} is applied in its
+ *                      factored form, the pseudoinverse's mode products with
+ *                      G_r in place of Ghat.  It may be indefinite for
+ *                      1 < r < min(nx, ny), as the paper notes; solves stop
+ *                      on the relative residual alone
  * (KP_FLAG_NO_PRECOND still selects M = I per solve.)  Jacobi needs one more
  * FP64 grid of workspace per right-hand side (kp_plan_workspace_bytes
  * follows the current choice); a library-owned workspace is reallocated, a
  * caller-provided one that is too small gives KP_ENOMEM and leaves the
  * choice unchanged.  Returns KP_OK, KP_EINVAL or KP_ENOMEM. */
-enum kp_precond { KP_PRECOND_PINV = 0, KP_PRECOND_JACOBI = 1 };
+enum kp_precond { KP_PRECOND_PINV = 0, KP_PRECOND_JACOBI = 1, KP_PRECOND_LOWRANK = 2 };
+#define KP_LOWRANK_MAX 16
 int kp_plan_set_preconditioner(kp_plan* plan, int kind, int steps, double omega);
+
+/* The low-rank preconditioner's factor (Sec. 4.3.2), host only, no GPU: the
+ * best rank-r approximation G_r (Eckart-Young-Mirsky) of the n x q Hadamard
+ * pseudoinverse g_ij = 1/(lambda_i(L_n) + lambda_j(L_q)) (0 where the sum is
+ * below 1e-13 in modulus; eigenvalues in kp_basis_1d's order for bc_n and
+ * bc_q), written to table[j*n + i] (n*q doubles, caller-owned).  Computed by
+ * block subspace iteration with r + 6 columns and a Rayleigh-Ritz step, in
+ * O(n q (r + 6)) work per iteration.  Returns KP_OK, or KP_EINVAL for bad
+ * sizes, boundary conditions, r outside 1..min(KP_LOWRANK_MAX, n, q) or a
+ * NULL table. */
+int kp_lowrank_table(int n, int bc_n, int q, int bc_q, int rank, double* table);
 
 /* Z = M(R) with the plan's preconditioner (pinv or Jacobi); device
  * pointers, batch grids each, not overlapping; enqueued on the plan's

@@ -21,7 +21,12 @@ struct PinvOps {
   const void* Bb[3];    // V_l^T packed for the backward product
   const double* lam[3]; // eigenvalues (FP64)
   int cfg[6];           // tile configuration of each mode product, in order
+  const double* gtab = nullptr;   // 2D low-rank preconditioner: G_r in place of Ghat
 };
+
+// G_r, the best rank-r approximation of the 2D Hadamard pseudoinverse with
+// g_ij = 1/(ln_i + lq_j) (kp_lowrank.cpp, host), to tab[j*n + i]; 0 or -1.
+int lowrank_table(const double* ln, int n, const double* lq, int q, int r, double* tab);
 
 // Mode-product kernel configuration and packed operator layout (kp_modeprod.hip).
 int mp_num_configs();

@@ -172,6 +172,8 @@ __device__ __forceinline__ typename MT<PREC>::chunk load_b(const u4* __restrict_
 //   X     input  [rhs][rows][K]  (type Ti)
 //   Y     output [rhs][K][rows]  (type To): Y[n*rows + r] = sum_k X[r][k] B[k][n]
 //   G epilogue (lc != nullptr): times ghat(la[r % a1] + lb[r / a1] + lc[n])
+//   table epilogue (gt != nullptr): times gt[n * rows + r], a precomputed
+//   factor in the output's layout (the low-rank preconditioner's G_r)
 //   in_scale / out_scale: per-RHS power-of-two scale on the input / its
 //   inverse on the output (low-precision range guard)
 // Grid: x = row blocks * column chunks, y = right-hand side.
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
     const u4* __restrict__ Bpk, int npk, int ncc, const Ti* __restrict__ X, To* __restrict__ Y,
     int K, int rows, int64_t N, const RhsState* __restrict__ st, int in_scale, int out_scale,
     const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
-    int a1) {
+    int a1, const double* __restrict__ gt) {
   using M = MT<PREC>;
   constexpr int NT = 64 * WR * WC;
   constexpr int CW = 16 * WN;                 // columns per wave
@@ -367,6 +369,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
             val = fabs(sum) < 1e-13 ? 0.0 : (double)((float)val * __frcp_rn((float)sum));
           }
         }
+        if (gt) val *= gt[(int64_t)n * rows + (rr[v] < rows ? rr[v] : 0)];
         if (out_scale) val *= oscale;
         if constexpr (sizeof(To) == 2) out[v] = (__bf16)(float)val;
         else out[v] = (To)val;
@@ -519,7 +522,7 @@ template <int PREC, class Ti, class To, int WN, int WM, int WC, bool VEC>
 static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int rows,
                        int batch, const RhsState* st, int in_scale, int out_scale,
                        const double* la, const double* lb, const double* lc, int a1,
-                       hipStream_t s) {
+                       const double* gt, hipStream_t s) {
   const int K = op.n[ax];
   const int cb = 16 * WN * WC, ncc = (K + cb - 1) / cb;
   constexpr int BR = WR * 16 * WM;
@@ -529,14 +532,14 @@ static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void*
   dim3 grid(nrb * ncc, batch);
   hipLaunchKernelGGL((mp_kernel<PREC, Ti, To, WN, WM, WC, VEC>), grid, dim3(64 * WR * WC), 0, s,
                      (const u4*)(fwd ? op.Bf[ax] : op.Bb[ax]), npk, ncc, (const Ti*)X, (To*)Y, K,
-                     rows, (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1);
+                     rows, (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1, gt);
 }
 
 template <int PREC, class Ti, class To>
 static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, const void* X,
                       void* Y, int batch, const RhsState* st, int in_scale, int out_scale,
                       const double* la, const double* lb, const double* lc, int a1,
-                      hipStream_t s) {
+                      const double* gt, hipStream_t s) {
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
   const int CH = MT<PREC>::CH;
@@ -545,14 +548,14 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
     // rows too ragged for 16-byte loads: one scalar-load tile serves every
     // configuration (such grids are small)
     launch_cfg<PREC, Ti, To, 4, 2, 2, false>(op, ax, fwd, X, Y, rows, batch, st, in_scale,
-                                             out_scale, la, lb, lc, a1, s);
+                                             out_scale, la, lb, lc, a1, gt, s);
     trace_end(cls, s);
     return;
   }
 #define KP_CASE(ID, W, M_, C)                                                                 \
   case ID:                                                                                    \
     launch_cfg<PREC, Ti, To, W, M_, C, true>(op, ax, fwd, X, Y, rows, batch, st, in_scale,    \
-                                             out_scale, la, lb, lc, a1, s);                   \
+                                             out_scale, la, lb, lc, a1, gt, s);               \
     break;
 #define KP_COMMON_CASES                                                                      \
   KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(4, 6, 2, 1)             \
@@ -598,12 +601,12 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
   trace_end(cls, s);
 }
 
-// Z = M(R) for `batch` right-hand sides.  R and Z are FP64 grids in the
-// natural layout; T0 and T1 are scratch grids in the compute type.
-// Product q of one application (Algs. 6-7) with the solver's buffers: R ->
-// T0 -> T1 -> T0 ... -> Z.  The first product scales its input per
-// right-hand side and the last unscales its output (not in FP64); the last
-// forward one carries the Hadamard factor.
+// Product q of one application Z = M(R) (Algs. 6-7) for `batch` right-hand
+// sides with the solver's buffers: R -> T0 -> T1 -> T0 ... -> Z (R and Z FP64
+// in the natural layout, T0 and T1 in the compute type).  The first product
+// scales its input per right-hand side and the last unscales its output (not
+// in FP64); the last forward one carries the Hadamard factor, Ghat from the
+// eigenvalues or, for the low-rank preconditioner, the table op.gtab.
 template <int PREC>
 static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, void* T0,
                         void* T1, int batch, const RhsState* st, hipStream_t s) {
@@ -618,16 +621,19 @@ static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, vo
                       : (ax == 0 ? KC_MP_X_BWD : (ax == 1 ? KC_MP_Y_BWD : KC_MP_Z_BWD));
   if (q == 0) {
     launch_mp<PREC, double, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, scl, 0, nullptr,
-                                nullptr, nullptr, 1, s);
+                                nullptr, nullptr, 1, nullptr, s);
   } else if (q == last) {
     launch_mp<PREC, tc, double>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, scl, nullptr,
-                                nullptr, nullptr, 1, s);
+                                nullptr, nullptr, 1, nullptr, s);
+  } else if (q == dim - 1 && op.gtab) {
+    launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, nullptr,
+                            nullptr, nullptr, 1, op.gtab, s);
   } else if (q == dim - 1) {
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, op.lam[0],
-                            dim == 3 ? op.lam[1] : nullptr, op.lam[dim - 1], op.n[0], s);
+                            dim == 3 ? op.lam[1] : nullptr, op.lam[dim - 1], op.n[0], nullptr, s);
   } else {
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, nullptr,
-                            nullptr, nullptr, 1, s);
+                            nullptr, nullptr, 1, nullptr, s);
   }
 }
 
@@ -654,13 +660,13 @@ static void product_t(const PinvOps& op, int q, const void* in, void* out, int b
                       : (ax == 0 ? KC_MP_X_BWD : (ax == 1 ? KC_MP_Y_BWD : KC_MP_Z_BWD));
   if (q == 0)
     launch_mp<PREC, double, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la,
-                                lb, lc, op.n[0], s);
+                                lb, lc, op.n[0], nullptr, s);
   else if (q == 2 * dim - 1)
     launch_mp<PREC, tc, double>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la,
-                                lb, lc, op.n[0], s);
+                                lb, lc, op.n[0], nullptr, s);
   else
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la, lb,
-                            lc, op.n[0], s);
+                            lc, op.n[0], nullptr, s);
 }
 
 void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch,

@@ -135,6 +135,8 @@ struct kp_plan {
   double jac_omega = 1.3;
   double* faces_dev = nullptr;        // boundary data of kp_assemble_rhs / kp_field
   size_t faces_cap = 0;               // doubles
+  double* lr_dev = nullptr;           // G_r of the low-rank preconditioner, [ny][nx] (2D)
+  int lr_rank = 0;                    // its rank (0: not built)
 };
 
 namespace {
@@ -254,6 +256,10 @@ void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int b
   } else if (p->pc_kind == KP_PRECOND_JACOBI) {
     launch_jacobi(p->g, R, Z, (double*)(base + L.J), p->jac_p, p->jac_omega, st, batch,
                   vec_blocks(p->g.N, batch), s);
+  } else if (p->pc_kind == KP_PRECOND_LOWRANK) {
+    PinvOps op = p->op;
+    op.gtab = p->lr_dev;
+    pinv_apply(op, R, Z, base + L.T0, base + L.T1, batch, st, s);
   } else {
     pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, s);
   }
@@ -411,6 +417,7 @@ void kp_plan_destroy(kp_plan* p) {
   if (p->resident) (void)hipFree(p->resident);
   if (p->st_host) (void)hipHostFree(p->st_host);
   if (p->faces_dev) (void)hipFree(p->faces_dev);
+  if (p->lr_dev) (void)hipFree(p->lr_dev);
   delete p;
 }
 
@@ -479,7 +486,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
   // Jacobi(p, omega) approximates L^{-1} too loosely for M(R) to estimate
   // the error either
-  if (p->pc_kind == KP_PRECOND_JACOBI) flags |= KP_FLAG_RESIDUAL_ONLY;
+  if (p->pc_kind == KP_PRECOND_JACOBI || p->pc_kind == KP_PRECOND_LOWRANK)
+    flags |= KP_FLAG_RESIDUAL_ONLY;
   int rc = ensure_workspace(p);
   if (rc != KP_OK) return rc;
   const int hs = max_iter + 1;
@@ -687,11 +695,44 @@ int kp_plan_diagnostics(const kp_plan* p, double* out, int batch, int hs, int de
   return KP_OK;
 }
 
+int kp_lowrank_table(int n, int bc_n, int q, int bc_q, int rank, double* table) {
+  if (n < 3 || q < 3 || bc_n < 0 || bc_n > 4 || bc_q < 0 || bc_q > 4 || !table) return KP_EINVAL;
+  if (rank < 1 || rank > std::min(KP_LOWRANK_MAX, std::min(n, q))) return KP_EINVAL;
+  std::vector<double> Qn((size_t)n * n), Qq((size_t)q * q), ln(n), lq(q);
+  if (basis_1d(n, bc_n, Qn.data(), ln.data()) != 0 || basis_1d(q, bc_q, Qq.data(), lq.data()) != 0)
+    return KP_EINVAL;
+  return lowrank_table(ln.data(), n, lq.data(), q, rank, table) == 0 ? KP_OK : KP_EINVAL;
+}
+
 int kp_plan_set_preconditioner(kp_plan* p, int kind, int steps, double omega) {
-  if (!p || (kind != KP_PRECOND_PINV && kind != KP_PRECOND_JACOBI)) return KP_EINVAL;
+  if (!p || (kind != KP_PRECOND_PINV && kind != KP_PRECOND_JACOBI && kind != KP_PRECOND_LOWRANK))
+    return KP_EINVAL;
   if (kind == KP_PRECOND_JACOBI &&
       (steps < 1 || steps > 10000 || !(omega >= 1.0) || !std::isfinite(omega)))
     return KP_EINVAL;
+  if (kind == KP_PRECOND_LOWRANK) {
+    if (p->g.dim != 2) return KP_EINVAL;   // no 3D analogue (Sec. 4.3.2)
+    if (steps < 1 || steps > std::min(KP_LOWRANK_MAX, std::min(p->g.nx, p->g.ny)))
+      return KP_EINVAL;
+    if (steps != p->lr_rank) {
+      const size_t n = (size_t)p->g.nx * p->g.ny;
+      std::vector<double> tab(n);
+      const int rc = kp_lowrank_table(p->g.nx, p->g.bc[0], p->g.ny, p->g.bc[1], steps, tab.data());
+      if (rc != KP_OK) return rc;
+      if (p->stream) (void)hipStreamSynchronize(p->stream);
+      if (p->own) (void)hipStreamSynchronize(p->own);
+      std::lock_guard<std::mutex> lk(api_mutex());
+      if (!p->lr_dev && !ok(hipMalloc((void**)&p->lr_dev, n * sizeof(double)))) {
+        p->lr_dev = nullptr;
+        return KP_ENOMEM;
+      }
+      if (!ok(hipMemcpy(p->lr_dev, tab.data(), n * sizeof(double), hipMemcpyHostToDevice))) {
+        p->lr_rank = 0;
+        return KP_EHIP;
+      }
+      p->lr_rank = steps;
+    }
+  }
   const int old_kind = p->pc_kind;
   p->pc_kind = kind;
   const size_t need = layout_for(p, p->max_batch).total;

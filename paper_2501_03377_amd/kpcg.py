@@ -47,7 +47,7 @@ EXPORTS = (
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
-    "kp_plan_diagnostics",
+    "kp_plan_diagnostics", "kp_lowrank_table",
 )
 KERNEL_CLASSES = 16
 
@@ -158,6 +158,7 @@ def _load():
         "kp_plan_autotune": (i, [vp, i, i, ctypes.POINTER(ctypes.c_int)]),
         "kp_plan_time_kernel": (i, [vp, i, i, i, i, pd]),
         "kp_plan_diagnostics": (i, [vp, pd, i, i, i]),
+        "kp_lowrank_table": (i, [i, i, i, i, i, pd]),
         "kp_plan_get_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_set_tuning": (i, [vp, ctypes.POINTER(ctypes.c_int), i]),
         "kp_plan_graph_count": (i, [vp]),
@@ -291,6 +292,17 @@ def kp_plan_diagnostics(handle, batch, hs, delay):
     rc = _lib.kp_plan_diagnostics(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   int(batch), int(hs), int(delay))
     return rc, out
+
+
+def kp_lowrank_table(n, bc_n, q, bc_q, rank):
+    """G_r of the low-rank preconditioner as an (q, n) array (host only)."""
+    out = np.zeros((q, n))
+    code = lambda bc: BC[bc] if isinstance(bc, str) else int(bc)
+    rc = _lib.kp_lowrank_table(int(n), code(bc_n), int(q), code(bc_q), int(rank),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != KP_OK:
+        raise KpError(rc, "kp_lowrank_table")
+    return out
 
 
 def kp_plan_get_tuning(handle):
@@ -497,8 +509,9 @@ class Plan:
         return f, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
     def set_preconditioner(self, kind="pinv", steps=3, omega=1.3):
-        """'pinv' (default) or 'jacobi' with p = steps and omega."""
-        code = {"pinv": 0, "jacobi": 1}[kind]
+        """'pinv' (default), 'jacobi' with p = steps and omega, or 'lowrank'
+        (2D) with Kronecker rank = steps."""
+        code = {"pinv": 0, "jacobi": 1, "lowrank": 2}[kind]
         rc = _lib.kp_plan_set_preconditioner(self._h, code, int(steps), float(omega))
         if rc != KP_OK:
             raise KpError(rc, "kp_plan_set_preconditioner")
