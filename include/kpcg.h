@@ -92,7 +92,10 @@ typedef struct {
   int32_t reserved;
   double rel_res;         /* ||R_s|| / ||eta_c||, recursive residual */
   double true_rel_res;    /* ||eta_c - L u|| / ||eta_c|| recomputed at exit */
-  double err_est;         /* ||Z_s|| / ||U_s||; Z_s approximates the error */
+  double err_est;         /* relative error estimate at exit: ||Z_s|| / ||U_s||
+                             (Z_s approximates the error), or the bound
+                             ||R_s|| / (lambda_min ||U_s||) when that stopped
+                             the solve (see kp_solve) */
   double removed_mean;    /* mean of eta projected out (singular operators) */
 } kp_result;
 
@@ -167,7 +170,12 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * (Remark 4.1), and u is returned with zero mean: the minimum-norm solution.
  * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
  * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
- * set, also ||Z_s||/||U_s|| <= tol (Z_s = M(R_s) estimates the error of U_s).
+ * set, also the relative error of U_s is certified <= tol: first by the
+ * bound ||U_s - u|| <= ||R_s|| / lambda_min (lambda_min the smallest nonzero
+ * eigenvalue of the Kronecker sum, from the closed-form spectra), which costs
+ * nothing; if that does not suffice, by the estimate ||Z_s||/||U_s|| <= tol
+ * after the next preconditioner application (Z_s = M(R_s) estimates the
+ * error of U_s).
  * With KP_FLAG_ANORM_STOP the rule is instead the A-norm error estimate that
  * Remark 4.2 recommends (Hestenes-Stiefel, as analysed by Strakos and Tichy):
  * with t_j = alpha_j rho_{j-1}, iteration s >= d stops when

@@ -49,6 +49,7 @@ struct Geom {
   int bc[3];
   int64_t N;
   int singular;
+  double lam_min;   // smallest nonzero eigenvalue of the Kronecker sum
 };
 
 // Vector-kernel launchers (kp_vector.hip).  `part` holds NSLOTS x G block

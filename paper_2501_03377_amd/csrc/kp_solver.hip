@@ -346,6 +346,7 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     offL[a] = bytes; bytes += align_up((size_t)n[a] * 8);
   }
   std::vector<char> host(bytes, 0);
+  double lam0[3] = {0.0, 0.0, 0.0}, lam1[3] = {INFINITY, INFINITY, INFINITY};
   for (int a = 0; a < dim; ++a) {
     const int na = n[a];
     std::vector<double> Q((size_t)na * na), Qt((size_t)na * na), lam(na);
@@ -355,6 +356,26 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     mp_pack(Q.data(), na, prec, host.data() + offF[a]);
     mp_pack(Qt.data(), na, prec, host.data() + offB[a]);
     std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
+    // smallest eigenvalue of the axis, and its smallest nonzero one
+    double m0 = INFINITY, m1 = INFINITY;
+    for (double l : lam) {
+      m0 = std::min(m0, l);
+      if (l > 1e-13) m1 = std::min(m1, l);
+    }
+    lam0[a] = m0;
+    lam1[a] = m1;
+  }
+  // The eigenvalues of the Kronecker sum are the sums over the axes (eq. 3.3):
+  // the smallest is the sum of the smallest; if that is zero (a singular
+  // set, each axis having a zero eigenvalue), the smallest nonzero one adds
+  // one axis's smallest nonzero eigenvalue to zeros.
+  {
+    double sum0 = 0.0, best1 = INFINITY;
+    for (int a = 0; a < dim; ++a) {
+      sum0 += lam0[a];
+      best1 = std::min(best1, lam1[a]);
+    }
+    p->g.lam_min = sum0 > 1e-13 ? sum0 : best1;
   }
   std::lock_guard<std::mutex> alk(api_mutex());   // held until the plan is complete
   if (!ok(hipMalloc(&p->resident, bytes))) { delete p; return KP_ENOMEM; }

@@ -548,6 +548,16 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   } else if ((flags & F_RESIDUAL_ONLY) && s.rel_res <= tol) {
     s.done = CONVERGED;
     return;
+  } else if (!(flags & F_RESIDUAL_ONLY) && s.rel_res <= tol && v[2] > 0.0) {
+    // the error U_s - u = -L^+ R_s has norm at most ||R_s|| / lambda_min:
+    // when this bound already meets tol, the error estimate ||Z_s|| / ||U_s||
+    // and the preconditioner application it needs are skipped
+    const double bound = sqrt(v[1] / v[2]) / g.lam_min;
+    if (bound <= tol) {
+      s.err_est = bound;
+      s.done = CONVERGED;
+      return;
+    }
   }
   set_scale(s, v[1], (double)g.N);
 }

@@ -188,3 +188,24 @@ def test_graph_replays_match_eager(prec, profile):
         assert prof["stencil_dot"][1] > 0
     else:
         assert kp_plan_graph_count(plan._h) >= 1
+
+
+@pytest.mark.parametrize("shape,bcs", [((5, 6, 7), ("D", "N", "DN")), ((6, 5, 7), ("P", "N", "N")),
+                                       ((8, 9), ("ND", "P")), ((7, 4, 6), ("P", "P", "P"))])
+def test_error_bound_stop(shape, bcs):
+    # an FP64 solve stops on the free bound ||R_s|| / (lambda_min ||U_s||)
+    # without the last preconditioner application; the reported bound is
+    # >= the actual error, and the lambda_min it used is the smallest
+    # nonzero eigenvalue of the assembled Kronecker sum (eq. 3.3)
+    eta = np.random.default_rng(12).standard_normal(shape)
+    u, res, hist, rc = _solve(eta, bcs, tol=1e-10)
+    r = res[0]
+    assert rc == 0 and r["pinv_applications"] == r["iterations"]
+    ref = oracle_solve(eta, bcs)
+    uz = _zero_mean_if(u, bcs)
+    err = rel(uz, ref)
+    assert err <= r["err_est"] <= 1e-10
+    h = eta - eta.mean() if oracle.is_singular(bcs) else eta
+    lam_min = r["rel_res"] * np.linalg.norm(h) / (r["err_est"] * np.linalg.norm(uz))
+    ev = np.linalg.eigvalsh(np.asarray(oracle.kronecker_sum(eta.T.shape, bcs)))
+    assert abs(lam_min - ev[ev > 1e-10].min()) <= 1e-9 * lam_min
