@@ -170,12 +170,17 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * (Remark 4.1), and u is returned with zero mean: the minimum-norm solution.
  * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
  * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
- * set, also the relative error of U_s is certified <= tol: first by the
- * bound ||U_s - u|| <= ||R_s|| / lambda_min (lambda_min the smallest nonzero
- * eigenvalue of the Kronecker sum, from the closed-form spectra), which costs
- * nothing; if that does not suffice, by the estimate ||Z_s||/||U_s|| <= tol
- * after the next preconditioner application (Z_s = M(R_s) estimates the
- * error of U_s).
+ * set, also the relative error of U_s is certified <= tol, by the first of:
+ *   - the bound ||U_s - u|| <= ||R_s|| / lambda_min (lambda_min the smallest
+ *     nonzero eigenvalue of the Kronecker sum, from the closed-form spectra),
+ *     which costs nothing;
+ *   - the sharper bound ||U_s - u||^2 <= sum_box rhat^2 / lambda^2 +
+ *     (||R_s||^2 - sum_box rhat^2) / theta^2, where rhat are the exact
+ *     coefficients of R_s on the box of the min(n_a, 32) lowest eigenmodes
+ *     per axis and theta the smallest eigenvalue outside the box (three
+ *     small FP64 GEMMs, about one read of R_s);
+ *   - the estimate ||Z_s||/||U_s|| <= tol after the next preconditioner
+ *     application (Z_s = M(R_s) estimates the error of U_s).
  * With KP_FLAG_ANORM_STOP the rule is instead the A-norm error estimate that
  * Remark 4.2 recommends (Hestenes-Stiefel, as analysed by Strakos and Tichy):
  * with t_j = alpha_j rho_{j-1}, iteration s >= d stops when
@@ -303,7 +308,7 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
  * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
  * products of Algs. 6-7, ...).  Timing adds two event records per launch;
  * while it is on, kp_solve launches every kernel directly (no graph replay). */
-#define KP_KERNEL_CLASSES 16
+#define KP_KERNEL_CLASSES 17
 int kp_plan_set_profiling(kp_plan* plan, int enable);
 /* Synchronises the plan's stream, then returns the accumulated milliseconds
  * and launch count of one class.  KP_EINVAL for a bad class. */

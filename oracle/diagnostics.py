@@ -83,3 +83,40 @@ def hs_stop_iteration(terms, tol, delay=4):
         if total > 0.0 and np.sqrt(float(np.sum(t[s - delay + 1:s + 1])) / total) <= tol:
             return s
     return None
+
+
+def lowmode_error_bound(R, U, bcs, m=32):
+    """Relative error bound of an iterate U with residual R (the
+    certificate the solver uses before its error estimate):
+        ||L^+ R||^2 <= sum_box rhat^2 / lambda^2 + (||R||^2 - sum_box rhat^2) / theta^2
+    divided by ||U||, where rhat are the coefficients of R on the box of the
+    min(n_a, m) eigenmodes of smallest eigenvalue per axis (eigenvectors from
+    LAPACK), lambda their eigenvalue sums (null modes skipped) and theta the
+    smallest eigenvalue sum outside the box (exact when the box is
+    everything).  L^+ R is the error of U when R = H - L U (eqs. 3.3, 4.6)."""
+    from .laplacian import laplacian_1d
+    R = np.asarray(R, dtype=np.float64)
+    lams, Vs, ms = [], [], []
+    for n, bc in zip(R.shape, bcs):
+        lam, V = np.linalg.eigh(laplacian_1d(n, bc))
+        lams.append(lam)
+        Vs.append(V)
+        ms.append(min(n, m))
+    rhat = R
+    for a in range(R.ndim):
+        rhat = np.moveaxis(np.tensordot(rhat, Vs[a][:, :ms[a]], axes=([a], [0])), -1, a)
+    lb = np.zeros(rhat.shape)
+    for a in range(R.ndim):
+        sh = [1] * R.ndim
+        sh[a] = ms[a]
+        lb = lb + lams[a][:ms[a]].reshape(sh)
+    pos = np.abs(lb) > 1e-13
+    low = float(np.sum(np.where(pos, rhat ** 2 / np.where(pos, lb, 1.0) ** 2, 0.0)))
+    box = float(np.sum(rhat ** 2))
+    theta = np.inf
+    for a in range(R.ndim):
+        if ms[a] < R.shape[a]:
+            theta = min(theta, lams[a][ms[a]] + sum(lams[b][0] for b in range(R.ndim) if b != a))
+    rest = max(float(np.sum(R * R)) - box, 0.0)
+    tail = rest / theta ** 2 if np.isfinite(theta) else 0.0
+    return np.sqrt(low + tail) / float(np.linalg.norm(U))

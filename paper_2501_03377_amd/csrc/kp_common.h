@@ -53,6 +53,7 @@ struct RhsState {
   int done;           // Done code
   int pinv_count;     // preconditioner applications so far
   int diag_iter;      // last iterate whose descriptors were recorded (-1: none)
+  int need_cert;      // residual small enough, error bound still to be certified
 };
 
 // Reduction slots written by the vector and mode-product kernels, one block

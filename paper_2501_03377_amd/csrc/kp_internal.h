@@ -68,6 +68,20 @@ bool zgrid_fits(const Geom& g);
 // [batch][stride][DIAG_RAW] table (Experiment 5.4), for every right-hand
 // side whose iterate s is not yet recorded.
 constexpr int DIAG_RAW = 4;
+// Low-mode error certificate.  The error U_s - u = -L^+ R_s has squared norm
+// sum_m rhat_m^2 / lambda_m^2 over the eigenmodes m of the Kronecker sum;
+// the coefficients of the box of the m_a <= CERT_M lowest modes per axis are
+// computed exactly (three small FP64 GEMMs on the matrix cores) and every
+// other mode is bounded by 1/theta^2, theta the smallest eigenvalue outside
+// the box.
+constexpr int CERT_M = 32;
+struct CertOps {
+  const double* V[3];   // per axis [n_a][CERT_M]: its m_a lowest eigenvectors, zero-padded
+  const double* w;      // [CERT_M][CERT_M][CERT_M] (z, y, x): 1/lambda^2 in the box, else 0
+  double theta2inv;     // 1/theta^2, or 0 when the box holds every mode
+};
+void launch_cert(const Geom& g, const CertOps& c, const double* R, double* C1, double* C2,
+                 double* C3, RhsState* st, int batch, double tol, hipStream_t s);
 void launch_diag(const Geom& g, const double* eta, const double* U, double* part, RhsState* st,
                  double* diag, int stride, int batch, hipStream_t s);
 // Timing support: fills n doubles with a fixed pseudo-random pattern in
@@ -93,12 +107,14 @@ void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int 
 void launch_copy(const Geom& g, const double* src, double* dst, const RhsState* st, int batch,
                  int G, hipStream_t s);
 
-// Solve flags (mirrors include/kpcg.h).
+// Solve flags (mirrors include/kpcg.h), plus internal ones above the public
+// range.
 enum {
   F_NO_PRECOND = 1,
   F_FLEX_BETA = 2,
   F_RESIDUAL_ONLY = 4,
   F_ANORM_STOP = 32,
+  F_CERT = 1 << 16,   // the low-mode error certificate runs after the residual test
 };
 
 }  // namespace kp
@@ -123,6 +139,7 @@ enum KernelClass {
   KC_COPY,          // Z = R when M = I
   KC_JACOBI,        // Jacobi(p, omega) preconditioner steps
   KC_DIAG,          // convergence descriptors of the iterate (diagnostic solves)
+  KC_CERT,          // low-mode error certificate
   KC_COUNT
 };
 

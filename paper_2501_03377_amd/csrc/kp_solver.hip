@@ -135,6 +135,7 @@ struct kp_plan {
   double jac_omega = 1.3;
   double* faces_dev = nullptr;        // boundary data of kp_assemble_rhs / kp_field
   size_t faces_cap = 0;               // doubles
+  CertOps cert{};                     // low-mode error certificate (in `resident`)
   double* lr_dev = nullptr;           // G_r of the low-rank preconditioner, [ny][nx] (2D)
   int lr_rank = 0;                    // its rank (0: not built)
 };
@@ -156,7 +157,7 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_BF16 ? 2 : 4); }
 
 struct Layout {
-  size_t R, P, W, Z, T0, T1, J, part, st, total;
+  size_t R, P, W, Z, T0, T1, J, C1, C2, C3, part, st, total;
 };
 
 Layout layout_for(const kp_plan* p, int batch) {
@@ -172,6 +173,12 @@ Layout layout_for(const kp_plan* p, int batch) {
   L.T0 = take(N * elem_bytes(p->prec));
   L.T1 = take(N * elem_bytes(p->prec));
   L.J = p->pc_kind == KP_PRECOND_JACOBI ? take(N * 8) : 0;   // Jacobi ping-pong buffer
+  // low-mode certificate: box coefficients after the x, y (and z) products
+  const size_t rows1 = (size_t)(p->g.N / p->g.nx);
+  const size_t nzp = p->g.dim == 3 ? (size_t)p->g.nz : 1;
+  L.C1 = take((size_t)batch * rows1 * CERT_M * 8);
+  L.C2 = take((size_t)batch * nzp * CERT_M * CERT_M * 8);
+  L.C3 = p->g.dim == 3 ? take((size_t)batch * CERT_M * CERT_M * CERT_M * 8) : 0;
   (void)G;
   L.part = take((size_t)batch * NSLOTS * 8192 * 8);   // GMAX partials per slot
   L.st = take((size_t)batch * sizeof(RhsState));
@@ -339,12 +346,17 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   const int n[3] = {nx, ny, nz};
   size_t bytes = 0;
   size_t offF[3] = {0, 0, 0}, offB[3] = {0, 0, 0}, offL[3] = {0, 0, 0};
+  size_t offV[3] = {0, 0, 0};
   for (int a = 0; a < dim; ++a) {
     const size_t pb = mp_packed_bytes(n[a], prec);
     offF[a] = bytes; bytes += align_up(pb);
     offB[a] = bytes; bytes += align_up(pb);
     offL[a] = bytes; bytes += align_up((size_t)n[a] * 8);
+    offV[a] = bytes; bytes += align_up((size_t)n[a] * CERT_M * 8);
   }
+  const size_t offW = bytes;
+  bytes += align_up((size_t)CERT_M * CERT_M * CERT_M * 8);
+  std::vector<double> lam_axis[3];
   std::vector<char> host(bytes, 0);
   double lam0[3] = {0.0, 0.0, 0.0}, lam1[3] = {INFINITY, INFINITY, INFINITY};
   for (int a = 0; a < dim; ++a) {
@@ -356,6 +368,12 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     mp_pack(Q.data(), na, prec, host.data() + offF[a]);
     mp_pack(Qt.data(), na, prec, host.data() + offB[a]);
     std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
+    // the m_a lowest eigenvectors (columns of Q, eigenvalues ascending)
+    const int ma = std::min(na, CERT_M);
+    double* Vl = (double*)(host.data() + offV[a]);
+    for (int x = 0; x < na; ++x)
+      for (int i = 0; i < ma; ++i) Vl[(size_t)x * CERT_M + i] = Q[(size_t)x * na + i];
+    lam_axis[a] = lam;
     // smallest eigenvalue of the axis, and its smallest nonzero one
     double m0 = INFINITY, m1 = INFINITY;
     for (double l : lam) {
@@ -376,6 +394,29 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
       best1 = std::min(best1, lam1[a]);
     }
     p->g.lam_min = sum0 > 1e-13 ? sum0 : best1;
+  }
+  // certificate weights 1/lambda^2 over the box of the m_a lowest modes per
+  // axis (0 for the null mode), and theta, the smallest eigenvalue outside
+  {
+    const int mx = std::min(nx, CERT_M), my = std::min(ny, CERT_M);
+    const int mz = dim == 3 ? std::min(nz, CERT_M) : 1;
+    double* w = (double*)(host.data() + offW);
+    for (int k = 0; k < mz; ++k)
+      for (int j = 0; j < my; ++j)
+        for (int i = 0; i < mx; ++i) {
+          const double l = lam_axis[0][i] + lam_axis[1][j] + (dim == 3 ? lam_axis[2][k] : 0.0);
+          w[((size_t)k * CERT_M + j) * CERT_M + i] = l > 1e-13 ? 1.0 / (l * l) : 0.0;
+        }
+    const int m[3] = {mx, my, mz};
+    double theta = INFINITY;
+    for (int a = 0; a < dim; ++a) {
+      if (m[a] >= n[a]) continue;
+      double t = lam_axis[a][m[a]];
+      for (int b = 0; b < dim; ++b)
+        if (b != a) t += lam_axis[b][0];
+      theta = std::min(theta, t);
+    }
+    p->cert.theta2inv = std::isfinite(theta) ? 1.0 / (theta * theta) : 0.0;
   }
   std::lock_guard<std::mutex> alk(api_mutex());   // held until the plan is complete
   if (!ok(hipMalloc(&p->resident, bytes))) { delete p; return KP_ENOMEM; }
@@ -399,11 +440,13 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
       p->op.Bf[a] = (char*)p->resident + offF[a];
       p->op.Bb[a] = (char*)p->resident + offB[a];
       p->op.lam[a] = (const double*)((char*)p->resident + offL[a]);
+      p->cert.V[a] = (const double*)((char*)p->resident + offV[a]);
     } else {
       p->op.Bf[a] = p->op.Bb[a] = nullptr;
       p->op.lam[a] = nullptr;
     }
   }
+  p->cert.w = (const double*)((char*)p->resident + offW);
   if (!ok(hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking)) ||
       !ok(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming))) {
     if (p->own) (void)hipStreamDestroy(p->own);
@@ -509,6 +552,10 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   // the error either
   if (p->pc_kind == KP_PRECOND_JACOBI || p->pc_kind == KP_PRECOND_LOWRANK)
     flags |= KP_FLAG_RESIDUAL_ONLY;
+  // the low-mode certificate backs the residual test unless the error test
+  // is off
+  const bool cert = !(flags & (KP_FLAG_RESIDUAL_ONLY | KP_FLAG_ANORM_STOP));
+  if (cert) flags |= F_CERT;
   int rc = ensure_workspace(p);
   if (rc != KP_OK) return rc;
   const int hs = max_iter + 1;
@@ -558,6 +605,9 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     for (int q = 0; q < n; ++q) {
       launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
       if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
+      if (cert)
+        launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
+                    p->g.dim == 3 ? (double*)(base + L.C3) : nullptr, st, batch, tol, s);
       precondition(p, L, R, Z, batch, flags, st, s);
       launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
     }
@@ -1017,7 +1067,7 @@ const char* kp_kernel_class_name(int cls) {
   static const char* names[KC_COUNT] = {
       "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
       "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
-      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi", "diagnostics"};
+      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi", "diagnostics", "certificate"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
 }
 

@@ -551,13 +551,15 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   } else if (!(flags & F_RESIDUAL_ONLY) && s.rel_res <= tol && v[2] > 0.0) {
     // the error U_s - u = -L^+ R_s has norm at most ||R_s|| / lambda_min:
     // when this bound already meets tol, the error estimate ||Z_s|| / ||U_s||
-    // and the preconditioner application it needs are skipped
+    // and the preconditioner application it needs are skipped; otherwise
+    // the sharper low-mode bound is tried next
     const double bound = sqrt(v[1] / v[2]) / g.lam_min;
     if (bound <= tol) {
       s.err_est = bound;
       s.done = CONVERGED;
       return;
     }
+    s.need_cert = (flags & F_CERT) ? 1 : 0;
   }
   set_scale(s, v[1], (double)g.N);
 }
@@ -844,6 +846,126 @@ void launch_diag(const Geom& g, const double* eta, const double* U, double* part
   hipLaunchKernelGGL(k_fin_diag, dim3(batch), dim3(VT), 0, s, g, part, st, diag, stride,
                      z.nblocks);
   trace_end(KC_DIAG, s);
+}
+
+// ---------------------------------------------------------- certificate ----
+// D(r, c) = sum_k A(r, k) B(k, c) per plane p and right-hand side, with
+// arbitrary strides, in FP64 on the matrix cores: one wave per 16 x 32 tile
+// of D (two 16 x 16 fragments), k in steps of 4.  Operand layout of
+// v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, k0 + l / 16) and
+// B(k0 + l / 16, l % 16); result element v of lane l is D(4 v + l / 16, l % 16).
+struct SmallGemm {
+  const double* A; int64_t a_r, a_k, a_p, a_rhs;
+  const double* B; int64_t b_k, b_c, b_p, b_rhs;
+  double* D; int64_t d_r, d_c, d_p, d_rhs;
+  int rows, cols, K, planes;
+};
+
+__global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* st) {
+  const int rhs = blockIdx.y;
+  if (!st[rhs].need_cert) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rtn = (q.rows + 15) / 16, ctn = (q.cols + 31) / 32;
+  const int64_t w = (int64_t)blockIdx.x * (VT / 64) + wave;
+  if (w >= (int64_t)rtn * ctn * q.planes) return;              // wave-uniform
+  const int p = (int)(w / ((int64_t)rtn * ctn));
+  const int rem = (int)(w % ((int64_t)rtn * ctn));
+  const int rt = rem % rtn, ct = rem / rtn;
+  const int l16 = lane & 15, grp = lane >> 4;
+  const int r = rt * 16 + l16;
+  const bool rok = r < q.rows;
+  const double* A = q.A + rhs * q.a_rhs + p * q.a_p + (int64_t)(rok ? r : 0) * q.a_r;
+  const double* B = q.B + rhs * q.b_rhs + p * q.b_p;
+  const int c0 = ct * 32 + l16, c1 = c0 + 16;
+  const bool c0ok = c0 < q.cols, c1ok = c1 < q.cols;
+  const double* B0 = B + (int64_t)(c0ok ? c0 : 0) * q.b_c;
+  const double* B1 = B + (int64_t)(c1ok ? c1 : 0) * q.b_c;
+  d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < q.K; k0 += 4) {
+    const int k = k0 + grp;
+    const bool kok = k < q.K;
+    const int kc = kok ? k : 0;
+    double a = A[(int64_t)kc * q.a_k];
+    double b0 = B0[(int64_t)kc * q.b_k];
+    double b1 = B1[(int64_t)kc * q.b_k];
+    a = (rok && kok) ? a : 0.0;
+    b0 = (c0ok && kok) ? b0 : 0.0;
+    b1 = (c1ok && kok) ? b1 : 0.0;
+    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+  }
+  double* D = q.D + rhs * q.d_rhs + p * q.d_p;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = rt * 16 + 4 * v + grp;
+    if (row >= q.rows) continue;
+    if (c0ok) D[(int64_t)row * q.d_r + (int64_t)c0 * q.d_c] = acc0[v];
+    if (c1ok) D[(int64_t)row * q.d_r + (int64_t)c1 * q.d_c] = acc1[v];
+  }
+}
+
+// The bound from the box coefficients C (nbox per right-hand side, zero
+// outside the box): ||L^+ R||^2 <= sum_box rhat^2 / lambda^2
+// + (||R||^2 - sum_box rhat^2) / theta^2, relative to ||U_s||.
+__global__ __launch_bounds__(VT) void k_cert_fin(const double* C, int nbox, const double* w,
+                                                 double theta2inv, RhsState* st, double tol) {
+  const int rhs = blockIdx.x;
+  if (!st[rhs].need_cert) return;
+  const double* c = C + (int64_t)rhs * nbox;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nbox; b += VT) {
+    const double x2 = c[b] * c[b];
+    v[0] += x2 * w[b];
+    v[1] += x2;
+  }
+  __shared__ double lds[4 * 2];
+  block_sum<2>(v, lds);
+  if (threadIdx.x != 0) return;
+  RhsState& s = st[rhs];
+  s.need_cert = 0;
+  const double rest = s.rr - v[1];
+  const double bound = sqrt((v[0] + (rest > 0.0 ? rest : 0.0) * theta2inv) / s.uu);
+  if (bound <= tol) {
+    s.err_est = bound;
+    s.done = CONVERGED;
+  }
+}
+
+void launch_cert(const Geom& g, const CertOps& c, const double* R, double* C1, double* C2,
+                 double* C3, RhsState* st, int batch, double tol, hipStream_t s) {
+  const int M = CERT_M;
+  const int64_t rows1 = g.N / g.nx;                 // (z, y) rows of R
+  const int nzp = g.dim == 3 ? g.nz : 1;
+  auto run = [&](const SmallGemm& q) {
+    const int64_t waves = (int64_t)((q.rows + 15) / 16) * ((q.cols + 31) / 32) * q.planes;
+    const int blocks = (int)((waves + VT / 64 - 1) / (VT / 64));
+    hipLaunchKernelGGL(k_cert_gemm, dim3(blocks, batch), dim3(VT), 0, s, q, (const RhsState*)st);
+  };
+  trace_begin(KC_CERT, s);
+  // x: C1[(z, y)][i] = sum_x R[(z, y)][x] Vx[x][i]
+  run({R, g.nx, 1, 0, g.N,
+       c.V[0], M, 1, 0, 0,
+       C1, M, 1, 0, rows1 * M,
+       (int)rows1, M, g.nx, 1});
+  // y, per z-plane: C2[z][j][i] = sum_y Vy[y][j] C1[(z, y)][i]
+  run({c.V[1], 1, M, 0, 0,
+       C1, M, 1, (int64_t)g.ny * M, rows1 * M,
+       C2, M, 1, (int64_t)M * M, (int64_t)nzp * M * M,
+       M, M, g.ny, nzp});
+  const double* box = C2;
+  if (g.dim == 3) {
+    // z: C3[k][(j, i)] = sum_z Vz[z][k] C2[z][(j, i)]
+    run({c.V[2], 1, M, 0, 0,
+         C2, (int64_t)M * M, 1, 0, (int64_t)nzp * M * M,
+         C3, (int64_t)M * M, 1, 0, (int64_t)M * M * M,
+         M, M * M, g.nz, 1});
+    box = C3;
+  }
+  const int nbox = g.dim == 3 ? M * M * M : M * M;
+  hipLaunchKernelGGL(k_cert_fin, dim3(batch), dim3(VT), 0, s, box, nbox, c.w, c.theta2inv, st,
+                     tol);
+  trace_end(KC_CERT, s);
 }
 
 // ------------------------------------------------------------- timing ----

@@ -209,3 +209,26 @@ def test_error_bound_stop(shape, bcs):
     lam_min = r["rel_res"] * np.linalg.norm(h) / (r["err_est"] * np.linalg.norm(uz))
     ev = np.linalg.eigvalsh(np.asarray(oracle.kronecker_sum(eta.T.shape, bcs)))
     assert abs(lam_min - ev[ev > 1e-10].min()) <= 1e-9 * lam_min
+
+
+@pytest.mark.parametrize("prec,shape,bcs", [("f32", (64, 96, 80), ("P", "P", "DN")),
+                                            ("bf16x6", (40, 48, 56), ("N", "N", "P")),
+                                            ("f32", (100, 120), ("D", "N"))])
+def test_lowmode_certificate_stop(prec, shape, bcs):
+    # a mixed-precision solve stops on the low-mode bound, without the
+    # preconditioner application of the error estimate; the bound it reports
+    # is the oracle's bound on the returned iterate and lies above its actual
+    # error
+    from oracle.diagnostics import lowmode_error_bound
+    eta = synth.charge_field(shape, ncharges=400, seed=13)
+    u, res, hist, rc = _solve(eta, bcs, prec=prec, tol=1e-10)
+    r = res[0]
+    assert rc == 0 and r["pinv_applications"] == r["iterations"], r
+    uh = u
+    h = eta - eta.mean() if oracle.is_singular(bcs) else eta
+    R = h.T - oracle.apply_minus_laplacian(uh.T, bcs)
+    ref = oracle_solve(eta, bcs)
+    err = rel(uh, ref)
+    assert err <= r["err_est"] <= 1e-10
+    b = lowmode_error_bound(R, uh.T, bcs, 32)
+    assert abs(b - r["err_est"]) <= 1e-3 * b, (b, r["err_est"])

@@ -162,3 +162,27 @@ def test_anorm_stopping_rule(precond):
     est = np.sqrt(t[s - d + 1:s + 1].sum())
     assert est <= err(s - d) * (1 + 1e-8)
     assert abs(t[1:].sum() - unorm ** 2) <= 1e-8 * unorm ** 2
+
+
+@pytest.mark.parametrize("shape,bcs,m", [((9, 8, 10), ("P", "P", "DN"), 4), ((12, 10), ("N", "D"), 5),
+                                         ((7, 6, 5), ("N", "N", "P"), 3)])
+def test_lowmode_bound(shape, bcs, m):
+    # an upper bound on the true relative error ||L^+ R|| / ||U||, exact when
+    # the box holds every mode, and never weaker than ||R|| / lambda_min
+    from oracle.diagnostics import lowmode_error_bound
+    rng = np.random.default_rng(19)
+    H = rng.standard_normal(shape)
+    if oracle.is_singular(bcs):
+        H -= H.mean()
+    ustar = oracle.dense_pinv_solve(H, bcs)
+    U = ustar + 1e-3 * rng.standard_normal(shape)
+    R = H - oracle.apply_minus_laplacian(U, bcs)
+    if oracle.is_singular(bcs):
+        R -= R.mean()
+    err = np.linalg.norm(oracle.dense_pinv_solve(R, bcs)) / np.linalg.norm(U)
+    b = lowmode_error_bound(R, U, bcs, m)
+    assert err <= b * (1 + 1e-12)
+    assert abs(lowmode_error_bound(R, U, bcs, max(shape)) - err) <= 1e-10 * err
+    ev = np.linalg.eigvalsh(np.asarray(oracle.kronecker_sum(shape, bcs)))
+    crude = np.linalg.norm(R) / ev[ev > 1e-10].min() / np.linalg.norm(U)
+    assert b <= crude * (1 + 1e-12)
