@@ -80,8 +80,11 @@ struct CertOps {
   const double* w;      // [CERT_M][CERT_M][CERT_M] (z, y, x): 1/lambda^2 in the box, else 0
   double theta2inv;     // 1/theta^2, or 0 when the box holds every mode
 };
+// C1 and C2 hold the coefficients after the x and y products, `part`
+// CERT_PARTS doubles per right-hand side for the per-tile sums of the box.
+constexpr int CERT_PARTS = 2 * 2 * CERT_M;   // two sums per tile, at most 2 * CERT_M tiles
 void launch_cert(const Geom& g, const CertOps& c, const double* R, double* C1, double* C2,
-                 double* C3, RhsState* st, int batch, double tol, hipStream_t s);
+                 double* part, RhsState* st, int batch, double tol, hipStream_t s);
 void launch_diag(const Geom& g, const double* eta, const double* U, double* part, RhsState* st,
                  double* diag, int stride, int batch, hipStream_t s);
 // Timing support: fills n doubles with a fixed pseudo-random pattern in

@@ -412,6 +412,8 @@ static const MpCfg kCfgs[] = {
     {2, 4, 2}, {3, 4, 2}, {4, 2, 2}, {4, 4, 2}, {6, 2, 2}, {8, 1, 2}, {8, 2, 2}, {16, 1, 2},
     // tall tiles (FP32 and BF16 accumulators only): fewer re-reads of the operator
     {16, 2, 1}, {8, 4, 2},
+    // short tiles of 128 columns: more blocks for short contractions
+    {8, 1, 1}, {4, 1, 2},
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
@@ -422,9 +424,9 @@ int mp_num_configs() { return kNumCfgs; }
 // fragments of 4 or more columns, in BF16 the 16 x 2 tile).
 bool mp_config_allowed(int id, int prec) {
   if (id < 0 || id >= kNumCfgs) return false;
-  if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || id >= 15);
+  if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
   if (prec == PREC_BF16) return id != 16;
-  if (prec == PREC_BF16X6) return !(id == 3 || id == 7 || id == 11 || id >= 15);
+  if (prec == PREC_BF16X6) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
   return true;
 }
 
@@ -560,7 +562,8 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
 #define KP_COMMON_CASES                                                                      \
   KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(4, 6, 2, 1)             \
   KP_CASE(5, 8, 2, 1) KP_CASE(6, 12, 1, 1) KP_CASE(8, 2, 4, 2) KP_CASE(9, 3, 4, 2)            \
-  KP_CASE(10, 4, 2, 2) KP_CASE(12, 6, 2, 2) KP_CASE(14, 8, 2, 2)
+  KP_CASE(10, 4, 2, 2) KP_CASE(12, 6, 2, 2) KP_CASE(14, 8, 2, 2)                            \
+  KP_CASE(18, 8, 1, 1) KP_CASE(19, 4, 1, 2)
   // tiles whose registers would spill are left out: FP64 accumulators and
   // operands are twice as wide, and the FP64-sourced BF16 product holds
   // 16 VGPRs of raw data per row fragment and k-block

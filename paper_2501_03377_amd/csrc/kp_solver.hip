@@ -104,6 +104,7 @@ struct kp_plan {
   RhsState* st_host = nullptr;  // pinned, mapped mirror of the state (written by the device)
   RhsState* st_dev = nullptr;   // its device address
   int expect_iters = 0;         // iterations the last solve needed (first chunk size)
+  bool expect_split = false;    // ... and whether it stopped before their last preconditioning
   bool profiling = false;
   Tracer tracer;
   hipStream_t own = nullptr;    // private stream of kp_solve (graph capture needs one)
@@ -178,7 +179,7 @@ Layout layout_for(const kp_plan* p, int batch) {
   const size_t nzp = p->g.dim == 3 ? (size_t)p->g.nz : 1;
   L.C1 = take((size_t)batch * rows1 * CERT_M * 8);
   L.C2 = take((size_t)batch * nzp * CERT_M * CERT_M * 8);
-  L.C3 = p->g.dim == 3 ? take((size_t)batch * CERT_M * CERT_M * CERT_M * 8) : 0;
+  L.C3 = take((size_t)batch * CERT_PARTS * 8);
   (void)G;
   L.part = take((size_t)batch * NSLOTS * 8192 * 8);   // GMAX partials per slot
   L.st = take((size_t)batch * sizeof(RhsState));
@@ -601,15 +602,25 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     precondition(p, L, R, Z, batch, flags, st, s);
     launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
   };
-  auto iterations = [&](int n) {
+  // An iteration in two parts: up to the residual test and certificate,
+  // then preconditioning and the updates that depend on it.
+  auto iteration_head = [&]() {
+    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
+    if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
+    if (cert)
+      launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
+                  (double*)(base + L.C3), st, batch, tol, s);
+  };
+  auto iteration_tail = [&]() {
+    precondition(p, L, R, Z, batch, flags, st, s);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
+  };
+  // n iterations; with `split` the last one stops after its residual test
+  // (its second part runs later, only if some right-hand side continues)
+  auto iterations = [&](int n, bool split) {
     for (int q = 0; q < n; ++q) {
-      launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
-      if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-      if (cert)
-        launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
-                    p->g.dim == 3 ? (double*)(base + L.C3) : nullptr, st, batch, tol, s);
-      precondition(p, L, R, Z, batch, flags, st, s);
-      launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
+      iteration_head();
+      if (!(split && q == n - 1)) iteration_tail();
     }
   };
   // exit step: true residual, centering of U, state to the mapped host mirror
@@ -660,14 +671,20 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   int done_iters = 0;
   int chunk = p->expect_iters > 0 ? p->expect_iters
               : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_BF16 ? 8 : 2)));
+  // a first chunk that ends where the previous solve stopped, before the
+  // last preconditioning, launches no kernels for finished right-hand sides
+  const bool split_first = p->expect_iters > 0 && p->expect_split;
+  bool pending_tail = false;    // second part of a split iteration still owed
   bool first = true;
   while (true) {
     const int n = std::min(chunk, max_iter - done_iters);
+    const bool split = first && split_first && n == chunk;
+    const int nkey = 2 * n + (split ? 1 : 0);
     bool launched = false;
     if (first && use_graphs) {
       if (repeat) {
-        const kp_plan::GraphKey key{batch, n, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
-        const int gi = graph_for(key, [&]() { head(); iterations(n); tail(); });
+        const kp_plan::GraphKey key{batch, nkey, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
+        const int gi = graph_for(key, [&]() { head(); iterations(n, split); tail(); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
           launched = true;
@@ -675,14 +692,14 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
       } else {
         head();
         // (the iterations read eta only for the descriptors)
-        const kp_plan::GraphKey key{batch, n,        flags,   hs,
+        const kp_plan::GraphKey key{batch, nkey,     flags,   hs,
                                     tol,   u,        p->hist_dev, diag_dev,
                                     diag ? eta : nullptr};
-        const int gi = graph_for(key, [&]() { iterations(n); });
+        const int gi = graph_for(key, [&]() { iterations(n, split); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
         } else {
-          iterations(n);
+          iterations(n, split);
         }
         tail();
         launched = true;
@@ -690,9 +707,11 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     }
     if (!launched) {
       if (first) head();
-      iterations(n);
+      if (pending_tail) iteration_tail();
+      iterations(n, split);
       tail();
     }
+    pending_tail = split;
     first = false;
     done_iters += n;
     if (!ok(hipGetLastError())) return KP_EHIP;
@@ -731,7 +750,17 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     else if (stt == KP_NOT_CONVERGED && worst == KP_OK) worst = stt;
     if (stt == KP_OK) max_it = std::max(max_it, x.iter);
   }
-  if (max_it > 0) p->expect_iters = max_it;
+  if (max_it > 0) {
+    p->expect_iters = max_it;
+    // split next time if every right-hand side that took max_it iterations
+    // stopped before preconditioning in its last one
+    bool split = true;
+    for (int b = 0; b < batch; ++b) {
+      const RhsState& x = p->st_host[b];
+      if (x.done == CONVERGED && x.iter == max_it && x.pinv_count > x.iter) split = false;
+    }
+    p->expect_split = split;
+  }
   return worst;
 }
 

@@ -362,10 +362,28 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     ed = eload ? p[base + erow] : 0.0;
   };
 
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  double pv[RY], cv[RY], nv[RY], nn[RY];
+  // the other streams of a mode (R and U, or eta, or R) at the cells of plane kk
+  constexpr bool XS = MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG;
+  auto extra = [&](int kk, double (&a)[RY], double (&b)[RY]) {
+    const uint32_t base = (uint32_t)kk * plane;
 #pragma unroll
-  for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = 0.0;
+    for (int r = 0; r < RY; ++r) {
+      const int64_t idx = off + base + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
+      if (MODE == ZM_UR) {
+        a[r] = R[idx];
+        b[r] = U[idx];
+      } else if (MODE == ZM_JAC) {
+        a[r] = R[idx];
+      } else {
+        a[r] = eta[idx];
+      }
+    }
+  };
+
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double pv[RY], cv[RY], nv[RY], nn[RY], ea[RY], eb[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = ea[r] = eb[r] = 0.0;
   double hlo = 0.0, hhi = 0.0, hed = 0.0;
   if (kb < ke) {
     if (three) {
@@ -374,30 +392,20 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     }
     centre(kb, cv);
     halo(kb, hlo, hhi, hed);
+    if (XS) extra(kb, ea, eb);
   }
   for (int k = kb; k < ke; ++k) {
-    // issue the loads of the next step
+    // issue the loads of the next step (the other streams one plane ahead)
     double nlo = 0.0, nhi = 0.0, ned = 0.0;
+    double na[RY], nb[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) na[r] = nb[r] = 0.0;
     if (k + 1 < ke) {
       if (three) centre(k + 2, nn);
       halo(k + 1, nlo, nhi, ned);
+      if (XS) extra(k + 1, na, nb);
     }
-    double ea[RY], eb[RY];
     const uint32_t pbase = (uint32_t)k * plane;
-    if (MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG) {
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const int64_t idx = off + pbase + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
-        if (MODE == ZM_UR) {
-          ea[r] = R[idx];
-          eb[r] = U[idx];
-        } else if (MODE == ZM_JAC) {
-          ea[r] = R[idx];
-        } else {
-          ea[r] = eta[idx];
-        }
-      }
-    }
     // x-neighbours from the adjacent lanes, tile edges from the edge lanes
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -455,6 +463,8 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
       pv[r] = cv[r];
       cv[r] = nv[r];
       nv[r] = nn[r];
+      ea[r] = na[r];
+      eb[r] = nb[r];
     }
     hlo = nlo;
     hhi = nhi;
@@ -850,15 +860,21 @@ void launch_diag(const Geom& g, const double* eta, const double* U, double* part
 
 // ---------------------------------------------------------- certificate ----
 // D(r, c) = sum_k A(r, k) B(k, c) per plane p and right-hand side, with
-// arbitrary strides, in FP64 on the matrix cores: one wave per 16 x 32 tile
-// of D (two 16 x 16 fragments), k in steps of 4.  Operand layout of
-// v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, k0 + l / 16) and
-// B(k0 + l / 16, l % 16); result element v of lane l is D(4 v + l / 16, l % 16).
+// arbitrary strides, in FP64 on the matrix cores.  A block owns one 16 x 32
+// tile of D (two 16 x 16 fragments); its four waves take interleaved blocks
+// of 16 k each and their partial tiles are added in a fixed order in LDS.
+// Operand layout of v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, k) and
+// B(k, l % 16) for the k of its group l / 16; result element v of lane l is
+// D(4 v + l / 16, l % 16).  Within a block of 16 k, group g takes
+// k = 4 g + step.
+// With w set, the tile is not stored: its sums sum d^2 w[i] and sum d^2
+// (i the element's index in D) go to part[rhs][tile][2] instead.
 struct SmallGemm {
   const double* A; int64_t a_r, a_k, a_p, a_rhs;
   const double* B; int64_t b_k, b_c, b_p, b_rhs;
   double* D; int64_t d_r, d_c, d_p, d_rhs;
   int rows, cols, K, planes;
+  const double* w; double* part;
 };
 
 __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* st) {
@@ -866,10 +882,8 @@ __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* s
   if (!st[rhs].need_cert) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rtn = (q.rows + 15) / 16, ctn = (q.cols + 31) / 32;
-  const int64_t w = (int64_t)blockIdx.x * (VT / 64) + wave;
-  if (w >= (int64_t)rtn * ctn * q.planes) return;              // wave-uniform
-  const int p = (int)(w / ((int64_t)rtn * ctn));
-  const int rem = (int)(w % ((int64_t)rtn * ctn));
+  const int tile = blockIdx.x;                       // < rtn * ctn * planes
+  const int p = tile / (rtn * ctn), rem = tile % (rtn * ctn);
   const int rt = rem % rtn, ct = rem / rtn;
   const int l16 = lane & 15, grp = lane >> 4;
   const int r = rt * 16 + l16;
@@ -881,19 +895,71 @@ __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* s
   const double* B0 = B + (int64_t)(c0ok ? c0 : 0) * q.b_c;
   const double* B1 = B + (int64_t)(c1ok ? c1 : 0) * q.b_c;
   d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int k0 = 0; k0 < q.K; k0 += 4) {
-    const int k = k0 + grp;
-    const bool kok = k < q.K;
-    const int kc = kok ? k : 0;
-    double a = A[(int64_t)kc * q.a_k];
-    double b0 = B0[(int64_t)kc * q.b_k];
-    double b1 = B1[(int64_t)kc * q.b_k];
-    a = (rok && kok) ? a : 0.0;
-    b0 = (c0ok && kok) ? b0 : 0.0;
-    b1 = (c1ok && kok) ? b1 : 0.0;
-    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+  const int nkb = (q.K + 15) / 16;
+  for (int kb = wave; kb < nkb; kb += VT / 64) {
+    // every load of the k-block first, then its eight MFMAs
+    double a[4], b0[4], b1[4];
+#pragma unroll
+    for (int st4 = 0; st4 < 4; ++st4) {
+      const int k = kb * 16 + 4 * grp + st4;
+      const bool kok = k < q.K;
+      const int kc = kok ? k : 0;
+      a[st4] = A[(int64_t)kc * q.a_k];
+      b0[st4] = B0[(int64_t)kc * q.b_k];
+      b1[st4] = B1[(int64_t)kc * q.b_k];
+      a[st4] = (rok && kok) ? a[st4] : 0.0;
+      b0[st4] = (c0ok && kok) ? b0[st4] : 0.0;
+      b1[st4] = (c1ok && kok) ? b1[st4] : 0.0;
+    }
+#pragma unroll
+    for (int st4 = 0; st4 < 4; ++st4) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st4], b0[st4], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st4], b1[st4], acc1, 0, 0, 0);
+    }
+  }
+  // waves 1..3 hand their tiles to wave 0, which adds them in order
+  __shared__ double red[3][8][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[wave - 1][v][lane] = acc0[v];
+      red[wave - 1][4 + v][lane] = acc1[v];
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc0[v] += red[w][v][lane];
+      acc1[v] += red[w][4 + v][lane];
+    }
+  if (q.w) {
+    double t[2] = {0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = rt * 16 + 4 * v + grp;
+      if (row >= q.rows) continue;
+      if (c0ok) {
+        const double x2 = acc0[v] * acc0[v];
+        t[0] += x2 * q.w[(int64_t)row * q.d_r + (int64_t)c0 * q.d_c];
+        t[1] += x2;
+      }
+      if (c1ok) {
+        const double x2 = acc1[v] * acc1[v];
+        t[0] += x2 * q.w[(int64_t)row * q.d_r + (int64_t)c1 * q.d_c];
+        t[1] += x2;
+      }
+    }
+    t[0] = wave_sum(t[0]);
+    t[1] = wave_sum(t[1]);
+    if (lane == 0) {
+      const int ntiles = rtn * ctn * q.planes;
+      q.part[((int64_t)rhs * ntiles + tile) * 2] = t[0];
+      q.part[((int64_t)rhs * ntiles + tile) * 2 + 1] = t[1];
+    }
+    return;
   }
   double* D = q.D + rhs * q.d_rhs + p * q.d_p;
 #pragma unroll
@@ -905,27 +971,26 @@ __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* s
   }
 }
 
-// The bound from the box coefficients C (nbox per right-hand side, zero
-// outside the box): ||L^+ R||^2 <= sum_box rhat^2 / lambda^2
-// + (||R||^2 - sum_box rhat^2) / theta^2, relative to ||U_s||.
-__global__ __launch_bounds__(VT) void k_cert_fin(const double* C, int nbox, const double* w,
+// The bound from the per-tile sums of the box coefficients:
+// ||L^+ R||^2 <= sum_box rhat^2 / lambda^2 + (||R||^2 - sum_box rhat^2) / theta^2,
+// relative to ||U_s||.
+__global__ __launch_bounds__(64) void k_cert_fin(const double* part, int ntiles,
                                                  double theta2inv, RhsState* st, double tol) {
   const int rhs = blockIdx.x;
   if (!st[rhs].need_cert) return;
-  const double* c = C + (int64_t)rhs * nbox;
-  double v[2] = {0.0, 0.0};
-  for (int b = threadIdx.x; b < nbox; b += VT) {
-    const double x2 = c[b] * c[b];
-    v[0] += x2 * w[b];
-    v[1] += x2;
+  const double* pp = part + (int64_t)rhs * ntiles * 2;
+  double low = 0.0, box = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += 64) {
+    low += pp[2 * t];
+    box += pp[2 * t + 1];
   }
-  __shared__ double lds[4 * 2];
-  block_sum<2>(v, lds);
+  low = wave_sum(low);
+  box = wave_sum(box);
   if (threadIdx.x != 0) return;
   RhsState& s = st[rhs];
   s.need_cert = 0;
-  const double rest = s.rr - v[1];
-  const double bound = sqrt((v[0] + (rest > 0.0 ? rest : 0.0) * theta2inv) / s.uu);
+  const double rest = s.rr - box;
+  const double bound = sqrt((low + (rest > 0.0 ? rest : 0.0) * theta2inv) / s.uu);
   if (bound <= tol) {
     s.err_est = bound;
     s.done = CONVERGED;
@@ -933,38 +998,40 @@ __global__ __launch_bounds__(VT) void k_cert_fin(const double* C, int nbox, cons
 }
 
 void launch_cert(const Geom& g, const CertOps& c, const double* R, double* C1, double* C2,
-                 double* C3, RhsState* st, int batch, double tol, hipStream_t s) {
+                 double* part, RhsState* st, int batch, double tol, hipStream_t s) {
   const int M = CERT_M;
   const int64_t rows1 = g.N / g.nx;                 // (z, y) rows of R
-  const int nzp = g.dim == 3 ? g.nz : 1;
   auto run = [&](const SmallGemm& q) {
-    const int64_t waves = (int64_t)((q.rows + 15) / 16) * ((q.cols + 31) / 32) * q.planes;
-    const int blocks = (int)((waves + VT / 64 - 1) / (VT / 64));
-    hipLaunchKernelGGL(k_cert_gemm, dim3(blocks, batch), dim3(VT), 0, s, q, (const RhsState*)st);
+    const int tiles = ((q.rows + 15) / 16) * ((q.cols + 31) / 32) * q.planes;
+    hipLaunchKernelGGL(k_cert_gemm, dim3(tiles, batch), dim3(VT), 0, s, q, (const RhsState*)st);
   };
   trace_begin(KC_CERT, s);
+  const int nzp = g.dim == 3 ? g.nz : 1;
   // x: C1[(z, y)][i] = sum_x R[(z, y)][x] Vx[x][i]
   run({R, g.nx, 1, 0, g.N,
        c.V[0], M, 1, 0, 0,
        C1, M, 1, 0, rows1 * M,
-       (int)rows1, M, g.nx, 1});
-  // y, per z-plane: C2[z][j][i] = sum_y Vy[y][j] C1[(z, y)][i]
-  run({c.V[1], 1, M, 0, 0,
-       C1, M, 1, (int64_t)g.ny * M, rows1 * M,
-       C2, M, 1, (int64_t)M * M, (int64_t)nzp * M * M,
-       M, M, g.ny, nzp});
-  const double* box = C2;
+       (int)rows1, M, g.nx, 1, nullptr, nullptr});
+  // y, per z-plane: C2[z][j][i] = sum_y Vy[y][j] C1[(z, y)][i]; in 2D this is
+  // the box, reduced at once into per-tile sums
+  const bool last_y = g.dim == 2;
+  const SmallGemm qy{c.V[1], 1, M, 0, 0,
+                     C1, M, 1, (int64_t)g.ny * M, rows1 * M,
+                     C2, M, 1, (int64_t)M * M, (int64_t)nzp * M * M,
+                     M, M, g.ny, nzp, last_y ? c.w : nullptr, last_y ? part : nullptr};
+  run(qy);
+  int ntiles = ((M + 15) / 16) * ((M + 31) / 32) * nzp;
   if (g.dim == 3) {
-    // z: C3[k][(j, i)] = sum_z Vz[z][k] C2[z][(j, i)]
-    run({c.V[2], 1, M, 0, 0,
-         C2, (int64_t)M * M, 1, 0, (int64_t)nzp * M * M,
-         C3, (int64_t)M * M, 1, 0, (int64_t)M * M * M,
-         M, M * M, g.nz, 1});
-    box = C3;
+    // z: box[k][(j, i)] = sum_z Vz[z][k] C2[z][(j, i)], reduced into per-tile sums
+    const SmallGemm qz{c.V[2], 1, M, 0, 0,
+                       C2, (int64_t)M * M, 1, 0, (int64_t)nzp * M * M,
+                       nullptr, (int64_t)M * M, 1, 0, 0,
+                       M, M * M, g.nz, 1, c.w, part};
+    run(qz);
+    ntiles = ((M + 15) / 16) * ((M * M + 31) / 32);
   }
-  const int nbox = g.dim == 3 ? M * M * M : M * M;
-  hipLaunchKernelGGL(k_cert_fin, dim3(batch), dim3(VT), 0, s, box, nbox, c.w, c.theta2inv, st,
-                     tol);
+  hipLaunchKernelGGL(k_cert_fin, dim3(batch), dim3(64), 0, s, (const double*)part, ntiles,
+                     c.theta2inv, st, tol);
   trace_end(KC_CERT, s);
 }
 
