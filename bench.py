@@ -197,8 +197,10 @@ def solve_work(name, grid, results, flex=False):
     the last forward product (z in 3D, y in 2D), so that the six add up to
     Table 2's 4N(nx+ny+nz) + N; or ('byte', B) for an HBM-bound vector
     kernel, FP64 words moved per unknown times 8 N.  A RHS that converged
-    after s iterations used s + 1 pinv applications p (one at start, one per
-    iteration) and s stencil and U/R updates; its last P update is skipped."""
+    after s iterations used p pinv applications (one at start, one per
+    iteration, except a last iteration that stopped on the residual test
+    and error bound) and s stencil and U/R updates; when the last
+    application was followed by the stop, its P update is skipped."""
     nx, ny, nz = grid
     N = nx * ny * nz
     tot = 0.0
@@ -215,7 +217,10 @@ def solve_work(name, grid, results, flex=False):
         elif name == "dot_rz":           # reads R, Z (and W for the flexible beta)
             tot += p * (2 + flex) * 8.0 * N
         elif name == "update_p":         # P_0 = Z_0: 2 words; P = Z + beta P: 3 words
-            tot += (2 + 3 * max(p - 2, 0)) * 8.0 * N if p >= 2 else 0.0
+            # one P update per application, except after the last when the
+            # solve stopped on the error estimate that followed it
+            nu = p - (1 if p > s else 0)
+            tot += (2 + 3 * (nu - 1)) * 8.0 * N if nu >= 1 else 0.0
         else:
             return None, 0.0
     return ("flop" if name in MODEPROD else "byte"), tot

@@ -98,9 +98,9 @@ __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict
 
 __global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, RhsState* st, int G) {
   const int rhs = blockIdx.x;
-  double v[1];
+  double v[1] = {0.0};
   const int sl[1] = {S_SUM};
-  read_partials<1>(part, rhs, sl, G, v);
+  if (g.singular) read_partials<1>(part, rhs, sl, G, v);   // no mean to remove otherwise
   if (threadIdx.x == 0) {
     RhsState s = {};
     s.mean = g.singular ? v[0] / (double)g.N : 0.0;
@@ -624,9 +624,11 @@ int vec_blocks(int64_t N, int batch) {
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s) {
   dim3 grid(G, batch);
-  trace_begin(KC_INIT, s);
-  hipLaunchKernelGGL(k_eta_sum, grid, dim3(VT), 0, s, g, eta, part, G);
-  trace_end(KC_INIT, s);
+  if (g.singular) {   // the mean of eta (eq. 3.6); a nonsingular set keeps eta as it is
+    trace_begin(KC_INIT, s);
+    hipLaunchKernelGGL(k_eta_sum, grid, dim3(VT), 0, s, g, eta, part, G);
+    trace_end(KC_INIT, s);
+  }
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_mean, dim3(batch), dim3(VT), 0, s, g, part, st, G);
   trace_end(KC_FINALIZE, s);
