@@ -199,11 +199,13 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   constexpr int CH = M::CH, NV = M::NV, KB = 4 * CH;
   constexpr int UNITS = 4 * NV * CB;          // 16-byte units per operator k-block
   // k-blocks per LDS stage (one barrier per stage), at most 32 KiB per stage
-  // (two stages resident).  The data rows are prefetched one stage ahead in a
+  // (two stages resident), 64 KiB for the eight-wave tiles, which run one
+  // block per CU anyway.  The data rows are prefetched one stage ahead in a
   // register ring of KS k-blocks indexed by the unrolled step, so no register
-  // ever moves inside the ring.
+  // ever moves inside the ring; larger stages prefetch further ahead.
   constexpr int KSP = PREC == PREC_F64 ? 2 : 4;
-  constexpr int KSL = 32768 / (16 * UNITS) > 0 ? 32768 / (16 * UNITS) : 1;
+  constexpr int SBYTES = (WC == 2 && WM < 4) ? 65536 : 32768;
+  constexpr int KSL = SBYTES / (16 * UNITS) > 0 ? SBYTES / (16 * UNITS) : 1;
   constexpr int KS = KSP < KSL ? KSP : KSL;
   constexpr int SUNITS = KS * UNITS;          // units per stage
   constexpr int UPT = (SUNITS + NT - 1) / NT; // units per thread per stage
