@@ -243,8 +243,9 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 // the two tile-edge columns of the 4 rows are fetched by one load in which
 // 8 lanes take part and broadcast with readlane; the y-neighbours of the
 // inner rows are the lane's own registers and only the rows above and below
-// the strip are loaded.  Every load for plane k+1 (and the centres of plane
-// k+2) is issued before plane k is computed.  Blocks are mapped to work
+// the strip are loaded.  The centre loads of plane k+2, the halo loads of
+// plane k+2 (k+1 in the U/R update) and the other streams of plane k+1 are
+// issued before plane k is computed.  Blocks are mapped to work
 // XCD-aware: the hardware deals blocks to the 8 XCDs round robin, and block
 // b is given work item (b % 8) * share + b / 8, so that each XCD sweeps a
 // contiguous range of plane groups and finds the neighbours in its own L2.
@@ -384,7 +385,11 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   double pv[RY], cv[RY], nv[RY], nn[RY], ea[RY], eb[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = ea[r] = eb[r] = 0.0;
-  double hlo = 0.0, hhi = 0.0, hed = 0.0;
+  // halo lookahead in planes: two, except for the U/R update, whose extra
+  // streams leave no registers for it at four waves per SIMD
+  constexpr int HA = MODE == ZM_UR ? 1 : 2;
+  double hlo = 0.0, hhi = 0.0, hed = 0.0;      // halo of plane k
+  double h1lo = 0.0, h1hi = 0.0, h1ed = 0.0;   // halo of plane k + 1 (HA == 2)
   if (kb < ke) {
     if (three) {
       centre(kb - 1, pv);
@@ -392,19 +397,21 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     }
     centre(kb, cv);
     halo(kb, hlo, hhi, hed);
+    if (HA == 2 && kb + 1 < ke) halo(kb + 1, h1lo, h1hi, h1ed);
     if (XS) extra(kb, ea, eb);
   }
   for (int k = kb; k < ke; ++k) {
-    // issue the loads of the next step (the other streams one plane ahead)
+    // issue the loads of later steps: centres and halos two planes ahead,
+    // the other streams one plane ahead
     double nlo = 0.0, nhi = 0.0, ned = 0.0;
     double na[RY], nb[RY];
 #pragma unroll
     for (int r = 0; r < RY; ++r) na[r] = nb[r] = 0.0;
     if (k + 1 < ke) {
       if (three) centre(k + 2, nn);
-      halo(k + 1, nlo, nhi, ned);
       if (XS) extra(k + 1, na, nb);
     }
+    if (k + HA < ke) halo(k + HA, nlo, nhi, ned);
     const uint32_t pbase = (uint32_t)k * plane;
     // x-neighbours from the adjacent lanes, tile edges from the edge lanes
 #pragma unroll
@@ -466,9 +473,18 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
       ea[r] = na[r];
       eb[r] = nb[r];
     }
-    hlo = nlo;
-    hhi = nhi;
-    hed = ned;
+    if (HA == 2) {
+      hlo = h1lo;
+      hhi = h1hi;
+      hed = h1ed;
+      h1lo = nlo;
+      h1hi = nhi;
+      h1ed = ned;
+    } else {
+      hlo = nlo;
+      hhi = nhi;
+      hed = ned;
+    }
   }
   if (MODE == ZM_LAP || MODE == ZM_JAC) return;
   if (MODE == ZM_UR) {
