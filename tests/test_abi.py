@@ -104,3 +104,14 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+@pytest.mark.parametrize("dims", [(2048, 1024, 1024), (4096, 4096, 128), (2, 8, 8), (8, 8, 2),
+                                  (8, 2, 1), (1 << 20, 1 << 11, 1)])
+def test_plan_size_limits_are_checked_before_any_device_call(dims):
+    # grids of 2^31 or more unknowns (32-bit in-plane indexing), an axis
+    # shorter than eq. (3.1) allows (n >= 3; nz = 1 for 2D), or more blocks
+    # per right-hand side than the reductions hold, are rejected up front
+    from paper_2501_03377_amd.kpcg import KP_EINVAL, kp_plan_create
+    rc, _ = kp_plan_create(*dims, (1, 1, 1), 1, 1, None)
+    assert rc == KP_EINVAL, dims

@@ -232,3 +232,20 @@ def test_lowmode_certificate_stop(prec, shape, bcs):
     assert err <= r["err_est"] <= 1e-10
     b = lowmode_error_bound(R, uh.T, bcs, 32)
     assert abs(b - r["err_est"]) <= 1e-3 * b, (b, r["err_est"])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_manufactured_solution_512_cube(prec):
+    # the 512^3 (P, P, D) grid at full size: eta = L u for a known u (the
+    # oracle's stencil, eq. 3.2), so every entry of the solve is checked
+    # against u without an oracle solve of this size
+    if "u512" not in _FULL:
+        rng = np.random.default_rng(15)
+        u = rng.standard_normal((512, 512, 512))
+        _FULL["u512"] = u
+        _FULL["eta512"] = oracle.apply_minus_laplacian(u.T, ("P", "P", "D")).T.copy()
+    u = _FULL["u512"]
+    got, res, hist, rc = _solve(_FULL["eta512"], ("P", "P", "D"), prec=prec, tol=1e-10)
+    r = res[0]
+    assert rc == 0 and r["true_rel_res"] <= 1e-10, r
+    assert rel(got, u) <= 1e-10, (rel(got, u), r)
