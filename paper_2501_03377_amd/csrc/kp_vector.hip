@@ -239,7 +239,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 // consecutive z-planes.  Each wave covers the 64 columns of 4 consecutive
 // rows: lane l holds the cells of column i0 + l in those rows for the planes
 // k-1, k and k+1 in registers, so a plane's centre values are loaded once
-// from memory.  The x-neighbours come from the adjacent lanes (a shuffle);
+// from memory.  The x-neighbours come from the adjacent lanes (DPP moves);
 // the two tile-edge columns of the 4 rows are fetched by one load in which
 // 8 lanes take part and broadcast with readlane; the y-neighbours of the
 // inner rows are the lane's own registers and only the rows above and below
@@ -277,6 +277,19 @@ __device__ __forceinline__ double diag_1d(int pos, int n, int bc) {
   if (pos == n - 1) return (bc == BC_N || bc == BC_DN) ? 1.0 : 2.0;
   return 2.0;
 }
+
+// Whole-wave DPP moves of a double: lane i receives lane i - 1 (shr) or
+// lane i + 1 (shl); the lane without a source receives 0.  VALU moves, where
+// a shuffle would take the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_shr1(double v) { return dpp_d<0x138>(v); }   // wave_shr:1
+__device__ __forceinline__ double wave_shl1(double v) { return dpp_d<0x130>(v); }   // wave_shl:1
 
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -418,7 +431,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     for (int r = 0; r < RY; ++r) {
       const double cc = cv[r];
       const double el = readlane_d(hed, r), eh = readlane_d(hed, 32 + r);
-      double vxl = __shfl_up(cc, 1), vxh = __shfl_down(cc, 1);
+      double vxl = wave_shr1(cc), vxh = wave_shl1(cc);
       if (lane == 0) vxl = lwall ? ghost_lo(bcx, cc) : el;
       if (lane == e) vxh = rwall ? ghost_hi(bcx, cc) : eh;
       double vyl = r > 0 ? cv[r > 0 ? r - 1 : 0] : (bwall ? ghost_lo(bcy, cc) : hlo);
