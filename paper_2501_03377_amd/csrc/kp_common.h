@@ -67,6 +67,12 @@ enum Slot {
   NSLOTS
 };
 
+constexpr int GMAX = 8192;     // most block partials per slot
+
+__device__ __forceinline__ double* slot_ptr(double* part, int rhs, int slot) {
+  return part + ((int64_t)rhs * NSLOTS + slot) * GMAX;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   // 64-lane butterfly; every lane ends with the same total, in a fixed order
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -22,7 +22,11 @@ struct PinvOps {
   const double* lam[3]; // eigenvalues (FP64)
   int cfg[6];           // tile configuration of each mode product, in order
   const double* gtab = nullptr;   // 2D low-rank preconditioner: G_r in place of Ghat
+  double* rpart = nullptr;        // the G product also leaves <R, Z>, ||Z||^2 (spectral)
 };
+// Blocks per right-hand side of the product that carries Ghat (the number of
+// its spectral partial sums).
+int pinv_ghat_blocks(const PinvOps& op);
 
 // G_r, the best rank-r approximation of the 2D Hadamard pseudoinverse with
 // g_ij = 1/(ln_i + lq_j) (kp_lowrank.cpp, host), to tab[j*n + i]; 0 or -1.
@@ -98,9 +102,10 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
                          int flags, hipStream_t s);
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
+// Gdot > 0: the preconditioner already left Gdot partial sums of <R, Z> etc.
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
                        double* P, double* part, RhsState* st, int batch, int G, int first,
-                       double tol, int flags, hipStream_t s);
+                       double tol, int flags, hipStream_t s, int Gdot = 0);
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
                       int flags, hipStream_t s);

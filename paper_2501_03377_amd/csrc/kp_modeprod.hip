@@ -174,6 +174,13 @@ __device__ __forceinline__ typename MT<PREC>::chunk load_b(const u4* __restrict_
 //   G epilogue (lc != nullptr): times ghat(la[r % a1] + lb[r / a1] + lc[n])
 //   table epilogue (gt != nullptr): times gt[n * rows + r], a precomputed
 //   factor in the output's layout (the low-rank preconditioner's G_r)
+//   spectral inner products (rpart != nullptr, with the G epilogue): the
+//   inputs are the coefficients rhat of R in the eigenbasis and the outputs
+//   those of Z = M(R), so by Parseval <R, Z> = sum rhat zhat and ||Z||^2 =
+//   sum zhat^2; the block's sums (times the square of the input scale's
+//   inverse when rscl) go to the partial slots of the CG step, block
+//   blockIdx.x.  Z has no component on the null space (Ghat is 0 there), so
+//   its sum is taken as 0.
 //   in_scale / out_scale: per-RHS power-of-two scale on the input / its
 //   inverse on the output (low-precision range guard)
 // Grid: x = row blocks * column chunks, y = right-hand side.
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
     const u4* __restrict__ Bpk, int npk, int ncc, const Ti* __restrict__ X, To* __restrict__ Y,
     int K, int rows, int64_t N, const RhsState* __restrict__ st, int in_scale, int out_scale,
     const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
-    int a1, const double* __restrict__ gt) {
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart, int rscl) {
   using M = MT<PREC>;
   constexpr int NT = 64 * WR * WC;
   constexpr int CW = 16 * WN;                 // columns per wave
@@ -336,6 +343,7 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   // ---- epilogue: optional G factor and output scale, transposed store ------
   const double oscale = (st && out_scale) ? st[rhs].inv_scale : 1.0;
   To* Yb = Y + (int64_t)rhs * N;
+  double fs[2] = {0.0, 0.0};   // spectral <R, Z> and ||Z||^2
   double rowsum[WM][4];
   if (lc) {
 #pragma unroll
@@ -371,10 +379,16 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
             val = fabs(sum) < 1e-13 ? 0.0 : (double)((float)val * __frcp_rn((float)sum));
           }
         }
+        const double rhat = (double)acc[i][j][v];
         if (gt) val *= gt[(int64_t)n * rows + (rr[v] < rows ? rr[v] : 0)];
         if (out_scale) val *= oscale;
         if constexpr (sizeof(To) == 2) out[v] = (__bf16)(float)val;
         else out[v] = (To)val;
+        if (rpart && rr[v] < rows) {
+          const double zhat = (double)out[v];
+          fs[0] += rhat * zhat;
+          fs[1] += zhat * zhat;
+        }
       }
       bool done_store = false;
       if constexpr (PREC != PREC_F64) {
@@ -399,6 +413,29 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
         for (int v = 0; v < 4; ++v)
           if (rr[v] < rows) dst[rr[v]] = out[v];
       }
+    }
+  }
+  if (rpart) {
+    // fixed-order block reduction: lanes, then waves in order
+    __shared__ double fred[NT / 64][2];
+    fs[0] = wave_sum(fs[0]);
+    fs[1] = wave_sum(fs[1]);
+    if (lane == 0) {
+      fred[wave][0] = fs[0];
+      fred[wave][1] = fs[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        t0 += fred[w][0];
+        t1 += fred[w][1];
+      }
+      const double m = (rscl && st) ? st[rhs].inv_scale * st[rhs].inv_scale : 1.0;
+      slot_ptr(rpart, rhs, S_DOT)[blockIdx.x] = t0 * m;
+      slot_ptr(rpart, rhs, S_SUM)[blockIdx.x] = 0.0;
+      slot_ptr(rpart, rhs, S_SQ)[blockIdx.x] = t1 * m;
+      slot_ptr(rpart, rhs, S_AUX2)[blockIdx.x] = 0.0;
     }
   }
 }
@@ -440,12 +477,11 @@ void mp_config(int id, int* wn, int* wm, int* wc) {
 // block width covers K most tightly (eight waves per block), else the widest
 // single-group tile.
 int mp_default_config(int K, int prec) {
-  (void)prec;
   const int frags = (K + 15) / 16;
   int best = -1, best_cb = 1 << 30;
   for (int id = 0; id < kNumCfgs; ++id) {
     const MpCfg& c = kCfgs[id];
-    if (c.wc != 2 || c.wm == 4) continue;
+    if (c.wc != 2 || c.wm == 4 || !mp_config_allowed(id, prec)) continue;
     const int cb = c.wn * c.wc;
     if (cb >= frags && cb < best_cb) { best = id; best_cb = cb; }
   }
@@ -526,7 +562,7 @@ template <int PREC, class Ti, class To, int WN, int WM, int WC, bool VEC>
 static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int rows,
                        int batch, const RhsState* st, int in_scale, int out_scale,
                        const double* la, const double* lb, const double* lc, int a1,
-                       const double* gt, hipStream_t s) {
+                       const double* gt, double* rpart, int rscl, hipStream_t s) {
   const int K = op.n[ax];
   const int cb = 16 * WN * WC, ncc = (K + cb - 1) / cb;
   constexpr int BR = WR * 16 * WM;
@@ -536,14 +572,16 @@ static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void*
   dim3 grid(nrb * ncc, batch);
   hipLaunchKernelGGL((mp_kernel<PREC, Ti, To, WN, WM, WC, VEC>), grid, dim3(64 * WR * WC), 0, s,
                      (const u4*)(fwd ? op.Bf[ax] : op.Bb[ax]), npk, ncc, (const Ti*)X, (To*)Y, K,
-                     rows, (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1, gt);
+                     rows, (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1, gt, rpart,
+                     rscl);
 }
 
 template <int PREC, class Ti, class To>
 static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, const void* X,
                       void* Y, int batch, const RhsState* st, int in_scale, int out_scale,
                       const double* la, const double* lb, const double* lc, int a1,
-                      const double* gt, hipStream_t s) {
+                      const double* gt, hipStream_t s, double* rpart = nullptr,
+                      int rscl = 0) {
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
   const int CH = MT<PREC>::CH;
@@ -552,14 +590,14 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
     // rows too ragged for 16-byte loads: one scalar-load tile serves every
     // configuration (such grids are small)
     launch_cfg<PREC, Ti, To, 4, 2, 2, false>(op, ax, fwd, X, Y, rows, batch, st, in_scale,
-                                             out_scale, la, lb, lc, a1, gt, s);
+                                             out_scale, la, lb, lc, a1, gt, rpart, rscl, s);
     trace_end(cls, s);
     return;
   }
 #define KP_CASE(ID, W, M_, C)                                                                 \
   case ID:                                                                                    \
     launch_cfg<PREC, Ti, To, W, M_, C, true>(op, ax, fwd, X, Y, rows, batch, st, in_scale,    \
-                                             out_scale, la, lb, lc, a1, gt, s);               \
+                                             out_scale, la, lb, lc, a1, gt, rpart, rscl, s);  \
     break;
 #define KP_COMMON_CASES                                                                      \
   KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(4, 6, 2, 1)             \
@@ -635,7 +673,8 @@ static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, vo
                             nullptr, nullptr, 1, op.gtab, s);
   } else if (q == dim - 1) {
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, op.lam[0],
-                            dim == 3 ? op.lam[1] : nullptr, op.lam[dim - 1], op.n[0], nullptr, s);
+                            dim == 3 ? op.lam[1] : nullptr, op.lam[dim - 1], op.n[0], nullptr, s,
+                            op.rpart, scl);
   } else {
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, 0, nullptr,
                             nullptr, nullptr, 1, nullptr, s);
@@ -672,6 +711,21 @@ static void product_t(const PinvOps& op, int q, const void* in, void* out, int b
   else
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la, lb,
                             lc, op.n[0], nullptr, s);
+}
+
+int pinv_ghat_blocks(const PinvOps& op) {
+  const int q = op.dim - 1, ax = q;
+  const int K = op.n[ax];
+  const int64_t rows = op.N / K;
+  const int CH = op.prec == PREC_F64 || op.prec == PREC_F32 ? 4 : 8;
+  int wn = 4, wm = 2, wc = 2;   // the scalar-load tile of ragged contractions
+  // a configuration not compiled for the precision launches tile 13, as the
+  // dispatch in launch_mp does
+  if (K % CH == 0) mp_config(mp_config_allowed(op.cfg[q], op.prec) ? op.cfg[q] : 13, &wn, &wm, &wc);
+  const int64_t nrb = (rows + WR * 16 * wm - 1) / (WR * 16 * wm);
+  const int64_t ncc = (K + 16 * wn * wc - 1) / (16 * wn * wc);
+  const int64_t b = nrb * ncc;
+  return b > (1 << 30) ? (1 << 30) : (int)b;
 }
 
 void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch,

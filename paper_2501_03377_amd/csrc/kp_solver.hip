@@ -256,21 +256,36 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-void precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
-                  const RhsState* st, hipStream_t s) {
+// Z = M(R).  In a solve (`part` given) the pseudoinverse also leaves the
+// partial sums of the CG step after it, <R, Z> and ||Z||^2 by Parseval in
+// the eigenbasis, and returns how many there are; 0 means the step computes
+// them itself (other preconditioners, and the flexible beta, which needs
+// <W, Z>).
+int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
+                 const RhsState* st, hipStream_t s, double* part = nullptr) {
   char* base = (char*)p->ws;
   if (flags & KP_FLAG_NO_PRECOND) {
     launch_copy(p->g, R, Z, st, batch, vec_blocks(p->g.N, batch), s);
-  } else if (p->pc_kind == KP_PRECOND_JACOBI) {
+    return 0;
+  }
+  if (p->pc_kind == KP_PRECOND_JACOBI) {
     launch_jacobi(p->g, R, Z, (double*)(base + L.J), p->jac_p, p->jac_omega, st, batch,
                   vec_blocks(p->g.N, batch), s);
-  } else if (p->pc_kind == KP_PRECOND_LOWRANK) {
-    PinvOps op = p->op;
-    op.gtab = p->lr_dev;
-    pinv_apply(op, R, Z, base + L.T0, base + L.T1, batch, st, s);
-  } else {
-    pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, st, s);
+    return 0;
   }
+  PinvOps op = p->op;
+  int Gdot = 0;
+  if (p->pc_kind == KP_PRECOND_LOWRANK) {
+    op.gtab = p->lr_dev;
+  } else if (part && st && !(flags & KP_FLAG_FLEX_BETA)) {
+    const int b = pinv_ghat_blocks(op);
+    if (b <= GMAX) {
+      op.rpart = part;
+      Gdot = b;
+    }
+  }
+  pinv_apply(op, R, Z, base + L.T0, base + L.T1, batch, st, s);
+  return Gdot;
 }
 
 // Checks host boundary data [batch][dim][2] (finite; zero on periodic axes)
@@ -599,8 +614,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   auto head = [&]() {
     launch_init(p->g, eta, R, u, part, st, p->hist_dev, hs, batch, G, s);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-    precondition(p, L, R, Z, batch, flags, st, s);
-    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s);
+    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot);
   };
   // An iteration in two parts: up to the residual test and certificate,
   // then preconditioning and the updates that depend on it.
@@ -612,8 +627,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
                   (double*)(base + L.C3), st, batch, tol, s);
   };
   auto iteration_tail = [&]() {
-    precondition(p, L, R, Z, batch, flags, st, s);
-    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s);
+    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s, Gdot);
   };
   // n iterations; with `split` the last one stops after its residual test
   // (its second part runs later, only if some right-hand side continues)

@@ -16,11 +16,6 @@
 namespace kp {
 
 constexpr int VT = 256;
-constexpr int GMAX = 8192;     // most block partials per slot
-
-__device__ __forceinline__ double* slot_ptr(double* part, int rhs, int slot) {
-  return part + ((int64_t)rhs * NSLOTS + slot) * GMAX;
-}
 
 // One axis of the 3/5/7-point stencil: 2c - lo - hi with the ghost rule of the
 // boundary condition (the rows of eq. 3.1): periodic wraps around, a Dirichlet
@@ -671,14 +666,17 @@ void launch_init(const Geom& g, const double* eta, double* R, double* U, double*
 
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
                        double* P, double* part, RhsState* st, int batch, int G, int first,
-                       double tol, int flags, hipStream_t s) {
+                       double tol, int flags, hipStream_t s, int Gdot) {
   dim3 grid(G, batch);
-  trace_begin(KC_DOT_RZ, s);
-  hipLaunchKernelGGL(k_dot_rz, grid, dim3(VT), 0, s, g, R, Z, (flags & F_FLEX_BETA) ? W : nullptr,
-                     part, st, G);
-  trace_end(KC_DOT_RZ, s);
+  if (Gdot == 0) {
+    trace_begin(KC_DOT_RZ, s);
+    hipLaunchKernelGGL(k_dot_rz, grid, dim3(VT), 0, s, g, R, Z,
+                       (flags & F_FLEX_BETA) ? W : nullptr, part, st, G);
+    trace_end(KC_DOT_RZ, s);
+  }
   trace_begin(KC_FINALIZE, s);
-  hipLaunchKernelGGL(k_fin_rho, dim3(batch), dim3(VT), 0, s, g, part, st, G, first, tol, flags);
+  hipLaunchKernelGGL(k_fin_rho, dim3(batch), dim3(VT), 0, s, g, part, st, Gdot ? Gdot : G, first,
+                     tol, flags);
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_P, s);
   hipLaunchKernelGGL(k_update_p, grid, dim3(VT), 0, s, g, Z, P, st, G, first);
