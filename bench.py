@@ -221,9 +221,11 @@ def solve_work(name, grid, results, flex=False):
             # solve stopped on the error estimate that followed it
             nu = p - (1 if p > s else 0)
             tot += (2 + 3 * (nu - 1)) * 8.0 * N if nu >= 1 else 0.0
+        elif name == "small_solve":      # the whole solve in one kernel: its mode products
+            tot += p * (4.0 * N * (nx + ny) + N)
         else:
             return None, 0.0
-    return ("flop" if name in MODEPROD else "byte"), tot
+    return ("flop" if name in MODEPROD or name == "small_solve" else "byte"), tot
 
 
 def launch_work(name, grid, batch, flex=False):
@@ -573,11 +575,17 @@ def main():
             # algorithmic work (the scalar finalize kernels are latency, not
             # work), timed back to back so that its average is the kernel's
             # own duration (the traced averages above include launch gaps)
-            cls = max((c for c in kernels if launch_work(c, wl["grid"], 1)[0] is not None),
-                      key=lambda c: kernels[c]["total_ms"])
-            reps = int(min(2000, max(20, 0.2e6 / max(kernels[cls]["avg_us"], 1.0))))
-            log(f"{p}: {reps} back-to-back launches of {cls}")
-            dom = (cls, plan.time_kernel(cls, batch=batch, flags=flex(p), reps=reps), reps)
+            timed = [c for c in kernels if launch_work(c, wl["grid"], 1)[0] is not None]
+            if timed:
+                cls = max(timed, key=lambda c: kernels[c]["total_ms"])
+                reps = int(min(2000, max(20, 0.2e6 / max(kernels[cls]["avg_us"], 1.0))))
+                log(f"{p}: {reps} back-to-back launches of {cls}")
+                dom = (cls, plan.time_kernel(cls, batch=batch, flags=flex(p), reps=reps), reps)
+            else:
+                # the whole solve is one kernel (small 2D problems): one
+                # launch per solve, so its traced average is its duration
+                cls = max(kernels, key=lambda c: kernels[c]["total_ms"])
+                dom = (cls, kernels[cls]["avg_us"] * 1e-3, kernels[cls]["launches"])
         plan.close()
         return dict(T=T, lat=lat, res=res, u=uh, tuning=tuning, Tp=Tp, kernels=kernels, dom=dom)
 
@@ -585,6 +593,8 @@ def main():
     kernels, res = m["kernels"], m["res"]
     dom, dom_ms, dom_reps = m["dom"]
     kind, units = launch_work(dom, wl["grid"], batch, prec == "bf16")
+    if kind is None:            # one launch per solve: the solve's work
+        kind, units = solve_work(dom, wl["grid"], res, prec == "bf16")
     rate = units / (dom_ms * 1e-3)
     ident = launch_identity(dom, prec, wl["grid"], batch, m["tuning"])
     traffic = measured_traffic(args.workload, ident)

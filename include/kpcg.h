@@ -194,6 +194,12 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * and replayed; the cache is keyed by batch, iteration count, flags, tol,
  * max_iter and u, and invalidated by kp_plan_set_workspace, the tuning calls
  * and kp_plan_set_profiling.  Results are identical with KP_FLAG_NO_GRAPH.
+ * 2D plans of at most 64 x 64 with the FP64 pseudoinverse run the whole
+ * solve as one kernel, one workgroup per right-hand side (not with
+ * KP_FLAG_DIAGNOSTICS, KP_FLAG_NO_PRECOND, KP_FLAG_FLEX_BETA or
+ * KP_FLAG_ANORM_STOP, nor with another preconditioner); the same recurrences
+ * and stopping rules except the low-mode certificate, with reductions summed
+ * in another fixed order, so results agree with the general path to rounding.
  * Returns the most severe per-RHS status (errors first, then
  * KP_NOT_CONVERGED); KP_EINVAL before any work for bad arguments.  Blocks
  * until the results are on the host. */
@@ -308,7 +314,7 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
  * kp_kernel_class_name (stencil, vector updates, reductions, the six mode
  * products of Algs. 6-7, ...).  Timing adds two event records per launch;
  * while it is on, kp_solve launches every kernel directly (no graph replay). */
-#define KP_KERNEL_CLASSES 17
+#define KP_KERNEL_CLASSES 18
 int kp_plan_set_profiling(kp_plan* plan, int enable);
 /* Synchronises the plan's stream, then returns the accumulated milliseconds
  * and launch count of one class.  KP_EINVAL for a bad class. */

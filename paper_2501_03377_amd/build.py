@@ -18,8 +18,8 @@ OUT = os.path.join(HERE, "libkpcg.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("KPCG_ARCH", "gfx950")
 
-SOURCES = ["kp_basis.cpp", "kp_lowrank.cpp", "kp_vector.hip", "kp_modeprod.hip", "kp_solver.hip",
-           "kp_server.cpp"]
+SOURCES = ["kp_basis.cpp", "kp_lowrank.cpp", "kp_vector.hip", "kp_modeprod.hip", "kp_small.hip",
+           "kp_solver.hip", "kp_server.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # never emit packed FP32 arithmetic (v_pk_*_f32)

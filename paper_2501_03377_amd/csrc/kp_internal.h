@@ -68,6 +68,22 @@ void launch_field(const Geom& g, const double* u, double* eps, const double* fac
 void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, double omega,
                    const RhsState* st, int batch, int G, hipStream_t s);
 bool zgrid_fits(const Geom& g);
+// Small 2D problems (kp_small.hip): the whole solve in one kernel, one
+// workgroup per right-hand side, FP64 pseudoinverse.  Vx, Vy are the full
+// eigenbases [n][n] (column = mode), Vxt, Vyt their transposes, lx, ly the
+// eigenvalues.
+struct SmallOps {
+  const double* Vx;
+  const double* Vy;
+  const double* Vxt;
+  const double* Vyt;
+  const double* lx;
+  const double* ly;
+};
+bool small_solve_fits(const Geom& g);
+void launch_small_solve(const Geom& g, const SmallOps& o, const double* eta, double* U,
+                        RhsState* st, RhsState* mirror, double* hist, int hist_stride, int batch,
+                        double tol, int max_iter, int flags, hipStream_t s);
 // Convergence descriptors of the current iterate U_s into row s of a
 // [batch][stride][DIAG_RAW] table (Experiment 5.4), for every right-hand
 // side whose iterate s is not yet recorded.
@@ -148,6 +164,7 @@ enum KernelClass {
   KC_JACOBI,        // Jacobi(p, omega) preconditioner steps
   KC_DIAG,          // convergence descriptors of the iterate (diagnostic solves)
   KC_CERT,          // low-mode error certificate
+  KC_SMALL,         // whole solve of a small 2D problem in one kernel
   KC_COUNT
 };
 

@@ -137,6 +137,8 @@ struct kp_plan {
   double* faces_dev = nullptr;        // boundary data of kp_assemble_rhs / kp_field
   size_t faces_cap = 0;               // doubles
   CertOps cert{};                     // low-mode error certificate (in `resident`)
+  bool small_ok = false;              // FP64 2D plan small enough for the one-kernel solve
+  SmallOps small{};                   // its full eigenbases (in `resident`)
   double* lr_dev = nullptr;           // G_r of the low-rank preconditioner, [ny][nx] (2D)
   int lr_rank = 0;                    // its rank (0: not built)
 };
@@ -372,6 +374,17 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   }
   const size_t offW = bytes;
   bytes += align_up((size_t)CERT_M * CERT_M * CERT_M * 8);
+  // full FP64 eigenbases and their transposes for the one-kernel solve of
+  // small 2D problems
+  const bool small = prec == PREC_F64 && small_solve_fits(p->g);
+  size_t offQ[2] = {0, 0}, offQt[2] = {0, 0};
+  if (small)
+    for (int a = 0; a < 2; ++a) {
+      offQ[a] = bytes;
+      bytes += align_up((size_t)n[a] * n[a] * 8);
+      offQt[a] = bytes;
+      bytes += align_up((size_t)n[a] * n[a] * 8);
+    }
   std::vector<double> lam_axis[3];
   std::vector<char> host(bytes, 0);
   double lam0[3] = {0.0, 0.0, 0.0}, lam1[3] = {INFINITY, INFINITY, INFINITY};
@@ -384,6 +397,10 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     mp_pack(Q.data(), na, prec, host.data() + offF[a]);
     mp_pack(Qt.data(), na, prec, host.data() + offB[a]);
     std::memcpy(host.data() + offL[a], lam.data(), (size_t)na * 8);
+    if (small) {
+      std::memcpy(host.data() + offQ[a], Q.data(), (size_t)na * na * 8);
+      std::memcpy(host.data() + offQt[a], Qt.data(), (size_t)na * na * 8);
+    }
     // the m_a lowest eigenvectors (columns of Q, eigenvalues ascending)
     const int ma = std::min(na, CERT_M);
     double* Vl = (double*)(host.data() + offV[a]);
@@ -463,6 +480,15 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     }
   }
   p->cert.w = (const double*)((char*)p->resident + offW);
+  if (small) {
+    p->small_ok = true;
+    p->small.Vx = (const double*)((char*)p->resident + offQ[0]);
+    p->small.Vy = (const double*)((char*)p->resident + offQ[1]);
+    p->small.Vxt = (const double*)((char*)p->resident + offQt[0]);
+    p->small.Vyt = (const double*)((char*)p->resident + offQt[1]);
+    p->small.lx = p->op.lam[0];
+    p->small.ly = p->op.lam[1];
+  }
   if (!ok(hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking)) ||
       !ok(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming))) {
     if (p->own) (void)hipStreamDestroy(p->own);
@@ -679,6 +705,17 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   // a stream synchronisation.  Kernels of finished right-hand sides return at
   // once, so a solve that behaves like the previous one takes a single
   // synchronisation and launches no idle iterations.
+  // Small 2D problems with the FP64 pseudoinverse: the whole solve is one
+  // kernel (the same stopping rules, without the low-mode certificate).
+  const bool small = p->small_ok && p->pc_kind == KP_PRECOND_PINV && !diag &&
+                     !(flags & (KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_ANORM_STOP));
+  if (small) {
+    launch_small_solve(p->g, p->small, eta, u, st, p->st_dev, p->hist_dev, hs, batch, tol, max_iter,
+                       flags, s);
+    if (!ok(hipGetLastError())) return KP_EHIP;
+    if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
+    if (p->profiling) p->tracer.collect();
+  } else {
   const bool use_graphs = p->graphs_ok && !p->profiling && !(flags & KP_FLAG_NO_GRAPH);
   const bool repeat = eta == p->last_eta && u == p->last_u;
   p->last_eta = eta;
@@ -737,6 +774,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     if (all_done || done_iters >= max_iter) break;
     chunk = 1;
   }
+  }   // general path
   if (res_hist) std::memcpy(res_hist, p->hist, (size_t)batch * hs * sizeof(double));
 
   int worst = KP_OK;
@@ -1111,7 +1149,8 @@ const char* kp_kernel_class_name(int cls) {
   static const char* names[KC_COUNT] = {
       "stencil_dot", "update_ur", "dot_rz", "update_p", "finalize", "init", "finish",
       "modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
-      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi", "diagnostics", "certificate"};
+      "modeprod_y_bwd", "modeprod_z_bwd", "copy", "jacobi", "diagnostics", "certificate",
+      "small_solve"};
   return (cls >= 0 && cls < KC_COUNT) ? names[cls] : "unknown";
 }
 

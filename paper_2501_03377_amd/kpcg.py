@@ -49,7 +49,7 @@ EXPORTS = (
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
     "kp_plan_diagnostics", "kp_lowrank_table",
 )
-KERNEL_CLASSES = 17
+KERNEL_CLASSES = 18
 
 
 class KpResult(ctypes.Structure):

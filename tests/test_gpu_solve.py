@@ -249,3 +249,31 @@ def test_manufactured_solution_512_cube(prec):
     r = res[0]
     assert rc == 0 and r["true_rel_res"] <= 1e-10, r
     assert rel(got, u) <= 1e-10, (rel(got, u), r)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (17, 50), (3, 64), (64, 5)])
+def test_small_2d_one_kernel_solve(shape):
+    # 2D grids up to 64 x 64 with the FP64 pseudoinverse run the whole solve
+    # in one kernel; every BC pair, two right-hand sides (one constant, which
+    # is all null space for singular pairs), against the oracle
+    from paper_2501_03377_amd import Plan
+    rng = np.random.default_rng(16)
+    ny, nx = shape
+    for bcs in ALL2:
+        eta = np.stack([rng.standard_normal(shape), np.full(shape, 0.5)])
+        plan = Plan(nx, ny, 1, bcs, prec="f64", max_batch=2)
+        plan.set_profiling(True)
+        u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-12, max_iter=20)
+        assert rc == 0, (bcs, res)
+        prof = plan.profile()
+        assert prof["small_solve"][1] == 1 and prof["stencil_dot"][1] == 0, bcs
+        uh = to_host(u)
+        for b in range(2):
+            ref = oracle_solve(eta[b], bcs)
+            if np.linalg.norm(ref) == 0.0:
+                assert np.abs(uh[b]).max() <= 1e-12, bcs
+            else:
+                assert rel(_zero_mean_if(uh[b], bcs), ref) <= 1e-10, (bcs, b)
+            assert res[b]["true_rel_res"] <= 1e-12
+            assert hist[b, 0] in (0.0, 1.0) and hist[b, res[b]["iterations"]] == res[b]["rel_res"]
+        plan.close()
