@@ -96,6 +96,8 @@ def launch_identity(cls, prec, grid, batch, tuning):
     kernel that a class launches with the given tile choices."""
     if cls in VEC_KERNELS:
         return VEC_KERNELS[cls]
+    if cls == "small_solve":
+        return "kp::(anonymous namespace)::k_small_solve"
     from paper_2501_03377_amd.kpcg import kp_tile_shape, PREC
     nx, ny, nz = grid
     dim = 3 if nz > 1 else 2
@@ -575,17 +577,14 @@ def main():
             # algorithmic work (the scalar finalize kernels are latency, not
             # work), timed back to back so that its average is the kernel's
             # own duration (the traced averages above include launch gaps)
-            timed = [c for c in kernels if launch_work(c, wl["grid"], 1)[0] is not None]
-            if timed:
-                cls = max(timed, key=lambda c: kernels[c]["total_ms"])
-                reps = int(min(2000, max(20, 0.2e6 / max(kernels[cls]["avg_us"], 1.0))))
-                log(f"{p}: {reps} back-to-back launches of {cls}")
-                dom = (cls, plan.time_kernel(cls, batch=batch, flags=flex(p), reps=reps), reps)
-            else:
-                # the whole solve is one kernel (small 2D problems): one
-                # launch per solve, so its traced average is its duration
-                cls = max(kernels, key=lambda c: kernels[c]["total_ms"])
-                dom = (cls, kernels[cls]["avg_us"] * 1e-3, kernels[cls]["launches"])
+            # (small 2D problems: the whole solve is one kernel, timed on
+            # the last solve's arguments)
+            timed = [c for c in kernels
+                     if launch_work(c, wl["grid"], 1)[0] is not None or c == "small_solve"]
+            cls = max(timed, key=lambda c: kernels[c]["total_ms"])
+            reps = int(min(2000, max(20, 0.2e6 / max(kernels[cls]["avg_us"], 1.0))))
+            log(f"{p}: {reps} back-to-back launches of {cls}")
+            dom = (cls, plan.time_kernel(cls, batch=batch, flags=flex(p), reps=reps), reps)
         plan.close()
         return dict(T=T, lat=lat, res=res, u=uh, tuning=tuning, Tp=Tp, kernels=kernels, dom=dom)
 
@@ -609,6 +608,10 @@ def main():
                  "algorithmic_per_launch": units})
     if traffic is not None and kind == "byte":
         roof["traffic_over_algorithmic"] = round(traffic / units, 3)
+    if dom == "small_solve":
+        # one workgroup, hence one of the 256 compute units, per right-hand side
+        cus = min(batch, 256)
+        roof["frac_of_used_cus"] = round(roof["frac"] * 256 / cus, 4)
 
     its = [r["iterations"] for r in res]
     out = {

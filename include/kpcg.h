@@ -357,8 +357,12 @@ int kp_plan_diagnostics(const kp_plan* plan, double* out, int batch, int hs, int
  * pattern, each product reading what the previous products of one
  * application produce from it, every right-hand side running.  It overwrites
  * the workspace (never the caller's buffers) and synchronises the plan's
- * stream.  Returns KP_OK, KP_EINVAL (bad class for the plan's dimension,
- * batch, reps outside 1..100000 or other flags), KP_ENOMEM or KP_EHIP. */
+ * stream.  The one-kernel solve of small 2D plans (class "small_solve")
+ * is timed on the arguments of the plan's last kp_solve that took that path
+ * (its eta, u, tol, max_iter, flags; batch at most its batch): each launch
+ * rewrites the same u and the workspace state.  Returns KP_OK, KP_EINVAL
+ * (bad class for the plan, no such solve yet, batch, reps outside 1..100000
+ * or other flags), KP_ENOMEM or KP_EHIP. */
 int kp_plan_time_kernel(kp_plan* plan, int cls, int batch, int flags, int reps, double* avg_ms);
 /* Name of a kernel class, "unknown" when out of range. */
 const char* kp_kernel_class_name(int cls);

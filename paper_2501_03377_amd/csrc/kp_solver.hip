@@ -139,6 +139,12 @@ struct kp_plan {
   CertOps cert{};                     // low-mode error certificate (in `resident`)
   bool small_ok = false;              // FP64 2D plan small enough for the one-kernel solve
   SmallOps small{};                   // its full eigenbases (in `resident`)
+  struct {                            // arguments of the last one-kernel solve
+    const double* eta = nullptr;
+    double* u = nullptr;
+    int batch = 0, max_iter = 0, flags = 0;
+    double tol = 0.0;
+  } small_last;
   double* lr_dev = nullptr;           // G_r of the low-rank preconditioner, [ny][nx] (2D)
   int lr_rank = 0;                    // its rank (0: not built)
 };
@@ -710,6 +716,12 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   const bool small = p->small_ok && p->pc_kind == KP_PRECOND_PINV && !diag &&
                      !(flags & (KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_ANORM_STOP));
   if (small) {
+    p->small_last.eta = eta;
+    p->small_last.u = u;
+    p->small_last.batch = batch;
+    p->small_last.max_iter = max_iter;
+    p->small_last.flags = flags;
+    p->small_last.tol = tol;
     launch_small_solve(p->g, p->small, eta, u, st, p->st_dev, p->hist_dev, hs, batch, tol, max_iter,
                        flags, s);
     if (!ok(hipGetLastError())) return KP_EHIP;
@@ -1040,6 +1052,11 @@ int kp_plan_time_kernel(kp_plan* p, int cls, int batch, int flags, int reps, dou
     case KC_MP_Y_BWD: q = dim + 1; break;
     case KC_MP_Z_BWD: q = dim == 3 ? 5 : -2; break;
     case KC_STENCIL: case KC_UPDATE_UR: case KC_DOT_RZ: case KC_UPDATE_P: break;
+    case KC_SMALL:
+      // the last one-kernel solve again: its input, output and stopping
+      // arguments (each launch recomputes the same result)
+      if (!p->small_ok || !p->small_last.eta || batch > p->small_last.batch) q = -2;
+      break;
     default: q = -2;
   }
   if (q == -2) return KP_EINVAL;
@@ -1072,6 +1089,10 @@ int kp_plan_time_kernel(kp_plan* p, int cls, int batch, int flags, int reps, dou
   for (int k = 0; k < q; ++k) pinv_step(p->op, k, R, Z, T0, T1, batch, st, s);
   auto once = [&]() {
     if (q >= 0) pinv_step(p->op, q, R, Z, T0, T1, batch, st, s);
+    else if (cls == KC_SMALL)
+      launch_small_solve(p->g, p->small, p->small_last.eta, p->small_last.u, st, nullptr, nullptr,
+                         0, batch, p->small_last.tol, p->small_last.max_iter,
+                         p->small_last.flags, s);
     else launch_vector_class(cls, p->g, P, W, R, Z, Z, part, st, batch, G, flags, s);
   };
   once();   // warm-up

@@ -277,3 +277,24 @@ def test_small_2d_one_kernel_solve(shape):
             assert res[b]["true_rel_res"] <= 1e-12
             assert hist[b, 0] in (0.0, 1.0) and hist[b, res[b]["iterations"]] == res[b]["rel_res"]
         plan.close()
+
+
+def test_small_2d_solve_kernel_timing():
+    # back-to-back launches of the one-kernel solve on the last solve's
+    # arguments: refused before any solve, then each launch rewrites the same u
+    from paper_2501_03377_amd import Plan
+    from paper_2501_03377_amd.kpcg import KpError
+    rng = np.random.default_rng(17)
+    eta = rng.standard_normal((2, 40, 48))
+    plan = Plan(48, 40, 1, ("N", "DN"), prec="f64", max_batch=2)
+    with pytest.raises(KpError):
+        plan.time_kernel("small_solve", batch=2, reps=3)
+    u, res, _, rc = plan.solve(to_dev(eta), tol=1e-12, max_iter=20)
+    assert rc == 0
+    before = to_host(u).copy()
+    ms = plan.time_kernel("small_solve", batch=2, reps=5)
+    assert 0.0 < ms < 50.0
+    assert np.array_equal(to_host(u), before)
+    with pytest.raises(KpError):
+        plan.time_kernel("small_solve", batch=3, reps=3)   # beyond max_batch
+    plan.close()
