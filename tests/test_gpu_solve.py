@@ -298,3 +298,34 @@ def test_small_2d_solve_kernel_timing():
     with pytest.raises(KpError):
         plan.time_kernel("small_solve", batch=3, reps=3)   # beyond max_batch
     plan.close()
+
+
+@pytest.mark.parametrize("bcs", [("D", "D"), ("N", "P"), ("P", "P"), ("DN", "ND")])
+def test_small_2d_path_agrees_with_general_path(bcs):
+    # the same solve through the one-kernel path and through the multi-kernel
+    # path (KP_FLAG_DIAGNOSTICS keeps a small plan on the latter): the same
+    # iteration counts and statuses, and results that differ only by the
+    # summation order of the reductions
+    from paper_2501_03377_amd import Plan
+    from paper_2501_03377_amd.kpcg import KP_FLAG_DIAGNOSTICS
+    rng = np.random.default_rng(18)
+    eta = rng.standard_normal((3, 33, 64))
+    plan = Plan(64, 33, 1, bcs, prec="f64", max_batch=3)
+    plan.set_profiling(True)
+    u1, r1, h1, rc1 = plan.solve(to_dev(eta), tol=1e-12, max_iter=20)
+    assert plan.profile()["small_solve"][1] == 1
+    plan.profile_reset()
+    u2, r2, h2, rc2 = plan.solve(to_dev(eta), tol=1e-12, max_iter=20, flags=KP_FLAG_DIAGNOSTICS)
+    assert plan.profile()["small_solve"][1] == 0
+    assert rc1 == rc2 == 0
+    for a, b in zip(r1, r2):
+        assert a["status"] == b["status"] and a["iterations"] == b["iterations"], (a, b)
+        # without the low-mode certificate the one-kernel path may certify
+        # the error with one more application instead
+        assert b["pinv_applications"] <= a["pinv_applications"] <= b["pinv_applications"] + 1
+        assert abs(a["rel_res"] - b["rel_res"]) <= 1e-13
+    a, b = to_host(u1), to_host(u2)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+    n = r1[0]["iterations"]
+    assert np.allclose(h1[:, :n + 1], h2[:, :n + 1], rtol=1e-9, atol=1e-13)
+    plan.close()
