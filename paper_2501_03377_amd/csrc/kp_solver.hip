@@ -644,15 +644,16 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
 
   // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
   auto head = [&]() {
-    launch_init(p->g, eta, R, u, part, st, p->hist_dev, hs, batch, G, s);
+    // U_0 = 0 is stored only for the descriptors of iterate 0
+    launch_init(p->g, eta, R, diag ? u : nullptr, part, st, p->hist_dev, hs, batch, G, s);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
     const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part);
     launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot);
   };
   // An iteration in two parts: up to the residual test and certificate,
   // then preconditioning and the updates that depend on it.
-  auto iteration_head = [&]() {
-    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s);
+  auto iteration_head = [&](bool u0) {
+    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s, u0);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
     if (cert)
       launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
@@ -663,10 +664,11 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s, Gdot);
   };
   // n iterations; with `split` the last one stops after its residual test
-  // (its second part runs later, only if some right-hand side continues)
-  auto iterations = [&](int n, bool split) {
+  // (its second part runs later, only if some right-hand side continues);
+  // `from_start`: the first of them is the solve's first iteration
+  auto iterations = [&](int n, bool split, bool from_start) {
     for (int q = 0; q < n; ++q) {
-      iteration_head();
+      iteration_head(from_start && q == 0);
       if (!(split && q == n - 1)) iteration_tail();
     }
   };
@@ -748,7 +750,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     if (first && use_graphs) {
       if (repeat) {
         const kp_plan::GraphKey key{batch, nkey, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
-        const int gi = graph_for(key, [&]() { head(); iterations(n, split); tail(); });
+        const int gi = graph_for(key, [&]() { head(); iterations(n, split, true); tail(); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
           launched = true;
@@ -759,11 +761,11 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
         const kp_plan::GraphKey key{batch, nkey,     flags,   hs,
                                     tol,   u,        p->hist_dev, diag_dev,
                                     diag ? eta : nullptr};
-        const int gi = graph_for(key, [&]() { iterations(n, split); });
+        const int gi = graph_for(key, [&]() { iterations(n, split, true); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
         } else {
-          iterations(n, split);
+          iterations(n, split, true);
         }
         tail();
         launched = true;
@@ -772,7 +774,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     if (!launched) {
       if (first) head();
       if (pending_tail) iteration_tail();
-      iterations(n, split);
+      iterations(n, split, first);
       tail();
     }
     pending_tail = split;

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
     const double r = eta[off + i] - m;      // eq. (3.6); m = 0 if nonsingular
     R[off + i] = r;
-    U[off + i] = 0.0;                       // U_0 = 0
+    if (U) U[off + i] = 0.0;                // U_0 = 0 (stored only when read before the
+                                            // first iteration writes U)
     v[0] += r;
     v[1] += r * r;
   }
@@ -302,8 +303,11 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 }
 
 // ZM_PW:   partials <L P, P>, sum L P; W = L P stored when W != nullptr
-// ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2
-// ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U
+// ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2;
+//          with u0 the previous U is 0 (the first iteration) and is not read
+// ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U; a right-hand
+//          side that made no iteration has U = 0, which is written to U here
+//          (it was never stored) and used in place of what P holds
 // ZM_LAP:  W = L P only
 // ZM_JAC:  one Jacobi(omega) step on L x = R (Sec. 4.3.1): P is x_{j-1}, W
 //          receives x_j = x_{j-1} + (R - L x_{j-1}) / (omega d), d the
@@ -316,7 +320,8 @@ template <int MODE>
 __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __restrict__ P,
                                            double* __restrict__ W, double* __restrict__ R,
                                            double* __restrict__ U, const double* __restrict__ eta,
-                                           double* part, const RhsState* st, double omega) {
+                                           double* part, const RhsState* st, double omega,
+                                           int u0) {
   const int rhs = blockIdx.y;
   if (MODE == ZM_DIAG) {
     if (st[rhs].iter <= st[rhs].diag_iter) return;
@@ -349,7 +354,11 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   const bool three = g.dim == 3;
   const uint32_t plane = (uint32_t)nx * ny;
   const int64_t off = (int64_t)rhs * g.N;
-  const double* p = P + off;
+  // U_0 = 0 is never stored: a right-hand side that made no iteration takes
+  // its stencil loads from eta (discarded) and writes U = 0 instead, so that
+  // no cell is both read through P and written through U
+  const bool uz = MODE == ZM_TRUE && st[rhs].iter == 0;
+  const double* p = (uz ? eta : P) + off;
   const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
   const double mean = (MODE == ZM_TRUE || MODE == ZM_DIAG) ? st[rhs].mean : 0.0;
   const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
@@ -380,7 +389,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
       const int64_t idx = off + base + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
       if (MODE == ZM_UR) {
         a[r] = R[idx];
-        b[r] = U[idx];
+        b[r] = u0 ? 0.0 : U[idx];
       } else if (MODE == ZM_JAC) {
         a[r] = R[idx];
       } else {
@@ -454,9 +463,10 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           a1 += rr * rr;
           a2 += u * u;
         } else if (MODE == ZM_TRUE) {
-          const double rr = (ea[r] - mean) - wv;
+          const double rr = (ea[r] - mean) - (uz ? 0.0 : wv);
           a0 += rr * rr;
-          a1 += cc;
+          a1 += uz ? 0.0 : cc;
+          if (uz) U[idx] = 0.0;
         } else if (MODE == ZM_DIAG) {
           const double h = ea[r] - mean;
           const double rr = h - wv;
@@ -689,7 +699,7 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s) {
+                      int flags, hipStream_t s, bool u0) {
   const ZGrid z = zgrid_for(g);
   const int Gz = z.nblocks;
   dim3 zgrid(z.nblocks, batch);
@@ -697,14 +707,14 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
   trace_begin(KC_STENCIL, s);
   hipLaunchKernelGGL(k_zm<ZM_PW>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
                      (flags & F_FLEX_BETA) ? W : (double*)nullptr, (double*)nullptr,
-                     (double*)nullptr, (const double*)nullptr, part, (const RhsState*)st, 0.0);
+                     (double*)nullptr, (const double*)nullptr, part, (const RhsState*)st, 0.0, 0);
   trace_end(KC_STENCIL, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_alpha, dim3(batch), dim3(VT), 0, s, g, part, st, Gz);
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_UR, s);
   hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
-                     R, U, (const double*)nullptr, part, (const RhsState*)st, 0.0);
+                     R, U, (const double*)nullptr, part, (const RhsState*)st, 0.0, u0 ? 1 : 0);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,
@@ -719,8 +729,8 @@ void launch_finish(const Geom& g, const double* eta, double* U, double* part, Rh
   const int Gz = z.nblocks;
   trace_begin(KC_FINISH, s);
   hipLaunchKernelGGL(k_zm<ZM_TRUE>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
-                     (const double*)U, (double*)nullptr, (double*)nullptr, (double*)nullptr, eta,
-                     part, (const RhsState*)st, 0.0);
+                     (const double*)U, (double*)nullptr, (double*)nullptr, U, eta, part,
+                     (const RhsState*)st, 0.0, 0);
   hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, Gz, mirror);
   if (g.singular) hipLaunchKernelGGL(k_center_u, dim3(G, batch), dim3(VT), 0, s, g, U, st, G);
   trace_end(KC_FINISH, s);
@@ -739,7 +749,7 @@ void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int 
   trace_begin(KC_STENCIL, s);
   hipLaunchKernelGGL(k_zm<ZM_LAP>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, P, W,
                      (double*)nullptr, (double*)nullptr, (const double*)nullptr, (double*)nullptr,
-                     (const RhsState*)nullptr, 0.0);
+                     (const RhsState*)nullptr, 0.0, 0);
   trace_end(KC_STENCIL, s);
 }
 
@@ -773,7 +783,7 @@ void launch_jacobi(const Geom& g, const double* R, double* Z, double* J, int p, 
   for (int j = 2; j <= p; ++j)
     hipLaunchKernelGGL(k_zm<ZM_JAC>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
                        (const double*)buf[(p - j + 1) % 2], buf[(p - j) % 2], (double*)R,
-                       (double*)nullptr, (const double*)nullptr, (double*)nullptr, st, omega);
+                       (double*)nullptr, (const double*)nullptr, (double*)nullptr, st, omega, 0);
   trace_end(KC_JACOBI, s);
 }
 
@@ -885,7 +895,7 @@ void launch_diag(const Geom& g, const double* eta, const double* U, double* part
   trace_begin(KC_DIAG, s);
   hipLaunchKernelGGL(k_zm<ZM_DIAG>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, U,
                      (double*)nullptr, (double*)nullptr, (double*)nullptr, eta, part,
-                     (const RhsState*)st, 0.0);
+                     (const RhsState*)st, 0.0, 0);
   hipLaunchKernelGGL(k_fin_diag, dim3(batch), dim3(VT), 0, s, g, part, st, diag, stride,
                      z.nblocks);
   trace_end(KC_DIAG, s);
@@ -1115,11 +1125,11 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
     case KC_STENCIL:
       hipLaunchKernelGGL(k_zm<ZM_PW>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
                          flex ? W : (double*)nullptr, (double*)nullptr, (double*)nullptr,
-                         (const double*)nullptr, part, st, 0.0);
+                         (const double*)nullptr, part, st, 0.0, 0);
       return true;
     case KC_UPDATE_UR:
       hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
-                         (double*)nullptr, R, U, (const double*)nullptr, part, st, 0.0);
+                         (double*)nullptr, R, U, (const double*)nullptr, part, st, 0.0, 0);
       return true;
     case KC_DOT_RZ:
       hipLaunchKernelGGL(k_dot_rz, grid, dim3(VT), 0, s, g, (const double*)R, (const double*)Z,

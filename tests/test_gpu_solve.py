@@ -329,3 +329,34 @@ def test_small_2d_path_agrees_with_general_path(bcs):
     n = r1[0]["iterations"]
     assert np.allclose(h1[:, :n + 1], h2[:, :n + 1], rtol=1e-9, atol=1e-13)
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bcs", [("D", "N", "P"), ("N", "N", "N")])
+def test_rhs_without_iterations_returns_zero_over_garbage(prec, bcs):
+    # U_0 = 0 is never stored: a right-hand side that stops before its first
+    # iteration (zero, or constant on a singular set, or non-finite) must
+    # still come back as exactly 0, whatever the output buffer held, next to
+    # right-hand sides that iterate; with graphs, without, and on a repeat
+    import torch
+    from paper_2501_03377_amd import KP_ENONFINITE, Plan
+    from paper_2501_03377_amd.kpcg import KP_FLAG_NO_GRAPH
+    shape = (12, 10, 16)
+    rng = np.random.default_rng(21)
+    eta = np.stack([rng.standard_normal(shape), np.full(shape, 2.5 if oracle.is_singular(bcs) else 0.0),
+                    rng.standard_normal(shape), np.ones(shape)])
+    eta[3, 1, 2, 3] = np.inf
+    plan = Plan(16, 10, 12, bcs, prec=prec, max_batch=4)
+    e = to_dev(eta)
+    for flags in (0, KP_FLAG_NO_GRAPH, 0):
+        u = torch.full_like(e, float("nan"))
+        u, res, _, rc = plan.solve(e, tol=1e-10, max_iter=20, flags=flags, out=u,
+                                   raise_on_error=False)
+        assert rc == KP_ENONFINITE
+        uh = to_host(u)
+        assert np.array_equal(uh[1], np.zeros(shape)) and np.array_equal(uh[3], np.zeros(shape))
+        assert res[1]["iterations"] == 0 and res[3]["iterations"] == 0
+        for b in (0, 2):
+            assert res[b]["status"] == 0 and res[b]["iterations"] >= 1
+            assert rel(_zero_mean_if(uh[b], bcs), oracle_solve(eta[b], bcs)) <= 1e-9
+    plan.close()
