@@ -122,9 +122,11 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
 // Gdot > 0: the preconditioner already left Gdot partial sums of <R, Z> etc.
+// p_written: P already holds the new P (P_0 = Z_0 written by the application).
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
                        double* P, double* part, RhsState* st, int batch, int G, int first,
-                       double tol, int flags, hipStream_t s, int Gdot = 0);
+                       double tol, int flags, hipStream_t s, int Gdot = 0,
+                       bool p_written = false);
 // u0: the first iteration of a solve (U_{s-1} = U_0 = 0, not read)
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,

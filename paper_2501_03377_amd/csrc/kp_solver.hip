@@ -269,8 +269,13 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // the eigenbasis, and returns how many there are; 0 means the step computes
 // them itself (other preconditioners, and the flexible beta, which needs
 // <W, Z>).
+// Z = M(R).  Returns Gdot > 0 when the pseudoinverse left the partial sums
+// of <R, Z> and ||Z||^2 (spectral, Gdot blocks) -- then Z has zero mean and,
+// if `z0` is given, the result goes to z0 instead of Z (the first
+// application writes P_0 = Z_0 directly).
 int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
-                 const RhsState* st, hipStream_t s, double* part = nullptr) {
+                 const RhsState* st, hipStream_t s, double* part = nullptr,
+                 double* z0 = nullptr) {
   char* base = (char*)p->ws;
   if (flags & KP_FLAG_NO_PRECOND) {
     launch_copy(p->g, R, Z, st, batch, vec_blocks(p->g.N, batch), s);
@@ -292,7 +297,7 @@ int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int ba
       Gdot = b;
     }
   }
-  pinv_apply(op, R, Z, base + L.T0, base + L.T1, batch, st, s);
+  pinv_apply(op, R, (Gdot > 0 && z0) ? z0 : Z, base + L.T0, base + L.T1, batch, st, s);
   return Gdot;
 }
 
@@ -647,8 +652,10 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     // U_0 = 0 is stored only for the descriptors of iterate 0
     launch_init(p->g, eta, R, diag ? u : nullptr, part, st, p->hist_dev, hs, batch, G, s);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part);
-    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot);
+    // spectral sums: Z_0 has zero mean, so P_0 = Z_0 is written by the
+    // application itself and the P update is skipped
+    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part, P);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot, Gdot > 0);
   };
   // An iteration in two parts: up to the residual test and certificate,
   // then preconditioning and the updates that depend on it.

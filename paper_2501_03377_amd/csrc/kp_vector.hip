@@ -680,7 +680,7 @@ void launch_init(const Geom& g, const double* eta, double* R, double* U, double*
 
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,
                        double* P, double* part, RhsState* st, int batch, int G, int first,
-                       double tol, int flags, hipStream_t s, int Gdot) {
+                       double tol, int flags, hipStream_t s, int Gdot, bool p_written) {
   dim3 grid(G, batch);
   if (Gdot == 0) {
     trace_begin(KC_DOT_RZ, s);
@@ -692,6 +692,7 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
   hipLaunchKernelGGL(k_fin_rho, dim3(batch), dim3(VT), 0, s, g, part, st, Gdot ? Gdot : G, first,
                      tol, flags);
   trace_end(KC_FINALIZE, s);
+  if (p_written) return;
   trace_begin(KC_UPDATE_P, s);
   hipLaunchKernelGGL(k_update_p, grid, dim3(VT), 0, s, g, Z, P, st, G, first);
   trace_end(KC_UPDATE_P, s);
