@@ -91,6 +91,10 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
+def pid_of(prec):
+    return {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3}[prec]
+
+
 def launch_identity(cls, prec, grid, batch, tuning):
     """The profiler's name (and, for mode products, total threads) of the
     kernel that a class launches with the given tile choices."""
@@ -110,6 +114,16 @@ def launch_identity(cls, prec, grid, batch, tuning):
     ti = "double" if q == 0 else tc
     to = "double" if q == 2 * dim - 1 else tc
     vec = K % (8 if prec in ("bf16", "bf16x6") else 4) == 0
+    if vec and tuning[q] in (20, 21) and K <= 128:
+        # operator-resident tiles: persistent blocks, as many per right-hand
+        # side as fill the chip once
+        wn, wc = (8, 1) if tuning[q] == 20 else (4, 2)
+        res_lds = {"f64": 131072, "f32": 65536, "bf16": 32768, "bf16x6": 98304}[prec]
+        per_cu = max(1, min(4, 160 * 1024 // res_lds))
+        nrb = -(-rows // 64)
+        blocks = max(1, min(nrb, -(-256 * per_cu // batch))) * batch
+        return (f"kp::mp_res<{pid_of(prec)}, {ti}, {to}, {wn}, {wc}>"
+                f"|{blocks * 256 * wc}")
     if vec:
         rc, (wn, wm, wc) = kp_tile_shape(tuning[q], PREC[prec])
         if rc != 0:
@@ -117,7 +131,7 @@ def launch_identity(cls, prec, grid, batch, tuning):
     else:
         wn, wm, wc = 4, 2, 2
     blocks = -(-rows // (64 * wm)) * -(-K // (16 * wn * wc)) * batch
-    pid = {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3}[prec]
+    pid = pid_of(prec)
     return (f"kp::mp_kernel<{pid}, {ti}, {to}, {wn}, {wm}, {wc}, {'true' if vec else 'false'}>"
             f"|{blocks * 256 * wc}")
 

@@ -296,7 +296,8 @@ int kp_field(kp_plan* plan, const double* u, double* eps, int batch, const doubl
 int kp_plan_autotune(kp_plan* plan, int batch, int reps, int* chosen);
 /* Copies the current tile choices (2*dim ints) to cfg; returns 2*dim or
  * KP_EINVAL.  kp_plan_set_tuning installs saved choices (n must be 2*dim;
- * KP_EINVAL for unknown ids), e.g. from a cache of earlier autotune runs. */
+ * KP_EINVAL for unknown ids and for an operator-resident id on an axis
+ * longer than 128), e.g. from a cache of earlier autotune runs. */
 int kp_plan_get_tuning(const kp_plan* plan, int* cfg, int n);
 int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
 /* Shape of tile configuration `id` for precision `prec` (kp_prec): column
@@ -305,7 +306,10 @@ int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
  * 16*wn*wc columns of the GEMM.  Host only, no GPU needed.  Returns KP_OK, or
  * KP_EINVAL if the id is unknown or not compiled for that precision.  A
  * product whose contracted length is not a multiple of 4 (8 in BF16) runs
- * one fixed shape (wn 4, wm 2, wc 2) whatever the choice. */
+ * one fixed shape (wn 4, wm 2, wc 2) whatever the choice.  Ids 20 and 21
+ * keep the whole operator in LDS and sweep row tiles with persistent blocks;
+ * they serve contractions of length at most 128 only (kp_plan_set_tuning
+ * refuses them for a longer axis, the autotuner skips them there). */
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
 
 /* Per-kernel timing (the library's tracing facility).  When enabled, every

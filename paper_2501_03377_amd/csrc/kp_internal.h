@@ -37,6 +37,9 @@ int mp_num_configs();
 void mp_config(int id, int* wn, int* wm, int* wc);
 int mp_default_config(int K, int prec);
 bool mp_config_allowed(int id, int prec);
+// operator-resident configurations (mp_res) and whether `id` serves K x K
+bool mp_config_resident(int id);
+bool mp_config_fits(int id, int K);
 void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch, hipStream_t s);
 size_t mp_packed_bytes(int K, int prec);
 void mp_pack(const double* B, int K, int prec, void* dst);

@@ -21,6 +21,7 @@
 // with FP32 accumulation.  Lane l supplies row (X) / column (B) l%16 and the k
 // values CH*(l/16) .. +CH-1 of each k-block; output item v of lane l is column
 // l%16 and row 4*(l/16)+v (FP32, BF16) or 4*v+l/16 (FP64, measured on gfx950).
+#include <algorithm>
 #include <type_traits>
 
 #include "kp_common.h"
@@ -440,6 +441,198 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Operator-resident variant for short contractions (K <= 128).  The whole
+// packed operator of one product (at most 128 KiB) is loaded into LDS once
+// per block; the block then sweeps row tiles of 64 rows x 128 columns
+// (WR x WC waves, each 16 rows x 16*WN columns) with no further barrier on
+// the operator.  A tile's rows are converted to the compute type, then the
+// next tile's rows are requested, so their loads overlap this tile's
+// products and stores.  Every output is summed over k in the same order as
+// in mp_kernel (bitwise the same product).  Spectral partials go to one slot
+// per row tile (their number depends on the grid only).
+template <int PREC, class Ti, class To, int WN, int WC>
+__global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
+    const u4* __restrict__ Bpk, int npk, const Ti* __restrict__ X, To* __restrict__ Y, int K,
+    int rows, int64_t N, const RhsState* __restrict__ st, int in_scale, int out_scale,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart, int rscl) {
+  using M = MT<PREC>;
+  constexpr int NT = 64 * WR * WC;
+  constexpr int CW = 16 * WN;                 // columns per wave
+  constexpr int CB = WC * CW;                 // columns per block
+  static_assert(CB == 128, "one block covers the operator's 128 columns");
+  constexpr int BR = WR * 16;                 // rows per tile
+  constexpr int CH = M::CH, NV = M::NV, KB = 4 * CH;
+  constexpr int UNITS = 4 * NV * CB;          // 16-byte units per operator k-block
+  constexpr int KBMAX = 128 / KB;             // k-blocks of a 128 x 128 operator
+  constexpr int JG = group_size(WN, (PREC == PREC_F64 || PREC == PREC_BF16X6) ? 4 : 8);
+
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WR, wc = wave / WR;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int cw = wc * CW;
+  const Ti* Xb = X + (int64_t)rhs * N;
+  To* Yb = Y + (int64_t)rhs * N;
+  const bool scaled = (st != nullptr) && in_scale;
+  const double scale = scaled ? st[rhs].scale : 1.0;
+  const double oscale = (st && out_scale) ? st[rhs].inv_scale : 1.0;
+  const int nkb = (K + KB - 1) / KB;
+  const int nrb = (rows + BR - 1) / BR;
+
+  __shared__ u4 lds[KBMAX * UNITS];
+  for (int su = tid; su < nkb * UNITS; su += NT) {
+    const int kk = su / UNITS, u = su % UNITS, gh = u / CB;
+    const int c = min(u % CB, npk - 1);
+    lds[su] = Bpk[((int64_t)kk * 4 * NV + gh) * npk + c];
+  }
+
+  // this lane's row data of tile rb (rows past the end, and k-blocks past the
+  // operator, read valid data that only feeds unused sums)
+  XRaw<PREC, Ti> xq[KBMAX];
+  int rb = blockIdx.x;
+  {
+    const int r = rb * BR + wr * 16 + l16;
+    const bool ok = r < rows;
+    const Ti* xr = Xb + (int64_t)(ok ? r : 0) * K;
+#pragma unroll
+    for (int d = 0; d < KBMAX; ++d)
+      xq[d] = load_raw<PREC, Ti, true>(xr, (ok && d < nkb) ? d * KB + CH * g : K, K);
+  }
+  __syncthreads();
+
+  for (; rb < nrb; rb += gridDim.x) {
+    typename M::chunk xa[KBMAX];
+#pragma unroll
+    for (int d = 0; d < KBMAX; ++d) xa[d] = cvt_raw<PREC, Ti>(xq[d], scale, scaled);
+    {
+      // the next tile's rows, while this one is computed
+      const int rn = rb + gridDim.x;
+      const int r = rn * BR + wr * 16 + l16;
+      const bool ok = rn < nrb && r < rows;
+      const Ti* xr = Xb + (int64_t)(ok ? r : 0) * K;
+#pragma unroll
+      for (int d = 0; d < KBMAX; ++d)
+        xq[d] = load_raw<PREC, Ti, true>(xr, (ok && d < nkb) ? d * KB + CH * g : K, K);
+    }
+    typename M::acc acc[WN];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[j][v] = 0;
+#pragma unroll
+    for (int kk = 0; kk < KBMAX; ++kk) {
+      if (kk < nkb) {
+#pragma unroll
+        for (int j0 = 0; j0 < WN; j0 += JG) {
+          typename M::chunk b[JG];
+#pragma unroll
+          for (int jj = 0; jj < JG; ++jj)
+            b[jj] = load_b<PREC>(lds + kk * UNITS, g, cw + 16 * (j0 + jj) + l16, CB);
+#pragma unroll
+          for (int s = 0; s < M::STEPS; ++s)
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj)
+              acc[j0 + jj] = M::mma(xa[kk], b[jj], acc[j0 + jj], s);
+        }
+      }
+    }
+
+    // epilogue: optional G factor and output scale, transposed store
+    const int rw = rb * BR + wr * 16;
+    double rowsum[4];
+    if (lc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rw + M::row(lane, v);
+        const int rc = r < rows ? r : 0;
+        rowsum[v] = la[rc % a1] + (lb ? lb[rc / a1] : 0.0);
+      }
+    }
+    double ts[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int n = cw + 16 * j + l16;
+      if (n >= K) continue;
+      const double lcn = lc ? lc[n] : 0.0;
+      To* dst = Yb + (int64_t)n * rows;
+      To out[4];
+      int rr[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        rr[v] = rw + M::row(lane, v);
+        double val = (double)acc[j][v];
+        if (lc) {
+          const double sum = rowsum[v] + lcn;
+          if constexpr (PREC == PREC_F64) {
+            val *= ghat(sum);
+          } else {
+            val = fabs(sum) < 1e-13 ? 0.0 : (double)((float)val * __frcp_rn((float)sum));
+          }
+        }
+        const double rhat = (double)acc[j][v];
+        if (gt) val *= gt[(int64_t)n * rows + (rr[v] < rows ? rr[v] : 0)];
+        if (out_scale) val *= oscale;
+        if constexpr (sizeof(To) == 2) out[v] = (__bf16)(float)val;
+        else out[v] = (To)val;
+        if (rpart && rr[v] < rows) {
+          const double zhat = (double)out[v];
+          ts[0] += rhat * zhat;
+          ts[1] += zhat * zhat;
+        }
+      }
+      bool done_store = false;
+      if constexpr (PREC != PREC_F64) {
+        if ((rows & 3) == 0 && rr[3] < rows) {
+          if constexpr (sizeof(To) == 8) {
+            const d2 a = {out[0], out[1]}, b2 = {out[2], out[3]};
+            *reinterpret_cast<d2*>(dst + rr[0]) = a;
+            *reinterpret_cast<d2*>(dst + rr[0] + 2) = b2;
+          } else if constexpr (sizeof(To) == 4) {
+            const f4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<f4*>(dst + rr[0]) = a;
+          } else {
+            const bf4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<bf4*>(dst + rr[0]) = a;
+          }
+          done_store = true;
+        }
+      }
+      if (!done_store) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (rr[v] < rows) dst[rr[v]] = out[v];
+      }
+    }
+    if (rpart) {
+      // this tile's sums, in a fixed order: lanes, then waves in order
+      __shared__ double fred[NT / 64][2];
+      ts[0] = wave_sum(ts[0]);
+      ts[1] = wave_sum(ts[1]);
+      if (lane == 0) {
+        fred[wave][0] = ts[0];
+        fred[wave][1] = ts[1];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+          t0 += fred[w][0];
+          t1 += fred[w][1];
+        }
+        const double m = (rscl && st) ? st[rhs].inv_scale * st[rhs].inv_scale : 1.0;
+        slot_ptr(rpart, rhs, S_DOT)[rb] = t0 * m;
+        slot_ptr(rpart, rhs, S_SUM)[rb] = 0.0;
+        slot_ptr(rpart, rhs, S_SQ)[rb] = t1 * m;
+        slot_ptr(rpart, rhs, S_AUX2)[rb] = 0.0;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host ----
 // Tile configurations (column fragments per wave, row fragments per wave,
 // column wave groups).  Block = 4 x wc waves, rows per block 64*wm, columns
@@ -453,10 +646,19 @@ static const MpCfg kCfgs[] = {
     {16, 2, 1}, {8, 4, 2},
     // short tiles of 128 columns: more blocks for short contractions
     {8, 1, 1}, {4, 1, 2},
+    // operator-resident tiles (mp_res) of the same shapes, for K <= 128
+    {8, 1, 1}, {4, 1, 2},
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+constexpr int kResFirst = 20;   // ids from here on are operator-resident
 
 int mp_num_configs() { return kNumCfgs; }
+
+bool mp_config_resident(int id) { return id >= kResFirst && id < kNumCfgs; }
+
+// Whether configuration `id` can serve a K x K operator: the operator-resident
+// tiles hold at most 128 x 128.
+bool mp_config_fits(int id, int K) { return !mp_config_resident(id) || K <= 128; }
 
 // Whether configuration `id` is compiled for `prec` (tiles whose registers
 // would spill are left out: in FP64 those 16 fragments wide or with 4 row
@@ -576,6 +778,35 @@ static void launch_cfg(const PinvOps& op, int ax, bool fwd, const void* X, void*
                      rscl);
 }
 
+// Persistent blocks of the operator-resident tile: as many per right-hand
+// side as fill the chip once (the operator's LDS share sets the blocks per
+// CU), never more than the row tiles.
+template <int PREC>
+constexpr int res_lds_bytes() {
+  return (128 / (4 * MT<PREC>::CH)) * 4 * MT<PREC>::NV * 128 * 16;
+}
+
+template <int PREC, class Ti, class To, int WN, int WC>
+static void launch_res(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int rows,
+                       int batch, const RhsState* st, int in_scale, int out_scale,
+                       const double* la, const double* lb, const double* lc, int a1,
+                       const double* gt, double* rpart, int rscl, hipStream_t s) {
+  const int K = op.n[ax];
+  constexpr int BR = WR * 16;
+  const int nrb = (rows + BR - 1) / BR;
+  int npk, nkb;
+  packed_geometry(K, PREC, &npk, &nkb);
+  constexpr int per_cu = (160 * 1024) / res_lds_bytes<PREC>() < 1 ? 1
+                         : ((160 * 1024) / res_lds_bytes<PREC>() > 4 ? 4
+                            : (160 * 1024) / res_lds_bytes<PREC>());
+  const int want = (256 * per_cu + batch - 1) / batch;
+  const int nblk = std::max(1, std::min(nrb, want));
+  dim3 grid(nblk, batch);
+  hipLaunchKernelGGL((mp_res<PREC, Ti, To, WN, WC>), grid, dim3(64 * WR * WC), 0, s,
+                     (const u4*)(fwd ? op.Bf[ax] : op.Bb[ax]), npk, (const Ti*)X, (To*)Y, K, rows,
+                     (int64_t)op.N, st, in_scale, out_scale, la, lb, lc, a1, gt, rpart, rscl);
+}
+
 template <int PREC, class Ti, class To>
 static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, const void* X,
                       void* Y, int batch, const RhsState* st, int in_scale, int out_scale,
@@ -599,6 +830,16 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
     launch_cfg<PREC, Ti, To, W, M_, C, true>(op, ax, fwd, X, Y, rows, batch, st, in_scale,    \
                                              out_scale, la, lb, lc, a1, gt, rpart, rscl, s);  \
     break;
+  if (mp_config_resident(cfg) && K <= 128) {
+    if (cfg == kResFirst)
+      launch_res<PREC, Ti, To, 8, 1>(op, ax, fwd, X, Y, rows, batch, st, in_scale, out_scale, la,
+                                     lb, lc, a1, gt, rpart, rscl, s);
+    else
+      launch_res<PREC, Ti, To, 4, 2>(op, ax, fwd, X, Y, rows, batch, st, in_scale, out_scale, la,
+                                     lb, lc, a1, gt, rpart, rscl, s);
+    trace_end(cls, s);
+    return;
+  }
 #define KP_COMMON_CASES                                                                      \
   KP_CASE(0, 1, 4, 1) KP_CASE(1, 2, 4, 1) KP_CASE(2, 3, 4, 1) KP_CASE(4, 6, 2, 1)             \
   KP_CASE(5, 8, 2, 1) KP_CASE(6, 12, 1, 1) KP_CASE(8, 2, 4, 2) KP_CASE(9, 3, 4, 2)            \
@@ -719,9 +960,16 @@ int pinv_ghat_blocks(const PinvOps& op) {
   const int64_t rows = op.N / K;
   const int CH = op.prec == PREC_F64 || op.prec == PREC_F32 ? 4 : 8;
   int wn = 4, wm = 2, wc = 2;   // the scalar-load tile of ragged contractions
+  // the operator-resident tiles write one partial per 64-row tile
+  if (K % CH == 0 && mp_config_resident(op.cfg[q]) && K <= 128) {
+    const int64_t t = (rows + WR * 16 - 1) / (WR * 16);
+    return t > (1 << 30) ? (1 << 30) : (int)t;
+  }
   // a configuration not compiled for the precision launches tile 13, as the
   // dispatch in launch_mp does
-  if (K % CH == 0) mp_config(mp_config_allowed(op.cfg[q], op.prec) ? op.cfg[q] : 13, &wn, &wm, &wc);
+  if (K % CH == 0)
+    mp_config((mp_config_allowed(op.cfg[q], op.prec) && !mp_config_resident(op.cfg[q]))
+                  ? op.cfg[q] : 13, &wn, &wm, &wc);
   const int64_t nrb = (rows + WR * 16 * wm - 1) / (WR * 16 * wm);
   const int64_t ncc = (K + 16 * wn * wc - 1) / (16 * wn * wc);
   const int64_t b = nrb * ncc;

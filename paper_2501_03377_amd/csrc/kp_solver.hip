@@ -1021,7 +1021,7 @@ int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
     float best = 1e30f;
     int best_id = p->op.cfg[q];
     for (int id = 0; id < mp_num_configs(); ++id) {
-      if (!mp_config_allowed(id, p->prec)) continue;
+      if (!mp_config_allowed(id, p->prec) || !mp_config_fits(id, K)) continue;
       int wn, wm, wc;
       mp_config(id, &wn, &wm, &wc);
       const int cb = wn * wc;
@@ -1140,7 +1140,8 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
 int kp_plan_set_tuning(kp_plan* p, const int* cfg, int n) {
   if (!p || !cfg || n != 2 * p->g.dim) return KP_EINVAL;
   for (int q = 0; q < n; ++q)
-    if (!mp_config_allowed(cfg[q], p->prec)) return KP_EINVAL;
+    if (!mp_config_allowed(cfg[q], p->prec) || !mp_config_fits(cfg[q], p->op.n[q % p->g.dim]))
+      return KP_EINVAL;
   for (int q = 0; q < n; ++q) p->op.cfg[q] = cfg[q];
   clear_graphs(p);
   return KP_OK;

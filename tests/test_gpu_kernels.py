@@ -127,10 +127,11 @@ def test_pinv_batch_matches_single():
 
 
 # tile configurations compiled per precision (the others would spill)
-TILE_CONFIGS = {"f64": [c for c in range(20) if c not in (3, 7, 11, 15, 16, 17)],
-                "f32": list(range(20)),
-                "bf16": [c for c in range(20) if c != 16],
-                "bf16x6": [c for c in range(20) if c not in (3, 7, 11, 15, 16, 17)]}
+# 20 and 21: the operator-resident tiles (contractions of at most 128)
+TILE_CONFIGS = {"f64": [c for c in range(22) if c not in (3, 7, 11, 15, 16, 17)],
+                "f32": list(range(22)),
+                "bf16": [c for c in range(22) if c != 16],
+                "bf16x6": [c for c in range(22) if c not in (3, 7, 11, 15, 16, 17)]}
 
 
 @pytest.mark.parametrize("shape", [(20, 36, 70), (24, 40, 72)])
@@ -147,7 +148,7 @@ def test_tile_shapes_are_bitwise_identical(prec, shape):
     rh = to_host(r)
     for b in range(2):
         assert rel(ref[b], oracle_pinv(rh[b], ("P", "D", "N"))) <= PINV_TOL[prec]
-    for cfg in range(21):
+    for cfg in range(23):
         rc = kp_plan_set_tuning(plan._h, [cfg] * 6)
         if cfg not in TILE_CONFIGS[prec]:
             assert rc != 0, cfg
@@ -206,3 +207,23 @@ def test_kernel_timing_call(shape, bcs, prec):
     assert np.array_equal(to_host(e), eta)
     u2, _, _, rc = plan.solve(e, tol=1e-10, flags=flags)
     assert rc == 0 and np.array_equal(to_host(u2), u1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_resident_tiles_only_for_short_contractions(prec):
+    # the operator-resident tiles hold a 128 x 128 operator at most: refused
+    # for a product along a longer axis, accepted (and bitwise the same as the
+    # default tiles) where every axis fits, including a batch
+    from paper_2501_03377_amd.kpcg import kp_plan_set_tuning
+    plan = _plan((16, 24, 160), ("P", "D", "N"), prec=prec)
+    assert kp_plan_set_tuning(plan._h, [20] * 6) != 0
+    plan.close()
+    rng = np.random.default_rng(22)
+    shape = (32, 64, 128)
+    r = to_dev(rng.standard_normal((3,) + shape))
+    plan = _plan(shape, ("N", "DN", "P"), prec=prec, max_batch=3)
+    ref = to_host(plan.apply_pinv(r))
+    for cfg in (20, 21):
+        assert kp_plan_set_tuning(plan._h, [cfg] * 6) == 0
+        assert np.array_equal(to_host(plan.apply_pinv(r)), ref), cfg
+    plan.close()
