@@ -178,7 +178,8 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  *     (||R_s||^2 - sum_box rhat^2) / theta^2, where rhat are the exact
  *     coefficients of R_s on the box of the min(n_a, 32) lowest eigenmodes
  *     per axis and theta the smallest eigenvalue outside the box (three
- *     small FP64 GEMMs, about one read of R_s);
+ *     small FP64 GEMMs, about one read of R_s; tried in the iterations where
+ *     the solve is expected to stop, i.e. the last of each chunk below);
  *   - the estimate ||Z_s||/||U_s|| <= tol after the next preconditioner
  *     application (Z_s = M(R_s) estimates the error of U_s).
  * With KP_FLAG_ANORM_STOP the rule is instead the A-norm error estimate that

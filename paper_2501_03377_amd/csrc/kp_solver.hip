@@ -659,10 +659,14 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   };
   // An iteration in two parts: up to the residual test and certificate,
   // then preconditioning and the updates that depend on it.
-  auto iteration_head = [&](bool u0) {
+  // with_cert: the low-mode certificate runs after this iteration's residual
+  // test (only the last iteration of a chunk, where the solve is expected to
+  // stop; earlier ones fall back to the error estimate after the next
+  // application, and their launches are saved)
+  auto iteration_head = [&](bool u0, bool with_cert) {
     launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s, u0);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-    if (cert)
+    if (cert && with_cert)
       launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
                   (double*)(base + L.C3), st, batch, tol, s);
   };
@@ -675,7 +679,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   // `from_start`: the first of them is the solve's first iteration
   auto iterations = [&](int n, bool split, bool from_start) {
     for (int q = 0; q < n; ++q) {
-      iteration_head(from_start && q == 0);
+      iteration_head(from_start && q == 0, q == n - 1);
       if (!(split && q == n - 1)) iteration_tail();
     }
   };

@@ -583,6 +583,7 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   s.rr = v[1];
   s.uu = v[2];
   s.iter += 1;
+  s.need_cert = 0;   // a certificate applies to this iterate only
   s.rel_res = sqrt(v[1] / s.h2);
   if (hist) hist[(int64_t)rhs * hist_stride + s.iter] = s.rel_res;
   if (!isfinite(s.rel_res)) { s.done = NONFINITE; return; }
