@@ -119,7 +119,8 @@ void launch_timing_states(RhsState* st, int batch, hipStream_t s);
 bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R, double* U,
                          double* Z, double* part, const RhsState* st, int batch, int G,
                          int flags, hipStream_t s);
-// R_0 = eta_c with its sums; U_0 = 0 is stored only when U is not null (the
+// R_0 = eta_c with its sums; R_0 is stored only when R is not null (a
+// nonsingular set uses eta itself), U_0 = 0 only when U is not null (the
 // first U/R update takes it as 0 without reading it, the exit step writes it
 // for a right-hand side that made no iteration).
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
@@ -130,10 +131,11 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
                        double* P, double* part, RhsState* st, int batch, int G, int first,
                        double tol, int flags, hipStream_t s, int Gdot = 0,
                        bool p_written = false);
-// u0: the first iteration of a solve (U_{s-1} = U_0 = 0, not read)
+// u0: the first iteration of a solve (U_{s-1} = U_0 = 0, not read); r0: if
+// not null, R_{s-1} is read from it (R_0 = eta of a nonsingular set)
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, bool u0);
+                      int flags, hipStream_t s, bool u0, const double* r0);
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
                    RhsState* mirror, int batch, int G, hipStream_t s);
 void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int G, hipStream_t s);

@@ -111,15 +111,17 @@ struct kp_plan {
   hipEvent_t ev_in = nullptr;   // orders kp_solve after earlier work on `stream`
   // Captured chunks of iterations, keyed by everything their kernels capture.
   struct GraphKey {
+    int whole;          // 1: start, iterations and exit step; 0: iterations only
     int batch, n, flags, hs;
     double tol;
     const void* u;
     const void* hist;
     const void* diag;   // descriptor table (nullptr without KP_FLAG_DIAGNOSTICS)
-    const void* eta;    // whole-solve graphs only (nullptr for iteration chunks)
+    const void* eta;    // when the captured kernels read it, else nullptr
     bool operator==(const GraphKey& o) const {
-      return batch == o.batch && n == o.n && flags == o.flags && hs == o.hs && tol == o.tol &&
-             u == o.u && hist == o.hist && diag == o.diag && eta == o.eta;
+      return whole == o.whole && batch == o.batch && n == o.n && flags == o.flags &&
+             hs == o.hs && tol == o.tol && u == o.u && hist == o.hist && diag == o.diag &&
+             eta == o.eta;
     }
   };
   struct GraphEntry {
@@ -647,15 +649,20 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   }
   double* diag_dev = diag ? p->diag_dev : nullptr;
 
-  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0
+  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0.
+  // R_0 is eta itself for a nonsingular set, read where R_0 is needed (the
+  // first application and the first U/R update, which stores R_1 in R).
+  const double* R0 = p->g.singular ? R : eta;
   auto head = [&]() {
-    // U_0 = 0 is stored only for the descriptors of iterate 0
-    launch_init(p->g, eta, R, diag ? u : nullptr, part, st, p->hist_dev, hs, batch, G, s);
+    // U_0 = 0 is stored only for the descriptors of iterate 0; R_0 = eta_c
+    // only for a singular set (a nonsingular one reads eta itself)
+    launch_init(p->g, eta, p->g.singular ? R : nullptr, diag ? u : nullptr, part, st,
+                p->hist_dev, hs, batch, G, s);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
     // spectral sums: Z_0 has zero mean, so P_0 = Z_0 is written by the
     // application itself and the P update is skipped
-    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part, P);
-    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot, Gdot > 0);
+    const int Gdot = precondition(p, L, R0, Z, batch, flags, st, s, part, P);
+    launch_after_pinv(p->g, R0, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot, Gdot > 0);
   };
   // An iteration in two parts: up to the residual test and certificate,
   // then preconditioning and the updates that depend on it.
@@ -664,7 +671,8 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   // stop; earlier ones fall back to the error estimate after the next
   // application, and their launches are saved)
   auto iteration_head = [&](bool u0, bool with_cert) {
-    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s, u0);
+    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s, u0,
+                     (u0 && !p->g.singular) ? eta : nullptr);
     if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
     if (cert && with_cert)
       launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
@@ -760,7 +768,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
     bool launched = false;
     if (first && use_graphs) {
       if (repeat) {
-        const kp_plan::GraphKey key{batch, nkey, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
+        const kp_plan::GraphKey key{1, batch, nkey, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
         const int gi = graph_for(key, [&]() { head(); iterations(n, split, true); tail(); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
@@ -768,10 +776,11 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
         }
       } else {
         head();
-        // (the iterations read eta only for the descriptors)
-        const kp_plan::GraphKey key{batch, nkey,     flags,   hs,
-                                    tol,   u,        p->hist_dev, diag_dev,
-                                    diag ? eta : nullptr};
+        // (the iterations read eta for the descriptors, and as R_0 of a
+        // nonsingular set in the first U/R update)
+        const kp_plan::GraphKey key{0,     batch, nkey,        flags,   hs,
+                                    tol,   u,     p->hist_dev, diag_dev,
+                                    (diag || !p->g.singular) ? eta : nullptr};
         const int gi = graph_for(key, [&]() { iterations(n, split, true); });
         if (gi >= 0) {
           if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
 #pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
     const double r = eta[off + i] - m;      // eq. (3.6); m = 0 if nonsingular
-    R[off + i] = r;
+    if (R) R[off + i] = r;                  // (a nonsingular set reads eta as R_0)
     if (U) U[off + i] = 0.0;                // U_0 = 0 (stored only when read before the
                                             // first iteration writes U)
     v[0] += r;
@@ -304,7 +304,8 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 
 // ZM_PW:   partials <L P, P>, sum L P; W = L P stored when W != nullptr
 // ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2;
-//          with u0 the previous U is 0 (the first iteration) and is not read
+//          with u0 the previous U is 0 (the first iteration) and is not read;
+//          with eta the previous R is read from eta (R_0 of a nonsingular set)
 // ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U; a right-hand
 //          side that made no iteration has U = 0, which is written to U here
 //          (it was never stored) and used in place of what P holds
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     for (int r = 0; r < RY; ++r) {
       const int64_t idx = off + base + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
       if (MODE == ZM_UR) {
-        a[r] = R[idx];
+        a[r] = eta ? eta[idx] : R[idx];   // R_0 = eta (nonsingular) is never stored
         b[r] = u0 ? 0.0 : U[idx];
       } else if (MODE == ZM_JAC) {
         a[r] = R[idx];
@@ -701,7 +702,7 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, bool u0) {
+                      int flags, hipStream_t s, bool u0, const double* r0) {
   const ZGrid z = zgrid_for(g);
   const int Gz = z.nblocks;
   dim3 zgrid(z.nblocks, batch);
@@ -716,7 +717,7 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_UR, s);
   hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
-                     R, U, (const double*)nullptr, part, (const RhsState*)st, 0.0, u0 ? 1 : 0);
+                     R, U, r0, part, (const RhsState*)st, 0.0, u0 ? 1 : 0);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,

@@ -360,3 +360,44 @@ def test_rhs_without_iterations_returns_zero_over_garbage(prec, bcs):
             assert res[b]["status"] == 0 and res[b]["iterations"] >= 1
             assert rel(_zero_mean_if(uh[b], bcs), oracle_solve(eta[b], bcs)) <= 1e-9
     plan.close()
+
+
+@pytest.mark.parametrize("bcs", [("D", "P", "DN"), ("P", "N", "P")])
+def test_graph_replay_with_another_eta_buffer(bcs):
+    # a nonsingular set reads eta itself as R_0 inside the captured
+    # iterations, a singular one its centred copy: solving a second right-hand
+    # side from another buffer into the same output must not replay the first
+    # one's input
+    from paper_2501_03377_amd import Plan
+    shape = (20, 24, 32)
+    rng = np.random.default_rng(23)
+    e1, e2 = rng.standard_normal(shape), rng.standard_normal(shape)
+    plan = Plan(32, 24, 20, bcs, prec="f32", max_batch=1)
+    d1, d2 = to_dev(e1), to_dev(e2)
+    import torch
+    u = torch.empty_like(d1)
+    for eta, ref_eta in ((d1, e1), (d2, e2), (d1, e1), (d2, e2)):
+        u, res, _, rc = plan.solve(eta, tol=1e-10, max_iter=20, out=u)
+        assert rc == 0
+        assert rel(_zero_mean_if(to_host(u), bcs), oracle_solve(ref_eta, bcs)) <= 1e-9
+    plan.close()
+
+
+def test_repeated_diagnostics_solve_replays_whole_graph():
+    # a diagnostics solve captures iterations that read eta; a second call with
+    # the same buffers captures the whole solve, a different graph that must
+    # not be confused with the first (the output is NaN-filled in between)
+    from paper_2501_03377_amd import Plan
+    from paper_2501_03377_amd.kpcg import KP_FLAG_DIAGNOSTICS, KP_FLAG_NO_GRAPH
+    import torch
+    shape = (12, 16, 20)
+    eta = to_dev(synth.charge_field(shape, ncharges=50, seed=24))
+    plan = Plan(20, 16, 12, ("N", "N", "P"), prec="f32")
+    ref, _, _, rc = plan.solve(eta, tol=1e-10, flags=KP_FLAG_DIAGNOSTICS | KP_FLAG_NO_GRAPH)
+    ref = to_host(ref)
+    out = torch.empty_like(eta)
+    for call in range(3):
+        out.fill_(float("nan"))
+        _, res, _, rc = plan.solve(eta, tol=1e-10, flags=KP_FLAG_DIAGNOSTICS, out=out)
+        assert rc == 0 and np.array_equal(to_host(out), ref), call
+    plan.close()
