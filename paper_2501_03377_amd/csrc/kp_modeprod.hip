@@ -356,6 +356,15 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
         rowsum[i][v] = la[rc % a1] + (lb ? lb[rc / a1] : 0.0);
       }
   }
+  // Outputs of at most 4 bytes: the block's tile is staged in LDS (free after
+  // the k-loop) as [column][row], then written column by column, 16 bytes a
+  // thread, so that each column gets one contiguous run of BR rows instead
+  // of 16-row pieces from every wave.
+  constexpr int SE = 16 / (int)sizeof(To);          // elements per 16-byte chunk
+  constexpr int BRP = BR + SE;                      // padded column length
+  constexpr bool STG = sizeof(To) <= 4 && (size_t)CB * BRP * sizeof(To) <= sizeof(lds);
+  const bool stage = STG && rows % SE == 0;
+  To* stg = reinterpret_cast<To*>(&lds[0][0]);
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
     const int n = c0 + cw + 16 * j + l16;
@@ -391,6 +400,20 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
           fs[1] += zhat * zhat;
         }
       }
+      if constexpr (STG) {
+        if (stage) {
+          // the four rows of this lane are consecutive
+          To* q = stg + (cw + 16 * j + l16) * BRP + wr * WM * 16 + 16 * i + M::row(lane, 0);
+          if constexpr (sizeof(To) == 4) {
+            const f4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<f4*>(q) = a;
+          } else {
+            const bf4 a = {out[0], out[1], out[2], out[3]};
+            *reinterpret_cast<bf4*>(q) = a;
+          }
+          continue;
+        }
+      }
       bool done_store = false;
       if constexpr (PREC != PREC_F64) {
         // the four rows of this lane are consecutive
@@ -413,6 +436,21 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           if (rr[v] < rows) dst[rr[v]] = out[v];
+      }
+    }
+  }
+  if constexpr (STG) {
+    if (stage) {
+      __syncthreads();
+      constexpr int CPC = BR / SE;                  // chunks per column
+      const int nvalid = min(CB, K - c0);
+      const int r0 = rb * BR;
+      for (int c = tid; c < CB * CPC; c += NT) {
+        const int col = c / CPC, part = c - col * CPC;
+        const int row = r0 + part * SE;
+        if (col >= nvalid || row >= rows) continue;   // (rows is a multiple of SE)
+        *reinterpret_cast<u4*>(Yb + (int64_t)(c0 + col) * rows + row) =
+            *reinterpret_cast<const u4*>(stg + col * BRP + part * SE);
       }
     }
   }
