@@ -401,3 +401,32 @@ def test_repeated_diagnostics_solve_replays_whole_graph():
         _, res, _, rc = plan.solve(eta, tol=1e-10, flags=KP_FLAG_DIAGNOSTICS, out=out)
         assert rc == 0 and np.array_equal(to_host(out), ref), call
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x6"])
+@pytest.mark.parametrize("cfg", [20, 21])
+def test_solve_with_operator_resident_tiles(prec, cfg):
+    # the operator-resident tiles carry the Ghat factor and the spectral
+    # <R, Z>, ||Z||^2 partials (one per row tile) when they serve the last
+    # forward product: whole solves with every product on them, a batch of
+    # two, against the oracle and against the default tiles
+    from paper_2501_03377_amd import Plan
+    from paper_2501_03377_amd.kpcg import kp_plan_set_tuning
+    shape = (24, 40, 64)
+    bcs = ("P", "N", "DN")
+    rng = np.random.default_rng(25)
+    eta = np.stack([synth.charge_field(shape, ncharges=80, seed=26), rng.standard_normal(shape)])
+    plan = Plan(64, 40, 24, bcs, prec=prec, max_batch=2)
+    u0, r0, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=30)
+    assert rc == 0
+    assert kp_plan_set_tuning(plan._h, [cfg] * 6) == 0
+    u1, r1, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=30)
+    assert rc == 0
+    a, b = to_host(u1), to_host(u0)
+    for k in range(2):
+        assert r1[k]["iterations"] == r0[k]["iterations"], (r1[k], r0[k])
+        ref = oracle_solve(eta[k], bcs)
+        bound = 1e-10 if prec == "f64" else 1e-9
+        assert rel(a[k], ref) <= bound
+        assert np.linalg.norm(a[k] - b[k]) <= 1e-9 * np.linalg.norm(b[k])
+    plan.close()
