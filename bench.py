@@ -216,7 +216,9 @@ def solve_work(name, grid, results, flex=False):
     after s iterations used p pinv applications (one at start, one per
     iteration, except a last iteration that stopped on the residual test
     and error bound) and s stencil and U/R updates; when the last
-    application was followed by the stop, its P update is skipped."""
+    application was followed by the stop, its P update is skipped.  The
+    timed back-to-back launches of the roofline move the full 5 words of a
+    later U/R update (launch_work)."""
     nx, ny, nz = grid
     N = nx * ny * nz
     tot = 0.0
@@ -229,14 +231,20 @@ def solve_work(name, grid, results, flex=False):
         elif name == "stencil_dot":      # reads P (W = L P stored for the flexible beta)
             tot += s * (1 + flex) * 8.0 * N
         elif name == "update_ur":        # reads P, R, U, writes R, U (L P recomputed)
-            tot += s * 5 * 8.0 * N
+            # (the first iteration takes U_0 = 0 without reading it)
+            tot += (5 * s - (1 if s >= 1 else 0)) * 8.0 * N
         elif name == "dot_rz":           # reads R, Z (and W for the flexible beta)
             tot += p * (2 + flex) * 8.0 * N
         elif name == "update_p":         # P_0 = Z_0: 2 words; P = Z + beta P: 3 words
             # one P update per application, except after the last when the
-            # solve stopped on the error estimate that followed it
+            # solve stopped on the error estimate that followed it; P_0 = Z_0
+            # is a launch of its own only off the spectral path (the flexible
+            # beta): otherwise the first application writes P_0 itself
             nu = p - (1 if p > s else 0)
-            tot += (2 + 3 * (nu - 1)) * 8.0 * N if nu >= 1 else 0.0
+            if flex:
+                tot += (2 + 3 * (nu - 1)) * 8.0 * N if nu >= 1 else 0.0
+            else:
+                tot += 3 * (nu - 1) * 8.0 * N if nu >= 2 else 0.0
         elif name == "small_solve":      # the whole solve in one kernel: its mode products
             tot += p * (4.0 * N * (nx + ny) + N)
         else:
