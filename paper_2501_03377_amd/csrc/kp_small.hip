@@ -10,8 +10,12 @@
 // the cache, Ghat is applied in the epilogue of the second product, and the
 // scalar recurrences, the stopping tests and the exit step (true residual,
 // centring) run in the same kernel.
-// The arithmetic is that of the multi-kernel path; only the summation order
-// of the reductions differs.
+// The recurrences and stopping tests are those of the multi-kernel path,
+// except that the low-mode certificate is not tried (the bound
+// ||R|| / lambda_min or the estimate after the next application decide);
+// the inner products, <R, Z> and the mean of Z included, are summed in space
+// in a fixed order of their own, so results agree with that path to
+// rounding.
 #include <math.h>
 
 #include "kp_common.h"
