@@ -420,8 +420,9 @@ class Plan:
         return f"{nx}x{ny}x{nz}:{self.prec}:b{batch}"
 
     def autotune(self, batch=1, reps=5, cache=None):
-        """Times every tile shape for each mode product and keeps the fastest.
-        With `cache` (a path), reuses and records choices in a JSON file."""
+        """Times every tile shape for each mode product and keeps the fastest
+        (the operator-resident shapes only on axes of at most 128).  With
+        `cache` (a path), reuses and records choices in a JSON file."""
         import json
         key = self.tuning_key(batch)
         if cache and os.path.exists(cache):
@@ -460,7 +461,9 @@ class Plan:
 
     def time_kernel(self, cls, batch=1, flags=0, reps=100):
         """Average milliseconds of one launch of a kernel class (name or
-        number), `reps` launches back to back on workspace data."""
+        number), `reps` launches back to back on workspace data; the
+        one-kernel 2D solve ("small_solve") is timed on the arguments of the
+        plan's last solve that took it (kp_plan_time_kernel)."""
         if isinstance(cls, str):
             names = [kp_kernel_class_name(c) for c in range(KERNEL_CLASSES)]
             cls = names.index(cls)
