@@ -37,9 +37,14 @@ if ROOT not in sys.path:
 METRIC = "3D solves/s at rel-res 1e-10, mixed vs FP64 PCG; p50/p99 latency"
 COPY_CAL_BYTES = 256 << 20     # bytes read (and written) by the calibration copy
 # TFLOP/s; bf16x6 counts the FP32-equivalent flops of a product, whose
-# emulation issues six BF16 matrix-core products: its ceiling is 2500 / 6
-PEAK = {"hbm_GBs": 8000.0, "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x6": 2500.0 / 6}
-DTYPE = {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16", "bf16x6": "f64+bf16x6"}
+# emulation issues six BF16 matrix-core products: its ceiling is 2500 / 6;
+# i8x7 counts the FP64-equivalent flops, each of which costs 28 int8
+# matrix-core operations (5000 TOP/s dense): its ceiling is 5000 / 28
+PEAK = {"hbm_GBs": 8000.0, "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x6": 2500.0 / 6,
+        "i8x7": 5000.0 / 28}
+DTYPE = {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16", "bf16x6": "f64+bf16x6",
+         "i8x7": "f64+i8x7"}
+PRECS = ("f64", "f32", "bf16", "bf16x6", "i8x7")
 MODEPROD = ("modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
             "modeprod_y_bwd", "modeprod_z_bwd")
 
@@ -91,8 +96,14 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
+def i8x7_fits(grid):
+    """The int8 split preconditioner needs every axis a multiple of 16 and at
+    most 512."""
+    return all(n % 16 == 0 and n <= 512 for n in grid if n > 1)
+
+
 def pid_of(prec):
-    return {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3}[prec]
+    return {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3, "i8x7": 4}[prec]
 
 
 def launch_identity(cls, prec, grid, batch, tuning):
@@ -110,6 +121,12 @@ def launch_identity(cls, prec, grid, batch, tuning):
     q = PRODUCT_ORDER[dim].index(cls)
     K = grid["xyz".index(cls.split("_")[1])]
     rows = nx * ny * nz // K
+    if prec == "i8x7":
+        # one kernel for every product: k-blocks of 64 per wave, split over
+        # two waves above 256; one block of 4 (8) waves per 64 rows
+        ks = 2 if K > 256 else 1
+        kbw = -(-(-(-K // 64)) // ks)
+        return f"kp::mp_oz<{kbw}, {ks}>|{-(-rows // 64) * batch * 256 * ks}"
     tc = {"f64": "double", "f32": "float", "bf16": "__bf16", "bf16x6": "float"}[prec]
     ti = "double" if q == 0 else tc
     to = "double" if q == 2 * dim - 1 else tc
@@ -519,7 +536,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="serving: also 0.5, 1.0, 1.2 mu")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--prec", default=None, choices=["f32", "f64", "bf16", "bf16x6"])
+    ap.add_argument("--prec", default=None, choices=list(PRECS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-compare", action="store_true",
@@ -690,8 +707,8 @@ def main():
 
     if not args.no_compare:
         comp = {}
-        for p in ("f64", "f32", "bf16", "bf16x6"):
-            if p == prec:
+        for p in PRECS:
+            if p == prec or (p == "i8x7" and not i8x7_fits(wl["grid"])):
                 continue
             c = measure(p, max(3, steps // 4))
             comp[p] = {"solves_per_s": batch * len(c["lat"]) / c["T"],
@@ -717,7 +734,11 @@ def main():
     for c in out.get("compare", {}).values():
         c.pop("u", None)
     if "f64" in out.get("compare", {}):
-        out["speedup_vs_fp64"] = out["value"] / out["compare"]["f64"]["solves_per_s"]
+        f64 = out["compare"]["f64"]["solves_per_s"]
+        out["speedup_vs_fp64"] = out["value"] / f64
+        for p, c in out["compare"].items():
+            if p != "f64":
+                c["speedup_vs_fp64"] = c["solves_per_s"] / f64
     print(json.dumps(out))
 
 

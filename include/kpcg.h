@@ -53,9 +53,18 @@ enum kp_bc { KP_BC_P = 0, KP_BC_D = 1, KP_BC_N = 2, KP_BC_DN = 3, KP_BC_ND = 4 }
  * (x = x1 + x2 + x3, each the round-to-nearest remainder of the previous)
  * and the six products xi*bj with i + j <= 4 (1-based) are accumulated in
  * FP32, the dropped terms being below 2^-24 relative; intermediates are FP32
- * and the input scale is as for BF16.  The Hadamard factor of eq. (4.6) is
- * always applied in at least FP32. */
-enum kp_prec { KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2, KP_PREC_BF16X6 = 3 };
+ * and the input scale is as for BF16.  I8X7 reaches FP64 accuracy on the
+ * int8 matrix cores: every row of the data (along the contracted axis) and
+ * every column of V_l is scaled by a power of two and cut into seven signed
+ * 7-bit integer digits; the 28 digit products i + j <= 6 (0-based) are summed
+ * exactly in int32 and recombined in FP64, the dropped terms and digits
+ * being about 2^-49 relative; intermediates are FP64 and nothing is scaled
+ * per right-hand side.  I8X7 plans need every axis a multiple of 16 and at
+ * most 512 (kp_plan_create returns KP_EINVAL otherwise).  The Hadamard
+ * factor of eq. (4.6) is always applied in at least FP32. */
+enum kp_prec {
+  KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2, KP_PREC_BF16X6 = 3, KP_PREC_I8X7 = 4
+};
 
 enum kp_status {
   KP_OK = 0,
@@ -310,7 +319,9 @@ int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
  * one fixed shape (wn 4, wm 2, wc 2) whatever the choice.  Ids 20 and 21
  * keep the whole operator in LDS and sweep row tiles with persistent blocks;
  * they serve contractions of length at most 128 only (kp_plan_set_tuning
- * refuses them for a longer axis, the autotuner skips them there). */
+ * refuses them for a longer axis, the autotuner skips them there).  I8X7
+ * products all run one kernel (64 rows per block, one 16-column fragment
+ * per step); its plans accept and report id 13 only. */
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
 
 /* Per-kernel timing (the library's tracing facility).  When enabled, every

@@ -17,7 +17,7 @@ typedef unsigned short u16;
 
 // Boundary conditions of eq. (3.1).
 enum Bc { BC_P = 0, BC_D = 1, BC_N = 2, BC_DN = 3, BC_ND = 4 };
-enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X6 = 3 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X6 = 3, PREC_I8X7 = 4 };
 
 // Termination codes kept per right-hand side on the device.
 enum Done { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, ZERO_RHS = 4 };

@@ -22,6 +22,8 @@
 // values CH*(l/16) .. +CH-1 of each k-block; output item v of lane l is column
 // l%16 and row 4*(l/16)+v (FP32, BF16) or 4*v+l/16 (FP64, measured on gfx950).
 #include <algorithm>
+#include <cfloat>
+#include <cmath>
 #include <type_traits>
 
 #include "kp_common.h"
@@ -32,6 +34,7 @@ namespace kp {
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // one 16-byte unit
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 template <int PREC> struct MT;
 template <> struct MT<PREC_F64> {
@@ -77,6 +80,11 @@ template <> struct MT<PREC_BF16X6> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[split_a(s)], b.p[split_b(s)], c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// The int8 split products (mp_oz below) keep FP64 between products.
+template <> struct MT<PREC_I8X7> {
+  using tc = double;
 };
 
 // Block = WR x WC waves (WR = 4 row groups, WC column groups); each wave owns
@@ -671,6 +679,297 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64-accurate products on the int8 matrix cores (PREC_I8X7), after the
+// splitting idea of Ozaki et al.: every value is a short sum of small
+// integers times powers of two, the integer products are exact on the
+// matrix cores, and only their recombination rounds.
+//   Data: each row r of X (its K values along the contracted axis) gets the
+//   power of two 2^e_r with |x| < 2^e_r and is cut into OZ_S = 7 digits,
+//       x = 2^e_r sum_i a_i 128^-(i+1),  a_i integers in [-127, 127]
+//   (truncation at every step, so all digits carry the sign of x; the
+//   remainder after the seventh is below 2^(e_r - 49)).
+//   Operator: column n of B likewise with 2^f_n, packed at plan time.
+//   Product: the digit products with i + j < OZ_S are summed exactly in
+//   int32 by v_mfma_i32_16x16x64_i8, one accumulator per diagonal d = i + j
+//   (|sum| <= 7 * 127^2 * K < 2^31 for K <= 512), and recombined in FP64,
+//       y = 2^(e_r + f_n - 14) sum_d 128^-d acc_d.
+//   The error per output is a few units of 2^-49 K max|x_r| max|b_n| at
+//   worst, far below what FP64 preconditioning needs (one CG iteration).
+// The data is read from HBM once and digitised in registers (16 consecutive
+// k per lane and k-block of 64); the operator digits stream through LDS one
+// column fragment (16 columns) at a time, double-buffered.  Block = 4 row
+// groups of 16 rows (64 rows); above K = 256 the k-blocks are split over two
+// waves per row group (KS = 2, eight waves), whose int32 sums are added
+// exactly through LDS.  A row with a non-finite value yields NaN outputs.
+// ---------------------------------------------------------------------------
+constexpr int OZ_S = 7;
+constexpr int OZ_BAD = 0x40000000;    // exponent marker of a non-finite row
+
+static int oz_split(int K) { return K > 256 ? 2 : 1; }
+static int oz_kb_per_wave(int K) {
+  const int nkb = (K + 63) / 64, ks = oz_split(K);
+  return (nkb + ks - 1) / ks;
+}
+// bytes of the operator digits: column fragments x padded k-blocks x digits
+// x 64 lanes x 16 bytes; the column exponents (int32) follow
+static size_t oz_digit_bytes(int K) {
+  return (size_t)((K + 15) / 16) * oz_split(K) * oz_kb_per_wave(K) * OZ_S * 64 * 16;
+}
+
+template <int KBW, int KS>
+__global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
+    const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
+    double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
+  constexpr int NT = 256 * KS;
+  constexpr int SU = KS * KBW * OZ_S * 64;      // 16-byte units per column fragment
+  constexpr int UPT = (SU + NT - 1) / NT;
+  __shared__ u4 lds[2][SU];
+  __shared__ double hmax[KS][4][16];
+  __shared__ v4i xch[KS == 2 ? 4 : 1][OZ_S][64];
+  __shared__ double fred[NT / 64][2];
+
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wr = wave & 3, h = wave >> 2;       // row group, k half
+  const int r0 = blockIdx.x * 64 + wr * 16;
+  const int r = r0 + l16;
+  const double* xr = X + (int64_t)rhs * N + (int64_t)(r < rows ? r : 0) * K;
+  const int kb0 = h * KBW;
+
+  // the lane's values, read once; the row's maximum and finiteness
+  d2 raw[KBW][8];
+  double mx = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb) {
+    const int k0 = (kb0 + kb) * 64 + 16 * g;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      raw[kb][q] = (d2){0.0, 0.0};
+      if (k0 < K) raw[kb][q] = *reinterpret_cast<const d2*>(xr + k0 + 2 * q);
+      const double a = fabs(raw[kb][q].x), b = fabs(raw[kb][q].y);
+      bad |= !(a <= DBL_MAX) | !(b <= DBL_MAX);
+      mx = fmax(mx, fmax(a, b));
+    }
+  }
+  mx = fmax(mx, __shfl_xor(mx, 16, 64));
+  mx = fmax(mx, __shfl_xor(mx, 32, 64));
+  bad |= __shfl_xor(bad, 16, 64);
+  bad |= __shfl_xor(bad, 32, 64);
+  if constexpr (KS == 2) {
+    if (g == 0) hmax[h][wr][l16] = bad ? INFINITY : mx;
+    __syncthreads();
+    const double o = hmax[h ^ 1][wr][l16];
+    bad |= !(o <= DBL_MAX);
+    mx = fmax(mx, o);
+  }
+  int e = 0;
+  if (mx > 0.0) (void)frexp(mx, &e);           // |x| < 2^e on the row
+
+  // digits, four values (one dword per digit) at a time
+  v4i xa[KBW][OZ_S];
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      int a[OZ_S][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const d2 pr = raw[kb][2 * w + (c >> 1)];
+        double t = ldexp((c & 1) ? pr.y : pr.x, -e);
+#pragma unroll
+        for (int s = 0; s < OZ_S; ++s) {
+          t *= 128.0;
+          const double d = trunc(t);
+          t -= d;
+          a[s][c] = bad ? 0 : (int)d;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < OZ_S; ++s) {
+        // low bytes of the four digits into one dword
+        const unsigned lo = __builtin_amdgcn_perm((unsigned)a[s][1], (unsigned)a[s][0], 0x0c0c0400u);
+        const unsigned hi = __builtin_amdgcn_perm((unsigned)a[s][3], (unsigned)a[s][2], 0x0c0c0400u);
+        xa[kb][s][w] = (int)__builtin_amdgcn_perm(hi, lo, 0x05040100u);
+      }
+    }
+  // exponents of this lane's output rows 4g + v (held by lane 4g + v)
+  const int eo = bad ? OZ_BAD : e;
+  int erow[4];
+  double rowsum[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    erow[v] = __shfl(eo, 4 * g + v, 64);
+    const int rr = r0 + 4 * g + v, rc = rr < rows ? rr : 0;
+    rowsum[v] = lc ? la[rc % a1] + (lb ? lb[rc / a1] : 0.0) : 0.0;
+  }
+
+  const int nfr = (K + 15) / 16;
+  u4 breg[UPT];
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) breg[q] = Bpk[min(tid + q * NT, SU - 1)];
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) lds[0][min(tid + q * NT, SU - 1)] = breg[q];
+  __syncthreads();
+
+  double* Yb = Y + (int64_t)rhs * N;
+  double fs[2] = {0.0, 0.0};                   // spectral <R, Z> and ||Z||^2
+  for (int j = 0; j < nfr; ++j) {
+    const int buf = j & 1;
+    const int64_t nxt = (int64_t)min(j + 1, nfr - 1) * SU;   // past the last: a reload
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) breg[q] = Bpk[nxt + min(tid + q * NT, SU - 1)];
+    v4i acc[OZ_S];
+#pragma unroll
+    for (int d = 0; d < OZ_S; ++d) acc[d] = (v4i){0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < KBW; ++kb) {
+      v4i b[OZ_S];
+#pragma unroll
+      for (int s = 0; s < OZ_S; ++s) {
+        const u4 u = lds[buf][((kb0 + kb) * OZ_S + s) * 64 + lane];
+        b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+      }
+      // consecutive products update different diagonals
+#pragma unroll
+      for (int i = 0; i < OZ_S; ++i)
+#pragma unroll
+        for (int s = 0; s + i < OZ_S; ++s)
+          acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xa[kb][i], b[s], acc[i + s], 0, 0, 0);
+    }
+    if constexpr (KS == 2) {
+      if (h == 1) {
+#pragma unroll
+        for (int d = 0; d < OZ_S; ++d) xch[wr][d][lane] = acc[d];
+      }
+      __syncthreads();
+      if (h == 0) {
+#pragma unroll
+        for (int d = 0; d < OZ_S; ++d) acc[d] += xch[wr][d][lane];
+      }
+    }
+    const int n = 16 * j + l16;
+    if (h == 0 && n < K) {
+      const int f = fexp[n];
+      const double lcn = lc ? lc[n] : 0.0;
+      double out[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * g + v;
+        double val = (double)acc[OZ_S - 1][v];
+#pragma unroll
+        for (int d = OZ_S - 2; d >= 0; --d) val = (double)acc[d][v] + val * (1.0 / 128.0);
+        val = erow[v] == OZ_BAD ? NAN : ldexp(val, erow[v] + f - 14);
+        const double rhat = val;
+        if (lc) val *= ghat(rowsum[v] + lcn);
+        if (gt) val *= gt[(int64_t)n * rows + (rr < rows ? rr : 0)];
+        if (rpart && rr < rows) {
+          fs[0] += rhat * val;
+          fs[1] += val * val;
+        }
+        out[v] = val;
+      }
+      double* dst = Yb + (int64_t)n * rows + r0 + 4 * g;
+      if ((rows & 1) == 0 && r0 + 4 * g + 3 < rows) {
+        *reinterpret_cast<d2*>(dst) = (d2){out[0], out[1]};
+        *reinterpret_cast<d2*>(dst + 2) = (d2){out[2], out[3]};
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (r0 + 4 * g + v < rows) dst[v] = out[v];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) lds[buf ^ 1][min(tid + q * NT, SU - 1)] = breg[q];
+    __syncthreads();
+  }
+  if (rpart) {
+    // fixed-order block reduction: lanes, then waves in order
+    fs[0] = wave_sum(fs[0]);
+    fs[1] = wave_sum(fs[1]);
+    if (lane == 0) {
+      fred[wave][0] = fs[0];
+      fred[wave][1] = fs[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        t0 += fred[w][0];
+        t1 += fred[w][1];
+      }
+      slot_ptr(rpart, rhs, S_DOT)[blockIdx.x] = t0;
+      slot_ptr(rpart, rhs, S_SUM)[blockIdx.x] = 0.0;
+      slot_ptr(rpart, rhs, S_SQ)[blockIdx.x] = t1;
+      slot_ptr(rpart, rhs, S_AUX2)[blockIdx.x] = 0.0;
+    }
+  }
+}
+
+// Packs B (K x K, row-major, FP64) as the digits read by mp_oz: for column
+// fragment j, k-block kb (padded to the split), digit s and lane 16 g + c,
+// 16 bytes hold digit s of B[64 kb + 16 g + b][16 j + c], b = 0..15; then
+// the K column exponents f_n (max_k |B[k][n]| < 2^f_n).
+static void oz_pack(const double* B, int K, void* dst) {
+  const int nkb = oz_split(K) * oz_kb_per_wave(K);
+  const size_t db = oz_digit_bytes(K);
+  int8_t* o = (int8_t*)dst;
+  for (size_t i = 0; i < db; ++i) o[i] = 0;
+  int* fx = (int*)(o + db);
+  for (int n = 0; n < K; ++n) {
+    double mx = 0.0;
+    for (int k = 0; k < K; ++k) mx = std::max(mx, std::fabs(B[(size_t)k * K + n]));
+    int f = 0;
+    if (mx > 0.0) (void)std::frexp(mx, &f);
+    fx[n] = f;
+    const int j = n / 16, c = n % 16;
+    for (int k = 0; k < K; ++k) {
+      double t = std::ldexp(B[(size_t)k * K + n], -f);
+      const int kb = k / 64, g = (k % 64) / 16, b = k % 16;
+      for (int s = 0; s < OZ_S; ++s) {
+        t *= 128.0;
+        const double d = std::trunc(t);
+        t -= d;
+        const size_t unit = (((size_t)j * nkb + kb) * OZ_S + s) * 64 + 16 * g + c;
+        o[unit * 16 + b] = (int8_t)(int)d;
+      }
+    }
+  }
+}
+
+static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
+                      const RhsState* st, const double* la, const double* lb, const double* lc,
+                      int a1, const double* gt, double* rpart, hipStream_t s) {
+  const int K = op.n[ax];
+  const int rows = (int)(op.N / K);
+  const char* Bp = (const char*)(fwd ? op.Bf[ax] : op.Bb[ax]);
+  const int* fx = (const int*)(Bp + oz_digit_bytes(K));
+  dim3 grid((rows + 63) / 64, batch);
+  const int kbw = oz_kb_per_wave(K), ks = oz_split(K);
+#define KP_OZ(W, S_)                                                                         \
+  hipLaunchKernelGGL((mp_oz<W, S_>), grid, dim3(256 * S_), 0, s, (const u4*)Bp, fx,          \
+                     (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
+                     gt, rpart)
+  if (ks == 1) {
+    switch (kbw) {
+      case 1: KP_OZ(1, 1); break;
+      case 2: KP_OZ(2, 1); break;
+      case 3: KP_OZ(3, 1); break;
+      default: KP_OZ(4, 1); break;
+    }
+  } else {
+    if (kbw == 3) KP_OZ(3, 2);
+    else KP_OZ(4, 2);
+  }
+#undef KP_OZ
+}
+
+
 // ------------------------------------------------------------------ host ----
 // Tile configurations (column fragments per wave, row fragments per wave,
 // column wave groups).  Block = 4 x wc waves, rows per block 64*wm, columns
@@ -689,6 +988,7 @@ static const MpCfg kCfgs[] = {
 };
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kResFirst = 20;   // ids from here on are operator-resident
+constexpr int kOzCfg = 13;      // the id an int8 split plan reports (mp_oz has one shape)
 
 int mp_num_configs() { return kNumCfgs; }
 
@@ -703,6 +1003,7 @@ bool mp_config_fits(int id, int K) { return !mp_config_resident(id) || K <= 128;
 // fragments of 4 or more columns, in BF16 the 16 x 2 tile).
 bool mp_config_allowed(int id, int prec) {
   if (id < 0 || id >= kNumCfgs) return false;
+  if (prec == PREC_I8X7) return id == kOzCfg;   // one kernel serves every product
   if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
   if (prec == PREC_BF16) return id != 16;
   if (prec == PREC_BF16X6) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
@@ -717,6 +1018,7 @@ void mp_config(int id, int* wn, int* wm, int* wc) {
 // block width covers K most tightly (eight waves per block), else the widest
 // single-group tile.
 int mp_default_config(int K, int prec) {
+  if (prec == PREC_I8X7) return kOzCfg;
   const int frags = (K + 15) / 16;
   int best = -1, best_cb = 1 << 30;
   for (int id = 0; id < kNumCfgs; ++id) {
@@ -740,6 +1042,7 @@ static void packed_geometry(int K, int prec, int* npk, int* nkb) {
 }
 
 size_t mp_packed_bytes(int K, int prec) {
+  if (prec == PREC_I8X7) return oz_digit_bytes(K) + (size_t)K * sizeof(int);
   int npk, nkb;
   packed_geometry(K, prec, &npk, &nkb);
   return (size_t)nkb * chunk_k(prec) * npk * elem_size(prec) * split_terms(prec);
@@ -765,6 +1068,10 @@ static double bf16_value(uint16_t h) {
 // the round-to-nearest remainder of the previous, from the FP64 value) as
 // three consecutive 16-byte units.
 void mp_pack(const double* B, int K, int prec, void* dst) {
+  if (prec == PREC_I8X7) {
+    oz_pack(B, K, dst);
+    return;
+  }
   int npk, nkb;
   packed_geometry(K, prec, &npk, &nkb);
   const int KBk = chunk_k(prec), es = elem_size(prec), T = split_terms(prec);
@@ -851,10 +1158,16 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
                       const double* la, const double* lb, const double* lc, int a1,
                       const double* gt, hipStream_t s, double* rpart = nullptr,
                       int rscl = 0) {
+  trace_begin(cls, s);
+  if constexpr (PREC == PREC_I8X7) {
+    (void)cfg;
+    launch_oz(op, ax, fwd, X, Y, batch, st, la, lb, lc, a1, gt, rpart, s);
+    trace_end(cls, s);
+    return;
+  } else {
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
   const int CH = MT<PREC>::CH;
-  trace_begin(cls, s);
   if (K % CH != 0) {
     // rows too ragged for 16-byte loads: one scalar-load tile serves every
     // configuration (such grids are small)
@@ -921,6 +1234,7 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
 #undef KP_COMMON_CASES
 #undef KP_CASE
   trace_end(cls, s);
+  }
 }
 
 // Product q of one application Z = M(R) (Algs. 6-7) for `batch` right-hand
@@ -933,7 +1247,7 @@ template <int PREC>
 static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, void* T0,
                         void* T1, int batch, const RhsState* st, hipStream_t s) {
   using tc = typename MT<PREC>::tc;
-  const int scl = (PREC == PREC_F64) ? 0 : 1;
+  const int scl = (PREC == PREC_F64 || PREC == PREC_I8X7) ? 0 : 1;
   const int dim = op.dim, ax = q % dim, last = 2 * dim - 1;
   const bool fwd = q < dim;
   void* T[2] = {T0, T1};
@@ -996,6 +1310,10 @@ int pinv_ghat_blocks(const PinvOps& op) {
   const int q = op.dim - 1, ax = q;
   const int K = op.n[ax];
   const int64_t rows = op.N / K;
+  if (op.prec == PREC_I8X7) {   // mp_oz: one block per 64 rows
+    const int64_t t = (rows + 63) / 64;
+    return t > (1 << 30) ? (1 << 30) : (int)t;
+  }
   const int CH = op.prec == PREC_F64 || op.prec == PREC_F32 ? 4 : 8;
   int wn = 4, wm = 2, wc = 2;   // the scalar-load tile of ragged contractions
   // the operator-resident tiles write one partial per 64-row tile
@@ -1020,6 +1338,7 @@ void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch
     case PREC_F64: product_t<PREC_F64>(op, q, in, out, batch, s); break;
     case PREC_F32: product_t<PREC_F32>(op, q, in, out, batch, s); break;
     case PREC_BF16X6: product_t<PREC_BF16X6>(op, q, in, out, batch, s); break;
+    case PREC_I8X7: product_t<PREC_I8X7>(op, q, in, out, batch, s); break;
     default: product_t<PREC_BF16>(op, q, in, out, batch, s); break;
   }
 }
@@ -1030,6 +1349,7 @@ void pinv_step(const PinvOps& op, int q, const double* R, double* Z, void* T0, v
     case PREC_F64: pinv_step_t<PREC_F64>(op, q, R, Z, T0, T1, batch, st, s); break;
     case PREC_F32: pinv_step_t<PREC_F32>(op, q, R, Z, T0, T1, batch, st, s); break;
     case PREC_BF16X6: pinv_step_t<PREC_BF16X6>(op, q, R, Z, T0, T1, batch, st, s); break;
+    case PREC_I8X7: pinv_step_t<PREC_I8X7>(op, q, R, Z, T0, T1, batch, st, s); break;
     default: pinv_step_t<PREC_BF16>(op, q, R, Z, T0, T1, batch, st, s); break;
   }
 }
@@ -1040,6 +1360,7 @@ void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T
     case PREC_F64: pinv_apply_t<PREC_F64>(op, R, Z, T0, T1, batch, st, s); break;
     case PREC_F32: pinv_apply_t<PREC_F32>(op, R, Z, T0, T1, batch, st, s); break;
     case PREC_BF16X6: pinv_apply_t<PREC_BF16X6>(op, R, Z, T0, T1, batch, st, s); break;
+    case PREC_I8X7: pinv_apply_t<PREC_I8X7>(op, R, Z, T0, T1, batch, st, s); break;
     default: pinv_apply_t<PREC_BF16>(op, R, Z, T0, T1, batch, st, s); break;
   }
 }

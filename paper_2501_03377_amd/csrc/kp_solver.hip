@@ -165,7 +165,9 @@ namespace {
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-size_t elem_bytes(int prec) { return prec == PREC_F64 ? 8 : (prec == PREC_BF16 ? 2 : 4); }
+size_t elem_bytes(int prec) {
+  return (prec == PREC_F64 || prec == PREC_I8X7) ? 8 : (prec == PREC_BF16 ? 2 : 4);
+}
 
 struct Layout {
   size_t R, P, W, Z, T0, T1, J, C1, C2, C3, part, st, total;
@@ -351,10 +353,16 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   if (!out || !bc) return KP_EINVAL;
   *out = nullptr;
   if (nx < 3 || ny < 3 || !(nz >= 3 || nz == 1)) return KP_EINVAL;
-  if (prec < PREC_F64 || prec > PREC_BF16X6 || max_batch < 1) return KP_EINVAL;
+  if (prec < PREC_F64 || prec > PREC_I8X7 || max_batch < 1) return KP_EINVAL;
   const int dim = nz == 1 ? 2 : 3;
   for (int a = 0; a < dim; ++a)
     if (bc[a] < 0 || bc[a] > 4) return KP_EINVAL;
+  // the int8 split products digitise 16 values per lane along every axis
+  if (prec == PREC_I8X7) {
+    const int n[3] = {nx, ny, nz};
+    for (int a = 0; a < dim; ++a)
+      if (n[a] % 16 != 0 || n[a] > 512) return KP_EINVAL;
+  }
   const int64_t N = (int64_t)nx * ny * nz;
   if (N >= ((int64_t)1 << 31)) return KP_EINVAL;
   if (max_batch > 65535) return KP_EINVAL;
@@ -755,7 +763,7 @@ int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, in
   p->last_u = u;
   int done_iters = 0;
   int chunk = p->expect_iters > 0 ? p->expect_iters
-              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : (p->prec == PREC_F64 ? 1 : (p->prec == PREC_BF16 ? 8 : 2)));
+              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : ((p->prec == PREC_F64 || p->prec == PREC_I8X7) ? 1 : (p->prec == PREC_BF16 ? 8 : 2)));
   // a first chunk that ends where the previous solve stopped, before the
   // last preconditioning, launches no kernels for finished right-hand sides
   const bool split_first = p->expect_iters > 0 && p->expect_split;
@@ -1144,7 +1152,7 @@ int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
 }
 
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
-  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_BF16X6) return KP_EINVAL;
+  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_I8X7) return KP_EINVAL;
   if (!mp_config_allowed(id, prec)) return KP_EINVAL;
   mp_config(id, wn, wm, wc);
   return KP_OK;

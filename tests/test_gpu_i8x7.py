@@ -1,0 +1,136 @@
+"""GPU parity of the FP64-accurate preconditioner on the int8 matrix cores
+(every value cut into seven 7-bit digits, 28 exact digit products): the
+application against the oracle's pseudoinverse (Algs. 6-7), and whole solves
+(Algorithm 1) against the converged oracle solution."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import grid_dims, oracle_pinv, oracle_solve, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+# the FP64 preconditioner's bound in the other parity tests
+PINV_TOL = 1e-12
+
+
+def _plan(shape, bcs, prec="i8x7", max_batch=1):
+    from paper_2501_03377_amd import Plan
+    nx, ny, nz = grid_dims(shape)
+    return Plan(nx, ny, nz, bcs, prec=prec, max_batch=max_batch)
+
+
+@pytest.mark.parametrize("shape,bcs", [
+    ((16, 16, 16), ("N", "N", "N")),      # one k-block of 64, 16 of it used
+    ((32, 48, 80), ("P", "DN", "ND")),    # 80: a partial second k-block
+    ((48, 64, 192), ("D", "P", "N")),     # 192: three k-blocks per wave
+    ((16, 32, 512), ("P", "P", "D")),     # 512: k split over two waves
+    ((16, 48, 320), ("N", "D", "DN")),    # 320: split, padded k-blocks
+    ((64, 80), ("P", "N")),               # 2D; 80 rows: a ragged row tile
+    ((16, 16), ("D", "D")),
+])
+def test_i8x7_pinv_parity(shape, bcs):
+    rng = np.random.default_rng(40)
+    r = rng.standard_normal(shape)
+    plan = _plan(shape, bcs)
+    z = to_host(plan.apply_pinv(to_dev(r)))
+    plan.close()
+    err = rel(z, oracle_pinv(r, bcs))
+    print(f"pinv i8x7 {shape} {bcs}: rel err {err:.3e}")
+    assert err <= PINV_TOL, err
+
+
+def test_i8x7_is_as_accurate_as_fp64():
+    # the split keeps about 49 bits of every row and column: its error to the
+    # exact pseudoinverse is within a small factor of the FP64 matrix cores'
+    shape, bcs = (32, 64, 128), ("P", "P", "DN")
+    rng = np.random.default_rng(41)
+    r = rng.standard_normal(shape)
+    ref = oracle_pinv(r, bcs)
+    err = {}
+    for prec in ("f64", "i8x7", "f32"):
+        plan = _plan(shape, bcs, prec=prec)
+        err[prec] = rel(to_host(plan.apply_pinv(to_dev(r))), ref)
+        plan.close()
+    print("pinv errors", err)
+    assert err["i8x7"] <= 10 * err["f64"] + 1e-14, err
+    assert err["i8x7"] * 1e6 <= err["f32"], err
+
+
+def test_i8x7_rows_of_any_magnitude():
+    # every row gets its own power of two: right-hand sides from 1e-200 to
+    # 1e200, and rows of one dominant entry, keep their relative accuracy;
+    # each right-hand side of a batch equals its single application exactly
+    shape, bcs = (16, 32, 64), ("D", "N", "P")
+    rng = np.random.default_rng(42)
+    r = rng.standard_normal((3,) + shape)
+    r[0] *= 1e-200
+    r[2] *= 1e200
+    r[1, :, :, 5] *= 1e9
+    plan = _plan(shape, bcs, max_batch=3)
+    zb = to_host(plan.apply_pinv(to_dev(r)))
+    for b in range(3):
+        z1 = to_host(plan.apply_pinv(to_dev(r[b])))
+        assert np.array_equal(zb[b], z1), b
+        s = 1e200 if b == 0 else (1e-200 if b == 2 else 1.0)
+        err = rel(zb[b] * s, oracle_pinv(r[b] * s, bcs))
+        assert err <= PINV_TOL, (b, err)
+    plan.close()
+
+
+def test_i8x7_nonfinite_input_gives_nonfinite_output():
+    # a NaN in R reaches every output, as in FP64 arithmetic (the solver's
+    # non-finite checks rely on it)
+    shape, bcs = (16, 16, 32), ("P", "D", "N")
+    r = np.random.default_rng(43).standard_normal(shape)
+    r[3, 4, 5] = np.nan
+    plan = _plan(shape, bcs)
+    z = to_host(plan.apply_pinv(to_dev(r)))
+    plan.close()
+    assert np.isnan(z).all()
+
+
+@pytest.mark.parametrize("shape,bcs", [
+    ((32, 64, 128), ("P", "P", "DN")),
+    ((48, 48, 48), ("N", "N", "N")),
+    ((64, 32, 96), ("P", "P", "D")),
+    ((64, 96), ("D", "N")),
+])
+def test_i8x7_solve_one_iteration(shape, bcs):
+    # as with the FP64 pseudoinverse, one iteration reaches tol 1e-10
+    from paper_2501_03377_amd import Plan
+    eta = synth.charge_field(shape, ncharges=2000, seed=9)
+    nx, ny, nz = grid_dims(shape)
+    plan = Plan(nx, ny, nz, bcs, prec="i8x7")
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, raise_on_error=False)
+    u = to_host(u)
+    plan.close()
+    err = rel(u, oracle_solve(eta, bcs))
+    print(f"i8x7 {shape} {bcs}: iters {res[0]['iterations']} err {err:.3e} "
+          f"rel_res {res[0]['rel_res']:.3e} true {res[0]['true_rel_res']:.3e}")
+    assert rc == 0, res
+    assert res[0]["iterations"] == 1, res
+    assert err <= 1e-10 and res[0]["true_rel_res"] <= 1e-10
+
+
+def test_i8x7_batch_solve_and_replay():
+    # a batch of 4 all-Neumann right-hand sides: each equals its single solve
+    # bitwise, a repeated solve (graph replay) is bitwise identical, and all
+    # match the oracle
+    from paper_2501_03377_amd import Plan
+    shape, bcs = (32, 32, 64), ("N", "N", "N")
+    eta = np.stack([synth.charge_field(shape, ncharges=1000, seed=20 + b) for b in range(4)])
+    plan = Plan(64, 32, 32, bcs, prec="i8x7", max_batch=4)
+    ub, res, _, rc = plan.solve(to_dev(eta), tol=1e-10, raise_on_error=False)
+    ub = to_host(ub)
+    assert rc == 0, res
+    ub2 = to_host(plan.solve(to_dev(eta), tol=1e-10)[0])
+    assert np.array_equal(ub, ub2)
+    for b in range(4):
+        u1 = to_host(plan.solve(to_dev(eta[b]), tol=1e-10)[0])
+        assert np.array_equal(ub[b], u1), b
+        err = rel(ub[b], oracle_solve(eta[b], bcs))
+        assert err <= 1e-10, (b, err)
+    plan.close()
