@@ -35,6 +35,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));   // one 16-byte unit
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 template <int PREC> struct MT;
 template <> struct MT<PREC_F64> {
@@ -687,8 +688,11 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 //   Data: each row r of X (its K values along the contracted axis) gets the
 //   power of two 2^e_r with |x| < 2^e_r and is cut into OZ_S = 7 digits,
 //       x = 2^e_r sum_i a_i 128^-(i+1),  a_i integers in [-127, 127]
-//   (truncation at every step, so all digits carry the sign of x; the
-//   remainder after the seventh is below 2^(e_r - 49)).
+//   (truncation at every step, so all digits carry the sign of x and a
+//   small value has small digits; the remainder after the seventh is below
+//   2^(e_r - 49)).  Digits of one sign matter: with two's complement digits
+//   a small negative value has large low digits, and the dropped products
+//   below would then carry the full 2^-49 scale for every such value.
 //   Operator: column n of B likewise with 2^f_n, packed at plan time.
 //   Product: the digit products with i + j < OZ_S are summed exactly in
 //   int32 by v_mfma_i32_16x16x64_i8, one accumulator per diagonal d = i + j
@@ -770,32 +774,53 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
   }
   int e = 0;
   if (mx > 0.0) (void)frexp(mx, &e);           // |x| < 2^e on the row
+  e = max(e, -1021);                            // images of subnormal rows fit 49 bits too
 
-  // digits, four values (one dword per digit) at a time
+  // Digits from the bit pattern: the image F = floor(|x| 2^(49 - e)) < 2^49
+  // is the 53-bit significand shifted right by e + 1026 - max(ef, 1) >= 4
+  // (ef the biased exponent field; a non-finite row shifts everything out);
+  // its 7-bit fields from the top are the digit magnitudes, which take the
+  // sign of x (negated two values at a time on 16-bit halves).  These are
+  // the digits of truncating |x| 2^-e one base-128 place at a time.
+  const int cshift = bad ? 4096 : e + 1026;
   v4i xa[KBW][OZ_S];
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb)
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      int a[OZ_S][4];
+      unsigned u[OZ_S][4], sg[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const d2 pr = raw[kb][2 * w + (c >> 1)];
-        double t = ldexp((c & 1) ? pr.y : pr.x, -e);
-#pragma unroll
-        for (int s = 0; s < OZ_S; ++s) {
-          t *= 128.0;
-          const double d = trunc(t);
-          t -= d;
-          a[s][c] = bad ? 0 : (int)d;
-        }
+        const uint64_t bits = (uint64_t)__double_as_longlong((c & 1) ? pr.y : pr.x);
+        const unsigned hi = (unsigned)(bits >> 32);
+        const unsigned ef = (hi >> 20) & 0x7ffu;
+        const unsigned sh = (unsigned)min(cshift - (int)max(ef, 1u), 63);
+        const uint64_t sig = ((uint64_t)((hi & 0xfffffu) | (min(ef, 1u) << 20)) << 32) |
+                             (bits & 0xffffffffull);
+        const uint64_t F = sig >> sh;
+        const unsigned fh = (unsigned)(F >> 32), fl = (unsigned)F;
+        sg[c] = (unsigned)((int)hi >> 31);      // 0 or all ones
+        u[0][c] = fh >> 10;
+        u[1][c] = (fh >> 3) & 127u;
+        u[2][c] = ((fh << 4) | (fl >> 28)) & 127u;
+        u[3][c] = (fl >> 21) & 127u;
+        u[4][c] = (fl >> 14) & 127u;
+        u[5][c] = (fl >> 7) & 127u;
+        u[6][c] = fl & 127u;
       }
+      const unsigned m01 = (sg[0] & 0xffffu) | (sg[1] & 0xffff0000u);
+      const unsigned m23 = (sg[2] & 0xffffu) | (sg[3] & 0xffff0000u);
 #pragma unroll
       for (int s = 0; s < OZ_S; ++s) {
-        // low bytes of the four digits into one dword
-        const unsigned lo = __builtin_amdgcn_perm((unsigned)a[s][1], (unsigned)a[s][0], 0x0c0c0400u);
-        const unsigned hi = __builtin_amdgcn_perm((unsigned)a[s][3], (unsigned)a[s][2], 0x0c0c0400u);
-        xa[kb][s][w] = (int)__builtin_amdgcn_perm(hi, lo, 0x05040100u);
+        // (d ^ m) - m on each 16-bit half negates where m is all ones; the
+        // low bytes of the four signed digits then make one dword
+        const u16x2 p01 = __builtin_bit_cast(u16x2, (u[s][0] | (u[s][1] << 16)) ^ m01) -
+                          __builtin_bit_cast(u16x2, m01);
+        const u16x2 p23 = __builtin_bit_cast(u16x2, (u[s][2] | (u[s][3] << 16)) ^ m23) -
+                          __builtin_bit_cast(u16x2, m23);
+        xa[kb][s][w] = (int)__builtin_amdgcn_perm(__builtin_bit_cast(unsigned, p23),
+                                                  __builtin_bit_cast(unsigned, p01), 0x06040200u);
       }
     }
   // exponents of this lane's output rows 4g + v (held by lane 4g + v)
