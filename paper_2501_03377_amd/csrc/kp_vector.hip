@@ -15,6 +15,8 @@
 
 namespace kp {
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
 constexpr int VT = 256;
 
 // One axis of the 3/5/7-point stencil: 2c - lo - hi with the ghost rule of the
@@ -915,6 +917,8 @@ void launch_diag(const Geom& g, const double* eta, const double* U, double* part
 // k = 4 g + step.
 // With w set, the tile is not stored: its sums sum d^2 w[i] and sum d^2
 // (i the element's index in D) go to part[rhs][tile][2] instead.
+// VA: A is contiguous in k (a_k = 1, K a multiple of 16, 16-byte aligned
+// rows), so a lane's four consecutive k come as two 16-byte loads.
 struct SmallGemm {
   const double* A; int64_t a_r, a_k, a_p, a_rhs;
   const double* B; int64_t b_k, b_c, b_p, b_rhs;
@@ -923,6 +927,7 @@ struct SmallGemm {
   const double* w; double* part;
 };
 
+template <bool VA>
 __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* st) {
   const int rhs = blockIdx.y;
   if (!st[rhs].need_cert) return;
@@ -945,15 +950,23 @@ __global__ __launch_bounds__(VT) void k_cert_gemm(SmallGemm q, const RhsState* s
   for (int kb = wave; kb < nkb; kb += VT / 64) {
     // every load of the k-block first, then its eight MFMAs
     double a[4], b0[4], b1[4];
+    if constexpr (VA) {
+      const d2 lo = *reinterpret_cast<const d2*>(A + kb * 16 + 4 * grp);
+      const d2 hi = *reinterpret_cast<const d2*>(A + kb * 16 + 4 * grp + 2);
+      a[0] = rok ? lo.x : 0.0;
+      a[1] = rok ? lo.y : 0.0;
+      a[2] = rok ? hi.x : 0.0;
+      a[3] = rok ? hi.y : 0.0;
+    }
 #pragma unroll
     for (int st4 = 0; st4 < 4; ++st4) {
       const int k = kb * 16 + 4 * grp + st4;
       const bool kok = k < q.K;
       const int kc = kok ? k : 0;
-      a[st4] = A[(int64_t)kc * q.a_k];
+      if constexpr (!VA) a[st4] = A[(int64_t)kc * q.a_k];
       b0[st4] = B0[(int64_t)kc * q.b_k];
       b1[st4] = B1[(int64_t)kc * q.b_k];
-      a[st4] = (rok && kok) ? a[st4] : 0.0;
+      if constexpr (!VA) a[st4] = (rok && kok) ? a[st4] : 0.0;
       b0[st4] = (c0ok && kok) ? b0[st4] : 0.0;
       b1[st4] = (c1ok && kok) ? b1[st4] : 0.0;
     }
@@ -1049,7 +1062,14 @@ void launch_cert(const Geom& g, const CertOps& c, const double* R, double* C1, d
   const int64_t rows1 = g.N / g.nx;                 // (z, y) rows of R
   auto run = [&](const SmallGemm& q) {
     const int tiles = ((q.rows + 15) / 16) * ((q.cols + 31) / 32) * q.planes;
-    hipLaunchKernelGGL(k_cert_gemm, dim3(tiles, batch), dim3(VT), 0, s, q, (const RhsState*)st);
+    const bool va = q.a_k == 1 && q.K % 16 == 0 && q.a_r % 2 == 0 && q.a_p % 2 == 0 &&
+                    q.a_rhs % 2 == 0 && ((uintptr_t)q.A & 15) == 0;
+    if (va)
+      hipLaunchKernelGGL(k_cert_gemm<true>, dim3(tiles, batch), dim3(VT), 0, s, q,
+                         (const RhsState*)st);
+    else
+      hipLaunchKernelGGL(k_cert_gemm<false>, dim3(tiles, batch), dim3(VT), 0, s, q,
+                         (const RhsState*)st);
   };
   trace_begin(KC_CERT, s);
   const int nzp = g.dim == 3 ? g.nz : 1;
