@@ -445,7 +445,8 @@ typedef struct {
 int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_batch);
 /* Queues a request (the descriptor is copied; eta and u are used later, see
  * kp_request).  Never blocks on the GPU.  Returns KP_OK or KP_EINVAL (bad
- * grid, boundary code, precision, tolerance, flags or null eta). */
+ * grid, boundary code, precision, tolerance, flags or null eta; for
+ * KP_PREC_I8X7 also an axis that is not a multiple of 16 or exceeds 512). */
 int kp_server_submit(kp_server* srv, const kp_request* req);
 /* Moves up to `max` completions to `out` (host array), waiting up to
  * timeout_s seconds for the first one; returns how many (0 on timeout), or

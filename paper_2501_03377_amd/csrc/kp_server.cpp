@@ -354,6 +354,13 @@ bool valid_request(const kp_request* r) {
   for (int a = 0; a < (r->nz > 1 ? 3 : 2); ++a)
     if (r->bc[a] < KP_BC_P || r->bc[a] > KP_BC_ND) return false;
   if (r->prec < KP_PREC_F64 || r->prec > KP_PREC_I8X7) return false;
+  if (r->prec == KP_PREC_I8X7) {
+    // the int8 split preconditioner's plans need every axis a multiple of 16
+    // and at most 512
+    const int n[3] = {r->nx, r->ny, r->nz};
+    for (int a = 0; a < (r->nz > 1 ? 3 : 2); ++a)
+      if (n[a] % 16 != 0 || n[a] > 512) return false;
+  }
   if (!(r->tol > 0.0) || !std::isfinite(r->tol)) return false;
   if (r->max_iter < 1 || r->max_iter > 1000000) return false;
   if (r->flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH))

@@ -113,3 +113,32 @@ def test_server_evicts_idle_plans_and_rejects_oversize():
         assert c["status"] == -2 and srv.stats()["rejected"] == 1
     finally:
         srv.close()
+
+
+def test_server_int8_split_requests():
+    # I8X7 requests are served like the others, in one iteration, and match
+    # the oracle; a grid the int8 split cannot take (an axis not a multiple
+    # of 16) is refused at submission, before any work is queued
+    from paper_2501_03377_amd import Server
+    from paper_2501_03377_amd.kpcg import KpError
+    srv = Server(hbm_budget=0, workers=2, max_batch=4)
+    try:
+        cases = [((32, 32, 48), ("P", "P", "DN")), ((16, 32, 32), ("N", "N", "N")),
+                 ((48, 64), ("D", "N"))]
+        etas, outs = {}, {}
+        for k, (shape, bcs) in enumerate(cases):
+            etas[k] = synth.charge_field(shape, ncharges=60, seed=1500 + k)
+            outs[k] = np.empty(shape)
+            srv.submit(k, etas[k], bcs, tol=1e-10, prec="i8x7", u=outs[k])
+        with pytest.raises(KpError):
+            srv.submit(99, synth.charge_field((20, 32, 32), ncharges=10, seed=1599),
+                       ("P", "P", "D"), prec="i8x7")
+        done = _drain(srv, len(cases))
+        for k, (shape, bcs) in enumerate(cases):
+            c = done[k]
+            assert c["status"] == 0 and c["iterations"] == 1, c
+            err = rel(outs[k], oracle_solve(etas[k], bcs))
+            assert err <= 1e-10, (k, err, c)
+        assert srv.stats()["completed"] == len(cases)
+    finally:
+        srv.close()
