@@ -456,14 +456,19 @@ def serving_bench(args):
 
     comp = {}
     if not args.no_compare:
-        log("closed loop, FP64 preconditioner")
-        srv = Server(hbm_budget=budget, workers=args.workers, max_batch=args.max_batch)
-        try:
-            closed_loop(srv, "f64")
-            _, mu64 = closed_loop(srv, "f64")
-            comp["f64"] = {"solves_per_s": mu64}
-        finally:
-            srv.close()
+        # the same stream with the FP64 preconditioner, and with its int8
+        # split where every grid allows it
+        for p in ("f64", "i8x7"):
+            if p == prec or (p == "i8x7" and not all(i8x7_fits(g) for g in grids)):
+                continue
+            log(f"closed loop, {'FP64' if p == 'f64' else p.upper()} preconditioner")
+            srv = Server(hbm_budget=budget, workers=args.workers, max_batch=args.max_batch)
+            try:
+                closed_loop(srv, p)
+                _, mu_p = closed_loop(srv, p)
+                comp[p] = {"solves_per_s": mu_p}
+            finally:
+                srv.close()
 
     lv = levels["0.8"]
     out = {
@@ -488,6 +493,9 @@ def serving_bench(args):
     }
     if "f64" in comp:
         out["speedup_vs_fp64"] = mu / comp["f64"]["solves_per_s"]
+        for p, c in comp.items():
+            if p != "f64":
+                c["speedup_vs_fp64"] = c["solves_per_s"] / comp["f64"]["solves_per_s"]
     if not args.no_cpu_baseline:
         # the oracle on the sampled requests: first one request of every
         # (grid, singular) stratum present, smallest grids first, then the
