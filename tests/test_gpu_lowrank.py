@@ -11,7 +11,7 @@ from oracle.lowrank import lowrank_apply, lowrank_init
 
 pytestmark = pytest.mark.gpu
 
-PREC_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16x6": 2e-4}
+PREC_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16x6": 2e-4, "i8x7": 1e-12}
 
 
 def _plan(shape, bcs, prec="f64", max_batch=1):
@@ -25,7 +25,10 @@ def _plan(shape, bcs, prec="f64", max_batch=1):
                                                  ((100, 50), ("N", "P"), 3, "f64"),
                                                  ((120, 40), ("DN", "P"), 16, "f64"),
                                                  ((70, 36), ("P", "ND"), 2, "f32"),
-                                                 ((64, 64), ("D", "D"), 3, "bf16x6")])
+                                                 ((64, 64), ("D", "D"), 3, "bf16x6"),
+                                                 # the int8 split carries the G_r table too
+                                                 ((48, 64), ("D", "N"), 3, "i8x7"),
+                                                 ((80, 32), ("N", "P"), 5, "i8x7")])
 def test_apply_parity(shape, bcs, rank, prec):
     rng = np.random.default_rng(90)
     batch = 2
