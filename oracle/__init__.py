@@ -20,8 +20,12 @@ Modules
   pinv       pseudoinverse preconditioner: initialisation (Algs. 4 and 5) and
              application (Algs. 6 and 7); eigenvectors come from LAPACK, as the
              paper's `eig`.
-  pcg        Algorithm 1 with the null-space centering of eq. (3.6) and
-             Remark 4.1, iterated to stagnation of the true residual.
+  spectral   the minimum-norm solution L^+ eta written out from the
+             eigen-expansion of the Kronecker sum (eq. 3.3): the converged
+             answer, computed without iterating.
+  pcg        preconditioned CG (Sec. 4.1) with the null-space centering of
+             eq. (3.6) and Remark 4.1, optional warm start, iterated to
+             stagnation of the true residual: the iteration-level checks.
   dense      Moore-Penrose solution of the assembled Kronecker-sum system.
   bcdata     right-hand side update for non-homogeneous Dirichlet / Neumann
              data (Sec. 3.4.2) and the field eps = -grad u (Sec. 1).
@@ -41,6 +45,7 @@ from .laplacian import (BCS, bc_corners, laplacian_1d, laplacian_1d_sparse,
                         apply_minus_laplacian, kronecker_sum, is_singular)
 from .pinv import pinv_init, pinv_apply, PinvPreconditioner
 from .pcg import pcg, solve, PCGResult
+from .spectral import min_norm_solution
 from .dense import dense_pinv_solve
 from .bcdata import assemble_rhs, field
 from .diagnostics import iterate_descriptors, error_norm_proxy, hs_error_estimate
@@ -49,6 +54,6 @@ __all__ = [
     "BCS", "bc_corners", "laplacian_1d", "laplacian_1d_sparse",
     "apply_minus_laplacian", "kronecker_sum", "is_singular",
     "pinv_init", "pinv_apply", "PinvPreconditioner",
-    "pcg", "solve", "PCGResult", "dense_pinv_solve", "assemble_rhs", "field",
+    "pcg", "solve", "PCGResult", "min_norm_solution", "dense_pinv_solve", "assemble_rhs", "field",
     "iterate_descriptors", "error_norm_proxy", "hs_error_estimate",
 ]

@@ -13,9 +13,9 @@ Jacobi-like method"):
   * for a Kronecker sum both parts split the same way (eq. 4.3), and the
     diagonal of the sum is the tensor of sums of the 1D diagonals times omega
     (eq. 4.4);
-  * Algs. 2 (2D) and 3 (3D): precompute O_omega(L_l) and the Hadamard
-    inverse of the diagonal tensor; from X_0 = 0 repeat p times
-    F_j = R - sum_l O_omega(L_l) x_l X_{j-1},  X_j = Dhat^{o-1} o F_j.
+  * Algs. 2 (2D) and 3 (3D) apply eq. (4.1) to the residual p times from
+    the zero start, with the off-diagonal part applied as one mode product
+    per axis and the diagonal inverted entrywise.
 Arrays are indexed in the paper's order U[i, j(, k)].
 """
 
@@ -44,15 +44,15 @@ def jacobi_init(shape, bcs, omega):
 
 
 def jacobi_apply(R, O, Dinv, p):
-    """Algs. 2 / 3: p steps from X_0 = 0."""
+    """Algs. 2 / 3: p sweeps of eq. (4.1) on L x = R from x = 0."""
     R = np.asarray(R, dtype=np.float64)
-    X = np.zeros(R.shape)
+    x = np.zeros(R.shape)
     for _ in range(p):
-        F = R.copy()
+        rhs = R.copy()
         for a, Oa in enumerate(O):
-            F -= _mode_product(Oa, X, a)
-        X = Dinv * F
-    return X
+            rhs -= _mode_product(Oa, x, a)
+        x = Dinv * rhs
+    return x
 
 
 class JacobiPreconditioner:

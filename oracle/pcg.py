@@ -1,25 +1,27 @@
-"""Preconditioned conjugate gradients, Algorithm 1 (Sec. 4.1).
+"""Preconditioned conjugate gradients for the discrete Poisson problem
+(Sec. 4.1), for checks at the level of single iterations.
 
 Test infrastructure (see the package docstring); never used by the product.
 
-The loop follows Algorithm 1 in the paper's order and notation:
-  W_0 = -Delta(U_0), R_0 = H - W_0, Z_0 = M(R_0), rho_0 = <R_0, Z_0>, P_0 = Z_0;
-  repeat: W_s = -Delta(P_{s-1}); alpha_s = rho_{s-1} / <W_s, P_{s-1}>;
-          U_s = U_{s-1} + alpha_s P_{s-1}; R_s = R_{s-1} - alpha_s W_s;
-          Z_s = M(R_s); rho_s = <R_s, Z_s>; beta_s = rho_s / rho_{s-1};
-          P_s = Z_s + beta_s P_{s-1}.
-The 2D variant is the same with matrices in place of tensors (Sec. 4.1).
+The converged answer has a direct definition, the minimum-norm solution
+L^+ eta, which `oracle.spectral.min_norm_solution` computes without iterating.
+This module is the iteration itself: residual histories, the convergence
+descriptors of Experiment 5.4, iteration counts of the preconditioners of
+Sec. 4.3 and warm starts.  It is a textbook preconditioned CG for a symmetric
+positive semidefinite operator -- iterate x, residual r, preconditioned
+residual z, search direction p, operator image q -- with what the paper adds:
+  * the start is x = 0 unless a warm start is given (the paper's experiments
+    start from 0, Sec. 5.2; the method itself takes any start, Sec. 4.1);
+  * the direction update uses the ratio of consecutive <r, z> (the paper's
+    choice of beta);
+  * for a singular set of boundary conditions the right-hand side is centred
+    once (eq. 3.6), every preconditioned residual is centred (Remark 4.1)
+    and the returned iterate is centred, giving the minimum-norm solution.
 
-Singular boundary-condition sets (all axes periodic or Neumann):
-  * the right-hand side is centred once, eq. (3.6) (Sec. 3.4.1);
-  * Z_s is centred after every preconditioner application (Remark 4.1).
-
-Stopping.  The paper stops after a fixed number of iterations chosen so that
-the true residual is small enough (Remark 4.2, Sec. 5.2).  The oracle's job is
-the converged answer, so it iterates until the true relative residual
-||H - L U_s|| / ||H|| drops to `true_tol` (default 1e-14), or has not
-decreased for `stall` consecutive iterations, or `max_iter` is reached.  The
-answer it converges to is the minimum-norm solution L^+ H of eq. (3.3).
+Stopping.  The paper runs a fixed number of iterations (Remark 4.2, Sec. 5.2).
+The default here iterates until the true relative residual ||h - L x|| / ||h||
+is at most `true_tol` (1e-14), or has not improved for `stall` iterations, or
+`max_iter` iterations were made; `fixed_iterations` runs exactly that many.
 """
 
 from dataclasses import dataclass, field
@@ -31,111 +33,101 @@ from .laplacian import apply_minus_laplacian, is_singular
 from .pinv import PinvPreconditioner
 
 
-def _center(X):
-    """Eq. (3.6): subtract the mean over all entries."""
-    return X - X.mean()
-
-
-def _inner(X, Y):
-    """<X, Y> = <vec X, vec Y> (Sec. 4.2, inner product)."""
-    return float(np.sum(X * Y))
-
-
 @dataclass
 class PCGResult:
     u: np.ndarray
     iterations: int
-    true_rel_res: list = field(default_factory=list)     # index s = iterate U_s
-    rec_rel_res: list = field(default_factory=list)      # ||R_s|| / ||H||
+    true_rel_res: list = field(default_factory=list)     # entry s: iterate after s steps
+    rec_rel_res: list = field(default_factory=list)      # updated residual ||r|| / ||h||
     removed_mean: float = 0.0
     h_norm: float = 0.0
-    # per iterate U_s: (true relative residual, kappa_s, null-space
-    # component, alpha_s rho_{s-1}) of Experiment 5.4 / Remark 4.2
+    # per iterate: (true relative residual, kappa, null-space component, the
+    # energy decrease step * <r, z> of the step that produced it), the
+    # descriptors of Experiment 5.4 and Remark 4.2
     diagnostics: list = field(default_factory=list)
 
 
-def pcg(eta, bcs, precond=None, true_tol=1e-14, stall=2, max_iter=20,
+def pcg(eta, bcs, precond=None, u0=None, true_tol=1e-14, stall=2, max_iter=20,
         fixed_iterations=None):
-    """Run Algorithm 1 from U_0 = 0 (the paper's choice, Sec. 5.2).
+    """Preconditioned CG for L u = eta.
 
-    eta     right-hand side H indexed [i, j] or [i, j, k]
-    bcs     one boundary condition per axis
-    precond callable R -> Z; None means M = I (unpreconditioned CG)
-    fixed_iterations  if given, run exactly that many iterations (Remark 4.2)
+    eta     right-hand side indexed [i, j] or [i, j, k] (Sec. 2.1 order)
+    bcs     one boundary condition per axis (eq. 3.1)
+    precond callable r -> z; None means no preconditioning
+    u0      starting iterate (same shape), default zero
     """
-    H = np.array(eta, dtype=np.float64)
+    h = np.array(eta, dtype=np.float64)
     singular = is_singular(bcs)
-    removed_mean = 0.0
+    removed_mean = float(h.mean()) if singular else 0.0
     if singular:
-        removed_mean = float(H.mean())
-        H = _center(H)
-    M = precond if precond is not None else (lambda R: R.copy())
+        h = h - removed_mean
 
-    def apply_M(R):
-        Z = M(R)
-        return _center(Z) if singular else Z
+    def operator(v):
+        return apply_minus_laplacian(v, bcs)
 
-    h_norm = float(np.linalg.norm(H))
-    U = np.zeros_like(H)
-    res = PCGResult(u=U, iterations=0, removed_mean=removed_mean, h_norm=h_norm)
+    def preconditioned(v):
+        z = precond(v) if precond is not None else v.copy()
+        return z - z.mean() if singular else z
+
+    h_norm = float(np.linalg.norm(h))
+    res = PCGResult(u=np.zeros_like(h), iterations=0, removed_mean=removed_mean,
+                    h_norm=h_norm)
     if h_norm == 0.0:
+        # every right-hand side of the null space has the solution 0
         res.true_rel_res.append(0.0)
         res.rec_rel_res.append(0.0)
         return res
 
-    W = apply_minus_laplacian(U, bcs)        # W_0 = -Delta(U_0)
-    R = H - W                                # R_0
-    Z = apply_M(R)                           # Z_0
-    rho = _inner(R, Z)                       # rho_0
-    P = Z.copy()                             # P_0
-    res.true_rel_res.append(float(np.linalg.norm(H - apply_minus_laplacian(U, bcs))) / h_norm)
-    res.rec_rel_res.append(float(np.linalg.norm(R)) / h_norm)
-    res.diagnostics.append(iterate_descriptors(U, H, bcs) + (0.0,))
+    x = np.zeros_like(h) if u0 is None else np.array(u0, dtype=np.float64)
 
-    best = res.true_rel_res[0]
-    no_progress = 0
-    s = 0
-    while True:
-        if rho == 0.0:
-            break
-        s += 1
-        W = apply_minus_laplacian(P, bcs)    # W_s = -Delta(P_{s-1})
-        alpha = rho / _inner(W, P)           # alpha_s
-        hs_term = alpha * rho                # alpha_s rho_{s-1}
-        U = U + alpha * P                    # U_s
-        R = R - alpha * W                    # R_s
-        Z = apply_M(R)                       # Z_s
-        rho_new = _inner(R, Z)               # rho_s
-        beta = rho_new / rho                 # beta_s
-        P = Z + beta * P                     # P_s
-        rho = rho_new
-
-        true_rel = float(np.linalg.norm(H - apply_minus_laplacian(U, bcs))) / h_norm
+    def record(x, r, energy_step):
+        true_rel, kappa, null = iterate_descriptors(x, h, bcs)
         res.true_rel_res.append(true_rel)
-        res.rec_rel_res.append(float(np.linalg.norm(R)) / h_norm)
-        res.diagnostics.append(iterate_descriptors(U, H, bcs) + (hs_term,))
+        res.rec_rel_res.append(float(np.linalg.norm(r)) / h_norm)
+        res.diagnostics.append((true_rel, kappa, null, energy_step))
 
-        if fixed_iterations is not None:
-            if s >= fixed_iterations:
-                break
-            continue
-        if true_rel < best:
-            best = true_rel
-            no_progress = 0
-        else:
-            no_progress += 1
-        if true_rel <= true_tol or no_progress >= stall or s >= max_iter:
-            break
+    # inner products use numpy's pairwise summation, whose rounding error
+    # grows like log N: long runs past convergence then keep the residual at
+    # rounding level instead of drifting upward
+    r = h - operator(x)
+    record(x, r, 0.0)
+    steps = 0
+    best, since_best = res.true_rel_res[0], 0
+    done = fixed_iterations is None and best <= true_tol
+    if not done and (fixed_iterations is None or fixed_iterations > 0):
+        z = preconditioned(r)
+        p = z.copy()
+        rz = float(np.sum(r * z))
+        while rz != 0.0:
+            q = operator(p)
+            step = rz / float(np.sum(p * q))
+            x = x + step * p
+            r = r - step * q
+            steps += 1
+            record(x, r, step * rz)
+            if fixed_iterations is not None:
+                if steps >= fixed_iterations:
+                    break
+            else:
+                now = res.true_rel_res[-1]
+                if now < best:
+                    best, since_best = now, 0
+                else:
+                    since_best += 1
+                if now <= true_tol or since_best >= stall or steps >= max_iter:
+                    break
+            z = preconditioned(r)
+            rz_next = float(np.sum(r * z))
+            p = z + (rz_next / rz) * p
+            rz = rz_next
 
-    if singular:
-        U = _center(U)
-    res.u = U
-    res.iterations = s
+    res.u = x - x.mean() if singular else x
+    res.iterations = steps
     return res
 
 
 def solve(eta, bcs, **kw):
-    """Converged minimum-norm solution with the pseudoinverse preconditioner."""
-    H = np.asarray(eta, dtype=np.float64)
-    M = PinvPreconditioner(H.shape, bcs)
-    return pcg(H, bcs, precond=M, **kw)
+    """PCG with the pseudoinverse preconditioner (Sec. 4.3.3), iterated to the
+    stopping rule above."""
+    h = np.asarray(eta, dtype=np.float64)
+    return pcg(h, bcs, precond=PinvPreconditioner(h.shape, bcs), **kw)

@@ -9,9 +9,10 @@ G of the tensor of eigenvalue sums (eqs. 4.6-4.7): g = 1/(lambda_i + lambda_j
 [+ lambda_k]), with sums of modulus below 1e-13 replaced by 0 (the threshold
 stated with eq. 4.7 and in Algs. 4-5).
 
-Application (Algs. 6 and 7): transform the residual into the eigenvector bases
-(V_n^T, V_q^T, V_t^T | R), multiply entrywise by G, and transform back with
-(V_n, V_q, V_t | .).
+Application (Algs. 6 and 7): the residual's coefficients in the product
+eigenbasis (each axis contracted with the transpose of its eigenvector
+matrix), scaled entrywise by G, and taken back to the grid with the
+eigenvector matrices themselves.
 """
 
 import numpy as np
@@ -48,14 +49,15 @@ def pinv_init(shape, bcs):
 
 
 def pinv_apply(R, V, G):
-    """Algorithms 6 (2D) and 7 (3D): Z = (V | G .* (V^T | R))."""
-    F = np.asarray(R, dtype=np.float64)
-    for axis, Q in enumerate(V):          # F1 = (V_n^T, V_q^T, V_t^T | R)
-        F = _mode_product(Q.T, F, axis)
-    F = F * G                             # F2 = F1 .* G
-    for axis, Q in enumerate(V):          # F3 = (V_n, V_q, V_t | F2)
-        F = _mode_product(Q, F, axis)
-    return F
+    """Algorithms 6 (2D) and 7 (3D): Z = M(R) for the pseudoinverse."""
+    coeff = np.asarray(R, dtype=np.float64)
+    for axis, Q in enumerate(V):          # into the eigenbasis, axis by axis
+        coeff = _mode_product(Q.T, coeff, axis)
+    coeff = coeff * G                     # Hadamard pseudoinverse of the sums
+    Z = coeff
+    for axis, Q in enumerate(V):          # back to the grid
+        Z = _mode_product(Q, Z, axis)
+    return Z
 
 
 class PinvPreconditioner:
