@@ -226,7 +226,7 @@ def make_eta(wl):
     return np.stack([one(b) for b in range(wl["batch"])])
 
 
-def solve_work(name, grid, results, flex=False):
+def solve_work(name, grid, results, flex=False, spectral=True):
     """Algorithmic work of one kernel class over one whole (batched) solve,
     summed over the right-hand sides that are still active in each launch
     (a converged RHS skips its blocks).  Returns ('flop', F) for a mode
@@ -259,10 +259,11 @@ def solve_work(name, grid, results, flex=False):
         elif name == "update_p":         # P_0 = Z_0: 2 words; P = Z + beta P: 3 words
             # one P update per application, except after the last when the
             # solve stopped on the error estimate that followed it; P_0 = Z_0
-            # is a launch of its own only off the spectral path (the flexible
-            # beta): otherwise the first application writes P_0 itself
+            # is a launch of its own only off the spectral path (FP32 and BF16
+            # products, the flexible beta): otherwise the first application
+            # writes P_0 itself
             nu = p - (1 if p > s else 0)
-            if flex:
+            if not spectral:
                 tot += (2 + 3 * (nu - 1)) * 8.0 * N if nu >= 1 else 0.0
             else:
                 tot += 3 * (nu - 1) * 8.0 * N if nu >= 2 else 0.0
@@ -624,7 +625,8 @@ def main():
             if cnt == 0:
                 continue
             avg_us = 1000.0 * ms / cnt
-            kind, work = solve_work(name, wl["grid"], results, p == "bf16")
+            kind, work = solve_work(name, wl["grid"], results, p == "bf16",
+                                    p in ("f64", "i8x7"))
             units = work * nsolves / cnt            # algorithmic work per launch
             entry = {"avg_us": round(avg_us, 2), "launches": cnt, "total_ms": round(ms, 3)}
             if kind == "flop":
@@ -690,7 +692,7 @@ def main():
     dom, dom_ms, dom_reps = m["dom"]
     kind, units = launch_work(dom, wl["grid"], batch, prec == "bf16")
     if kind is None:            # one launch per solve: the solve's work
-        kind, units = solve_work(dom, wl["grid"], res, prec == "bf16")
+        kind, units = solve_work(dom, wl["grid"], res, prec == "bf16", prec in ("f64", "i8x7"))
     rate = units / (dom_ms * 1e-3)
     ident = launch_identity(dom, prec, wl["grid"], batch, m["tuning"])
     traffic = measured_traffic(args.workload, ident)

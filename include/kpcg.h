@@ -22,7 +22,8 @@
  *              owned by the caller (for example torch.empty(..., device='cuda')),
  *              16-byte aligned.  The library never frees caller memory.
  *   Streams.   Work is enqueued on the plan's HIP stream.  kp_solve blocks
- *              until the solve has finished; kp_apply_* only enqueue.
+ *              until the solve has finished (kp_solve_async returns at once
+ *              with a ticket); kp_apply_* only enqueue.
  *   Errors.    Every call returns a kp_status; negative values are errors and
  *              leave outputs undefined; no call throws across the ABI.
  *   Threads.   One plan must be used by one host thread at a time; distinct
@@ -73,7 +74,9 @@ enum kp_status {
   KP_ENOMEM = -2,         /* device allocation failed or workspace too small */
   KP_EHIP = -3,           /* a HIP runtime call failed */
   KP_ENONFINITE = -4,     /* eta or an iterate contains NaN/Inf */
-  KP_EBREAKDOWN = -5      /* <W,P> <= 0 or rho <= 0 before convergence */
+  KP_EBREAKDOWN = -5,     /* <W,P> <= 0 or rho <= 0 before convergence */
+  KP_EBUSY = -6           /* the plan has a solve in flight (kp_solve_async
+                             not yet waited for) */
 };
 
 /* Solve flags (bitwise or). */
@@ -87,11 +90,14 @@ enum kp_flags {
   KP_FLAG_DIAGNOSTICS = 16, /* record the convergence descriptors of every iterate
                                (kp_plan_diagnostics); costs one stencil pass over
                                U and eta per iteration, results are unchanged */
-  KP_FLAG_ANORM_STOP = 32   /* stop on an estimate of the L-norm error instead of
+  KP_FLAG_ANORM_STOP = 32,  /* stop on an estimate of the L-norm error instead of
                                the residual tests (see kp_solve) */
+  KP_FLAG_WARM_START = 64   /* Algorithm 1 from the U_0 held in u on entry
+                               instead of U_0 = 0 (see kp_solve) */
 };
 
 typedef struct kp_plan kp_plan;   /* opaque */
+typedef struct kp_ticket kp_ticket; /* opaque: a solve in flight (kp_solve_async) */
 
 /* Per right-hand-side outcome of kp_solve. */
 typedef struct {
@@ -103,8 +109,9 @@ typedef struct {
   double true_rel_res;    /* ||eta_c - L u|| / ||eta_c|| recomputed at exit */
   double err_est;         /* relative error estimate at exit: ||Z_s|| / ||U_s||
                              (Z_s approximates the error), or the bound
-                             ||R_s|| / (lambda_min ||U_s||) when that stopped
-                             the solve (see kp_solve) */
+                             ||R_s|| / (lambda_min ||U_s||) or the low-mode
+                             bound when that stopped the solve (see kp_solve;
+                             both are bounds for the recursive residual R_s) */
   double removed_mean;    /* mean of eta projected out (singular operators) */
 } kp_result;
 
@@ -164,10 +171,12 @@ int kp_apply_laplacian(kp_plan* plan, const double* P, double* W, int batch);
 int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
 
 /* Solves -Delta_FD(u) = eta for `batch` right-hand sides with Algorithm 1
- * from U_0 = 0 and the pseudoinverse preconditioner (or M = I with
- * KP_FLAG_NO_PRECOND).
+ * from U_0 = 0 (or from the U_0 in u with KP_FLAG_WARM_START) and the
+ * pseudoinverse preconditioner (or M = I with KP_FLAG_NO_PRECOND).
  *   eta       device, batch*N doubles, read only
- *   u         device, batch*N doubles, output; must not overlap eta
+ *   u         device, batch*N doubles, output; must not overlap eta; with
+ *             KP_FLAG_WARM_START it holds U_0 on entry (Algorithm 1's
+ *             input, Sec. 4.1)
  *   tol       > 0, relative tolerance
  *   max_iter  >= 1, largest iteration count s
  *   flags     kp_flags
@@ -177,9 +186,18 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * Singular operators (every axis P or N, Sec. 3.4.1): eta is centred
  * (eq. 3.6; the removed mean is reported), Z_s is centred every iteration
  * (Remark 4.1), and u is returned with zero mean: the minimum-norm solution.
+ * Warm start: R_0 = eta_c - L U_0 (one stencil pass); res_hist[0] is
+ * ||R_0||/||eta_c|| and the start itself may already stop the solve (s = 0)
+ * by the residual test with the lambda_min bound below (or the residual alone
+ * with KP_FLAG_RESIDUAL_ONLY); a singular set returns the minimum-norm
+ * (zero-mean) solution whatever the mean of U_0; a right-hand side with
+ * eta_c = 0 returns u = 0.  With KP_FLAG_ANORM_STOP the estimate below is
+ * then relative to the error of U_0 rather than to ||u||_L.  Not with the
+ * one-kernel 2D path (the general path runs instead); the serving layer does
+ * not take the flag.
  * Stopping: the paper fixes the iteration count (Remark 4.2); here iteration
  * s stops when ||R_s||/||eta_c|| <= tol and, unless KP_FLAG_RESIDUAL_ONLY is
- * set, also the relative error of U_s is certified <= tol, by the first of:
+ * set, also the relative error of U_s is bounded by tol, by the first of:
  *   - the bound ||U_s - u|| <= ||R_s|| / lambda_min (lambda_min the smallest
  *     nonzero eigenvalue of the Kronecker sum, from the closed-form spectra),
  *     which costs nothing;
@@ -215,6 +233,41 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * until the results are on the host. */
 int kp_solve(kp_plan* plan, const double* eta, double* u, int batch, double tol, int max_iter,
              int flags, kp_result* results, double* res_hist);
+
+/* R_s is Algorithm 1's recursive residual; U_s - u = -L^+ R_s holds for
+ * the true residual eta_c - L U_s, which equals R_s up to the rounding the
+ * recurrence accumulates (the exit step recomputes the true residual and
+ * reports it as true_rel_res, so a caller sees any gap).  The inner
+ * products <R, Z> and <W, P> of alpha and beta are FP64 in every precision:
+ * with the FP64 and int8 split products <R, Z> comes by Parseval from the
+ * FP64 eigenbasis coefficients the application produces anyway, with FP32
+ * and BF16 products from an FP64 pass over R and Z.
+ *
+ * Asynchronous solve.  kp_solve_async validates and enqueues the start of
+ * the same solve as kp_solve (same arguments and flags) and returns at once
+ * with a ticket; the results and res_hist arrays it was given are written
+ * when the solve finishes.  The solve runs on the plan's private stream
+ * after earlier work on the plan's stream.  Its first chunk of iterations
+ * and the exit step are enqueued at the start; a solve that needs more
+ * iterations than the previous solve on the plan is continued by kp_poll or
+ * kp_wait (one iteration per call to kp_poll that finds the device idle), so
+ * the host must poll or wait for it to progress.  Until kp_wait has returned,
+ * the plan belongs to the ticket: every other call on the plan returns
+ * KP_EBUSY (kp_plan_destroy finishes the solve first and releases the
+ * ticket, which must then not be used), and eta, u, results and res_hist
+ * must stay valid.  u is complete when kp_poll has returned 1.
+ *   ticket  receives the ticket (NULL on error)
+ * Returns KP_OK (enqueued), KP_EBUSY, or the errors kp_solve returns before
+ * any work. */
+int kp_solve_async(kp_plan* plan, const double* eta, double* u, int batch, double tol,
+                   int max_iter, int flags, kp_result* results, double* res_hist,
+                   kp_ticket** ticket);
+/* Non-blocking: 1 when the solve has finished (results written), 0 while it
+ * runs; KP_EINVAL for a NULL ticket. */
+int kp_poll(kp_ticket* ticket);
+/* Blocks until the solve has finished, releases the ticket (it must not be
+ * used again) and returns the solve's status, as kp_solve would have. */
+int kp_wait(kp_ticket* ticket);
 
 /* Preconditioner of kp_solve and kp_apply_preconditioner (Sec. 4.3).
  *   KP_PRECOND_PINV    the Moore-Penrose pseudoinverse (Sec. 4.3.3), default

@@ -54,6 +54,9 @@ struct RhsState {
   int pinv_count;     // preconditioner applications so far
   int diag_iter;      // last iterate whose descriptors were recorded (-1: none)
   int need_cert;      // residual small enough, error bound still to be certified
+  int warm;           // U_0 came from the caller (warm start): kept at exit
+  int pad_;
+  double u0mean;      // mean of U_0 (singular operators: the iterates keep it)
 };
 
 // Reduction slots written by the vector and mode-product kernels, one block

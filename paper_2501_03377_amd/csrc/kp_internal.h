@@ -125,6 +125,11 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
 // for a right-hand side that made no iteration).
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
+// Warm start: R_0 = eta_c - L U_0 with its sums and the stopping rule at
+// s = 0 (after launch_init without R, which gives ||eta_c||).
+void launch_warm(const Geom& g, const double* eta, const double* U, double* R, double* part,
+                 RhsState* st, double* hist, int hist_stride, int batch, double tol, int flags,
+                 hipStream_t s);
 // Gdot > 0: the preconditioner already left Gdot partial sums of <R, Z> etc.
 // p_written: P already holds the new P (P_0 = Z_0 written by the application).
 void launch_after_pinv(const Geom& g, const double* R, const double* Z, const double* W,

@@ -109,6 +109,8 @@ struct kp_plan {
   Tracer tracer;
   hipStream_t own = nullptr;    // private stream of kp_solve (graph capture needs one)
   hipEvent_t ev_in = nullptr;   // orders kp_solve after earlier work on `stream`
+  hipEvent_t ev_done = nullptr; // recorded after each enqueued chunk of a solve
+  kp_ticket* busy = nullptr;    // the solve in flight (kp_solve_async), if any
   // Captured chunks of iterations, keyed by everything their kernels capture.
   struct GraphKey {
     int whole;          // 1: start, iterations and exit step; 0: iterations only
@@ -268,12 +270,12 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Z = M(R).  In a solve (`part` given) the pseudoinverse also leaves the
-// partial sums of the CG step after it, <R, Z> and ||Z||^2 by Parseval in
-// the eigenbasis, and returns how many there are; 0 means the step computes
-// them itself (other preconditioners, and the flexible beta, which needs
-// <W, Z>).
-// Z = M(R).  Returns Gdot > 0 when the pseudoinverse left the partial sums
+// Z = M(R).  In a solve (`part` given) the FP64 and int8 split
+// pseudoinverse also leaves the partial sums of the CG step after it, <R, Z>
+// and ||Z||^2 by Parseval in the eigenbasis, and returns how many there are;
+// 0 means the step computes them itself in FP64 from R and Z (other
+// preconditioners, the FP32 and BF16 products, and the flexible beta, which
+// needs <W, Z>).  Returns Gdot > 0 when the pseudoinverse left the partial sums
 // of <R, Z> and ||Z||^2 (spectral, Gdot blocks) -- then Z has zero mean and,
 // if `z0` is given, the result goes to z0 instead of Z (the first
 // application writes P_0 = Z_0 directly).
@@ -294,7 +296,11 @@ int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int ba
   int Gdot = 0;
   if (p->pc_kind == KP_PRECOND_LOWRANK) {
     op.gtab = p->lr_dev;
-  } else if (part && st && !(flags & KP_FLAG_FLEX_BETA)) {
+  } else if (part && st && !(flags & KP_FLAG_FLEX_BETA) &&
+             (p->prec == PREC_F64 || p->prec == PREC_I8X7)) {
+    // <R, Z> by Parseval from the coefficients in the eigenbasis, which are
+    // FP64-accurate only for the FP64 and the int8 split products; the FP32
+    // and BF16 forms take the inner products in FP64 from R and Z in space
     const int b = pinv_ghat_blocks(op);
     if (b <= GMAX) {
       op.rpart = part;
@@ -337,6 +343,385 @@ void clear_graphs(kp_plan* p) {
   std::lock_guard<std::mutex> lk(api_mutex());
   for (auto& e : p->graphs) (void)hipGraphExecDestroy(e.exec);
   p->graphs.clear();
+}
+
+}  // namespace
+
+// A solve in flight: the host side of Algorithm 1's outer loop.  The first
+// chunk of iterations (and the exit step) is enqueued at the start; the
+// host then reads the per-RHS done flags once the chunk has finished and
+// enqueues one more iteration (and the exit step again) while some
+// right-hand side still runs.  kp_solve drives it to the end; kp_solve_async
+// returns after the start and kp_poll / kp_wait advance it.
+struct kp_ticket {
+  kp_plan* p = nullptr;
+  const double* eta = nullptr;
+  double* u = nullptr;
+  int batch = 0, max_iter = 0, flags = 0, hs = 0;
+  double tol = 0.0;
+  kp_result* results = nullptr;
+  double* res_hist = nullptr;
+  bool diag = false, cert = false, warm = false, small = false;
+  int done_iters = 0;
+  bool pending_tail = false;   // second part of a split iteration still owed
+  bool finished = false;
+  int status = KP_OK;
+};
+
+namespace {
+
+// Argument checks shared by kp_solve and kp_solve_async; returns the flags
+// the solve runs with (or a negative status).
+int solve_flags(kp_plan* p, const double* eta, double* u, int batch, double tol, int max_iter,
+                int flags) {
+  if (!p || !eta || !u || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 1000000) return KP_EINVAL;
+  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH |
+                KP_FLAG_DIAGNOSTICS | KP_FLAG_ANORM_STOP | KP_FLAG_WARM_START))
+    return KP_EINVAL;
+  if (!aligned16(eta) || !aligned16(u)) return KP_EINVAL;
+  const size_t vbytes = (size_t)p->g.N * batch * 8;
+  if (overlap(eta, u, vbytes)) return KP_EINVAL;
+  // With M = I the preconditioned residual is R itself, which is no error
+  // estimate: stop on the residual alone.
+  if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
+  // Jacobi(p, omega) approximates L^{-1} too loosely for M(R) to estimate
+  // the error either
+  if (p->pc_kind == KP_PRECOND_JACOBI || p->pc_kind == KP_PRECOND_LOWRANK)
+    flags |= KP_FLAG_RESIDUAL_ONLY;
+  // the low-mode certificate backs the residual test unless the error test
+  // is off
+  if (!(flags & (KP_FLAG_RESIDUAL_ONLY | KP_FLAG_ANORM_STOP))) flags |= F_CERT;
+  return flags;
+}
+
+// The launches of one solve on the plan's private stream.
+struct SolveRun {
+  kp_ticket* t;
+  kp_plan* p;
+  Layout L;
+  char* base;
+  double *R, *P, *W, *Z, *part;
+  RhsState* st;
+  int G;
+  hipStream_t s;
+  double* diag_dev;
+  const double* R0;
+
+  explicit SolveRun(kp_ticket* t_) : t(t_), p(t_->p) {
+    L = layout_for(p, t->batch);
+    base = (char*)p->ws;
+    R = (double*)(base + L.R);
+    P = (double*)(base + L.P);
+    W = (double*)(base + L.W);
+    Z = (double*)(base + L.Z);
+    part = (double*)(base + L.part);
+    st = (RhsState*)(base + L.st);
+    G = vec_blocks(p->g.N, t->batch);
+    s = p->own;
+    diag_dev = t->diag ? p->diag_dev : nullptr;
+    // Algorithm 1 from U_0 = 0 has R_0 = eta_c: a nonsingular set reads eta
+    // itself where R_0 is needed (the first application and the first U/R
+    // update, which stores R_1 in R); a warm start stores eta_c - L U_0
+    R0 = (p->g.singular || t->warm) ? R : t->eta;
+  }
+  // R_0, Z_0 = M(R_0), rho_0, P_0 = Z_0
+  void head() {
+    // U_0 = 0 is stored only for the descriptors of iterate 0; R_0 = eta_c
+    // only for a singular set started from zero
+    launch_init(p->g, t->eta, (p->g.singular && !t->warm) ? R : nullptr,
+                (t->diag && !t->warm) ? t->u : nullptr, part, st, p->hist_dev, t->hs, t->batch,
+                G, s);
+    if (t->warm)
+      launch_warm(p->g, t->eta, t->u, R, part, st, p->hist_dev, t->hs, t->batch, t->tol,
+                  t->flags, s);
+    if (t->diag) launch_diag(p->g, t->eta, t->u, part, st, diag_dev, t->hs, t->batch, s);
+    // spectral sums: Z_0 has zero mean, so P_0 = Z_0 is written by the
+    // application itself and the P update is skipped
+    const int Gdot = precondition(p, L, R0, Z, t->batch, t->flags, st, s, part, P);
+    launch_after_pinv(p->g, R0, Z, W, P, part, st, t->batch, G, 1, t->tol, t->flags, s, Gdot,
+                      Gdot > 0);
+  }
+  // An iteration in two parts: up to the residual test and certificate,
+  // then preconditioning and the updates that depend on it.  with_cert: the
+  // low-mode certificate runs after this iteration's residual test (only
+  // the last iteration of a chunk, where the solve is expected to stop;
+  // earlier ones fall back to the error estimate after the next
+  // application, and their launches are saved)
+  void iteration_head(bool first_iter, bool with_cert) {
+    const bool u0 = first_iter && !t->warm;
+    launch_iter_head(p->g, P, W, R, t->u, part, st, p->hist_dev, t->hs, t->batch, G, t->tol,
+                     t->flags, s, u0, (u0 && !p->g.singular) ? t->eta : nullptr);
+    if (t->diag) launch_diag(p->g, t->eta, t->u, part, st, diag_dev, t->hs, t->batch, s);
+    if (t->cert && with_cert)
+      launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
+                  (double*)(base + L.C3), st, t->batch, t->tol, s);
+  }
+  void iteration_tail() {
+    const int Gdot = precondition(p, L, R, Z, t->batch, t->flags, st, s, part);
+    launch_after_pinv(p->g, R, Z, W, P, part, st, t->batch, G, 0, t->tol, t->flags, s, Gdot);
+  }
+  // n iterations; with `split` the last one stops after its residual test
+  // (its second part runs later, only if some right-hand side continues);
+  // `from_start`: the first of them is the solve's first iteration
+  void iterations(int n, bool split, bool from_start) {
+    for (int q = 0; q < n; ++q) {
+      iteration_head(from_start && q == 0, q == n - 1);
+      if (!(split && q == n - 1)) iteration_tail();
+    }
+  }
+  // exit step: true residual, centering of U, state to the mapped host mirror
+  void tail() {
+    launch_finish(p->g, t->eta, t->u, part, st, p->st_dev, t->batch, G, s);
+  }
+  // Finds or captures the graph of `key`; returns its index or -1.
+  template <class F>
+  int graph_for(const kp_plan::GraphKey& key, F&& body) {
+    for (size_t e = 0; e < p->graphs.size(); ++e)
+      if (p->graphs[e].key == key) {
+        std::rotate(p->graphs.begin() + e, p->graphs.begin() + e + 1, p->graphs.end());
+        return (int)p->graphs.size() - 1;
+      }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::lock_guard<std::mutex> lk(api_mutex());
+    bool okc = ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    if (okc) {
+      body();
+      okc = ok(hipStreamEndCapture(s, &graph)) && graph != nullptr;
+    }
+    if (okc) okc = ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!okc) {
+      p->graphs_ok = false;   // capture unavailable: launch directly from now on
+      return -1;
+    }
+    if (p->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(p->graphs.front().exec);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, exec, {}});
+    return (int)p->graphs.size() - 1;
+  }
+};
+
+// Validates, prepares and enqueues the start of a solve: the first chunk of
+// iterations (what the previous solve on this plan needed, or a guess per
+// precision) and the exit step, as one captured HIP graph where possible
+// (cached per plan; when the caller repeats the previous solve's buffers the
+// whole solve -- start, chunk and exit step -- is one graph).  Small 2D
+// problems with the FP64 pseudoinverse run the whole solve as one kernel.
+int solve_start(kp_ticket* t, kp_plan* p, const double* eta, double* u, int batch, double tol,
+                int max_iter, int flags, kp_result* results, double* res_hist) {
+  flags = solve_flags(p, eta, u, batch, tol, max_iter, flags);
+  if (flags < 0) return flags;
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  const int hs = max_iter + 1;
+  rc = ensure_hist(p, (size_t)batch * hs);
+  if (rc != KP_OK) return rc;
+  const bool diag = (flags & KP_FLAG_DIAGNOSTICS) != 0;
+  p->diag_batch = 0;
+  if (diag) {
+    rc = ensure_mapped(&p->diag, &p->diag_dev, &p->diag_cap, (size_t)batch * hs * DIAG_RAW);
+    if (rc != KP_OK) return rc;
+  }
+  (void)hipGetLastError();
+  t->p = p;
+  t->eta = eta;
+  t->u = u;
+  t->batch = batch;
+  t->tol = tol;
+  t->max_iter = max_iter;
+  t->flags = flags;
+  t->hs = hs;
+  t->results = results;
+  t->res_hist = res_hist;
+  t->diag = diag;
+  t->cert = (flags & F_CERT) != 0;
+  t->warm = (flags & KP_FLAG_WARM_START) != 0;
+  // Work runs on the plan's private stream, ordered after earlier work on the
+  // caller's stream.
+  hipStream_t s = p->own;
+  if (!ok(hipEventRecord(p->ev_in, p->stream)) || !ok(hipStreamWaitEvent(s, p->ev_in, 0)))
+    return KP_EHIP;
+
+  TraceScope scope(p);
+  std::memset(p->hist, 0, (size_t)batch * hs * sizeof(double));   // no kernel writes it now
+  if (diag) {
+    std::fill(p->diag, p->diag + (size_t)batch * hs * DIAG_RAW,
+              std::numeric_limits<double>::quiet_NaN());
+    p->diag_batch = batch;
+    p->diag_hs = hs;
+  }
+  SolveRun run(t);
+  // Small 2D problems with the FP64 pseudoinverse: the whole solve is one
+  // kernel (the same stopping rules, without the low-mode certificate).
+  t->small = p->small_ok && p->pc_kind == KP_PRECOND_PINV && !diag &&
+             !(flags & (KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_ANORM_STOP |
+                        KP_FLAG_WARM_START));
+  if (t->small) {
+    p->small_last.eta = eta;
+    p->small_last.u = u;
+    p->small_last.batch = batch;
+    p->small_last.max_iter = max_iter;
+    p->small_last.flags = flags;
+    p->small_last.tol = tol;
+    launch_small_solve(p->g, p->small, eta, u, run.st, p->st_dev, p->hist_dev, hs, batch, tol,
+                       max_iter, flags, s);
+    t->done_iters = max_iter;
+  } else {
+    const bool use_graphs = p->graphs_ok && !p->profiling && !(flags & KP_FLAG_NO_GRAPH);
+    const bool repeat = eta == p->last_eta && u == p->last_u;
+    p->last_eta = eta;
+    p->last_u = u;
+    const int chunk = p->expect_iters > 0
+                          ? p->expect_iters
+                          : ((flags & KP_FLAG_NO_PRECOND)
+                                 ? 8
+                                 : ((p->prec == PREC_F64 || p->prec == PREC_I8X7)
+                                        ? 1
+                                        : (p->prec == PREC_BF16 ? 8 : 2)));
+    // a first chunk that ends where the previous solve stopped, before the
+    // last preconditioning, launches no kernels for finished right-hand sides
+    const int n = std::min(chunk, max_iter);
+    const bool split = p->expect_iters > 0 && p->expect_split && n == chunk;
+    const int nkey = 2 * n + (split ? 1 : 0);
+    bool launched = false;
+    if (use_graphs) {
+      if (repeat) {
+        const kp_plan::GraphKey key{1, batch, nkey, flags, hs, tol, u, p->hist_dev, run.diag_dev,
+                                    eta};
+        const int gi = run.graph_for(key, [&]() {
+          run.head();
+          run.iterations(n, split, true);
+          run.tail();
+        });
+        if (gi >= 0) {
+          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
+          launched = true;
+        }
+      } else {
+        run.head();
+        // (the iterations read eta for the descriptors, and as R_0 of a
+        // nonsingular set in the first U/R update)
+        const bool reads_eta = diag || (!p->g.singular && !t->warm);
+        const kp_plan::GraphKey key{0,   batch, nkey,         flags,
+                                    hs,  tol,   u,            p->hist_dev,
+                                    run.diag_dev, reads_eta ? eta : nullptr};
+        const int gi = run.graph_for(key, [&]() { run.iterations(n, split, true); });
+        if (gi >= 0) {
+          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
+        } else {
+          run.iterations(n, split, true);
+        }
+        run.tail();
+        launched = true;
+      }
+    }
+    if (!launched) {
+      run.head();
+      run.iterations(n, split, true);
+      run.tail();
+    }
+    t->pending_tail = split;
+    t->done_iters = n;
+  }
+  if (!ok(hipGetLastError()) || !ok(hipEventRecord(p->ev_done, s))) return KP_EHIP;
+  return KP_OK;
+}
+
+// Per-RHS statuses and results of a finished solve; the first chunk of the
+// next solve on this plan is sized by this one.
+void solve_finish(kp_ticket* t) {
+  kp_plan* p = t->p;
+  const int batch = t->batch;
+  if (t->res_hist) std::memcpy(t->res_hist, p->hist, (size_t)batch * t->hs * sizeof(double));
+  int worst = KP_OK;
+  int max_it = 0;
+  for (int b = 0; b < batch; ++b) {
+    const RhsState& x = p->st_host[b];
+    int stt;
+    switch (x.done) {
+      case CONVERGED: case ZERO_RHS: stt = KP_OK; break;
+      case BREAKDOWN: stt = KP_EBREAKDOWN; break;
+      case NONFINITE: stt = KP_ENONFINITE; break;
+      default: stt = KP_NOT_CONVERGED; break;
+    }
+    if (t->results) {
+      kp_result& r = t->results[b];
+      r.status = stt;
+      r.iterations = x.iter;
+      r.pinv_applications = x.pinv_count;
+      r.reserved = 0;
+      r.rel_res = x.rel_res;
+      r.true_rel_res = x.true_rel_res;
+      r.err_est = x.err_est;
+      r.removed_mean = x.mean;
+    }
+    if (stt < 0 && (worst >= 0 || stt < worst)) worst = stt;
+    else if (stt == KP_NOT_CONVERGED && worst == KP_OK) worst = stt;
+    if (stt == KP_OK) max_it = std::max(max_it, x.iter);
+  }
+  if (max_it > 0) {
+    p->expect_iters = max_it;
+    // split next time if every right-hand side that took max_it iterations
+    // stopped before preconditioning in its last one
+    bool split = true;
+    for (int b = 0; b < batch; ++b) {
+      const RhsState& x = p->st_host[b];
+      if (x.done == CONVERGED && x.iter == max_it && x.pinv_count > x.iter) split = false;
+    }
+    p->expect_split = split;
+  }
+  t->status = worst;
+  t->finished = true;
+}
+
+// Advances a solve: once its last enqueued chunk has finished (waiting for
+// it with `block`, else returning 0 while it runs), either finishes it or
+// enqueues one more iteration and the exit step.  Returns 1 when finished.
+int solve_advance(kp_ticket* t, bool block) {
+  if (t->finished) return 1;
+  kp_plan* p = t->p;
+  for (;;) {
+    if (block) {
+      if (!ok(hipEventSynchronize(p->ev_done))) {
+        t->status = KP_EHIP;
+        t->finished = true;
+        return 1;
+      }
+    } else {
+      const hipError_t q = hipEventQuery(p->ev_done);
+      if (q == hipErrorNotReady) return 0;
+      if (!ok_at(q, "hipEventQuery")) {
+        t->status = KP_EHIP;
+        t->finished = true;
+        return 1;
+      }
+    }
+    if (p->profiling) p->tracer.collect();
+    bool all_done = true;
+    for (int b = 0; b < t->batch; ++b) all_done = all_done && p->st_host[b].done != RUNNING;
+    if (all_done || t->done_iters >= t->max_iter) {
+      solve_finish(t);
+      return 1;
+    }
+    TraceScope scope(p);
+    SolveRun run(t);
+    if (t->pending_tail) run.iteration_tail();
+    run.iterations(1, false, false);
+    run.tail();
+    t->pending_tail = false;
+    t->done_iters += 1;
+    if (!ok(hipGetLastError()) || !ok(hipEventRecord(p->ev_done, p->own))) {
+      t->status = KP_EHIP;
+      t->finished = true;
+      return 1;
+    }
+    if (!block) return 0;
+  }
 }
 
 }  // namespace
@@ -511,7 +896,8 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
     p->small.ly = p->op.lam[1];
   }
   if (!ok(hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking)) ||
-      !ok(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming))) {
+      !ok(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming)) ||
+      !ok(hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming))) {
     if (p->own) (void)hipStreamDestroy(p->own);
     (void)hipFree(p->resident);
     delete p;
@@ -531,6 +917,11 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
 
 void kp_plan_destroy(kp_plan* p) {
   if (!p) return;
+  if (p->busy) {   // a solve still in flight: finished and released here
+    solve_advance(p->busy, true);
+    delete p->busy;
+    p->busy = nullptr;
+  }
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   if (p->own) (void)hipStreamSynchronize(p->own);
@@ -538,6 +929,7 @@ void kp_plan_destroy(kp_plan* p) {
   std::lock_guard<std::mutex> lk(api_mutex());
   if (p->own) (void)hipStreamDestroy(p->own);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->ev_done) (void)hipEventDestroy(p->ev_done);
   if (p->ws_owned && p->ws) (void)hipFree(p->ws);
   if (p->hist) (void)hipHostFree(p->hist);
   if (p->diag) (void)hipHostFree(p->diag);
@@ -557,6 +949,7 @@ size_t kp_plan_resident_bytes(const kp_plan* p) { return p ? p->resident_bytes :
 
 int kp_plan_set_workspace(kp_plan* p, void* dev, size_t bytes) {
   if (!p || !dev || ((uintptr_t)dev & (ALIGN - 1))) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (bytes < layout_for(p, p->max_batch).total) return KP_ENOMEM;
   if (p->ws_owned && p->ws) {
     (void)hipStreamSynchronize(p->stream);
@@ -572,12 +965,14 @@ int kp_plan_set_workspace(kp_plan* p, void* dev, size_t bytes) {
 
 int kp_plan_set_stream(kp_plan* p, void* s) {
   if (!p) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   p->stream = (hipStream_t)s;
   return KP_OK;
 }
 
 int kp_apply_laplacian(kp_plan* p, const double* P, double* W, int batch) {
   if (!p || !P || !W || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (!aligned16(P) || !aligned16(W)) return KP_EINVAL;
   if (overlap(P, W, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
   TraceScope scope(p);
@@ -587,6 +982,7 @@ int kp_apply_laplacian(kp_plan* p, const double* P, double* W, int batch) {
 
 int kp_apply_pinv(kp_plan* p, const double* R, double* Z, int batch) {
   if (!p || !R || !Z || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (!aligned16(R) || !aligned16(Z)) return KP_EINVAL;
   if (overlap(R, Z, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
   int rc = ensure_workspace(p);
@@ -600,269 +996,51 @@ int kp_apply_pinv(kp_plan* p, const double* R, double* Z, int batch) {
 
 int kp_solve(kp_plan* p, const double* eta, double* u, int batch, double tol, int max_iter,
              int flags, kp_result* results, double* res_hist) {
-  if (!p || !eta || !u || batch < 1 || batch > p->max_batch) return KP_EINVAL;
-  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 1000000) return KP_EINVAL;
-  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY | KP_FLAG_NO_GRAPH |
-                KP_FLAG_DIAGNOSTICS | KP_FLAG_ANORM_STOP))
-    return KP_EINVAL;
-  if (!aligned16(eta) || !aligned16(u)) return KP_EINVAL;
-  const size_t vbytes = (size_t)p->g.N * batch * 8;
-  if (overlap(eta, u, vbytes)) return KP_EINVAL;
-  // With M = I the preconditioned residual is R itself, which is no error
-  // estimate: stop on the residual alone.
-  if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
-  // Jacobi(p, omega) approximates L^{-1} too loosely for M(R) to estimate
-  // the error either
-  if (p->pc_kind == KP_PRECOND_JACOBI || p->pc_kind == KP_PRECOND_LOWRANK)
-    flags |= KP_FLAG_RESIDUAL_ONLY;
-  // the low-mode certificate backs the residual test unless the error test
-  // is off
-  const bool cert = !(flags & (KP_FLAG_RESIDUAL_ONLY | KP_FLAG_ANORM_STOP));
-  if (cert) flags |= F_CERT;
-  int rc = ensure_workspace(p);
+  if (!p) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
+  kp_ticket t;
+  int rc = solve_start(&t, p, eta, u, batch, tol, max_iter, flags, results, res_hist);
   if (rc != KP_OK) return rc;
-  const int hs = max_iter + 1;
-  rc = ensure_hist(p, (size_t)batch * hs);
-  if (rc != KP_OK) return rc;
-  const bool diag = (flags & KP_FLAG_DIAGNOSTICS) != 0;
-  p->diag_batch = 0;
-  if (diag) {
-    rc = ensure_mapped(&p->diag, &p->diag_dev, &p->diag_cap, (size_t)batch * hs * DIAG_RAW);
-    if (rc != KP_OK) return rc;
+  solve_advance(&t, true);
+  return t.status;
+}
+
+int kp_solve_async(kp_plan* p, const double* eta, double* u, int batch, double tol, int max_iter,
+                   int flags, kp_result* results, double* res_hist, kp_ticket** ticket) {
+  if (ticket) *ticket = nullptr;
+  if (!p || !ticket) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
+  kp_ticket* t = new (std::nothrow) kp_ticket();
+  if (!t) return KP_ENOMEM;
+  const int rc = solve_start(t, p, eta, u, batch, tol, max_iter, flags, results, res_hist);
+  if (rc != KP_OK) {
+    delete t;
+    return rc;
   }
-  (void)hipGetLastError();
+  p->busy = t;
+  *ticket = t;
+  return KP_OK;
+}
 
-  const Layout L = layout_for(p, batch);
-  char* base = (char*)p->ws;
-  double* R = (double*)(base + L.R);
-  double* P = (double*)(base + L.P);
-  double* W = (double*)(base + L.W);
-  double* Z = (double*)(base + L.Z);
-  double* part = (double*)(base + L.part);
-  RhsState* st = (RhsState*)(base + L.st);
-  const int G = vec_blocks(p->g.N, batch);
-  // Work runs on the plan's private stream, ordered after earlier work on the
-  // caller's stream.
-  hipStream_t s = p->own;
-  if (!ok(hipEventRecord(p->ev_in, p->stream)) || !ok(hipStreamWaitEvent(s, p->ev_in, 0)))
-    return KP_EHIP;
+int kp_poll(kp_ticket* t) {
+  if (!t) return KP_EINVAL;
+  return solve_advance(t, false);
+}
 
-  TraceScope scope(p);
-  std::memset(p->hist, 0, (size_t)batch * hs * sizeof(double));   // no kernel writes it now
-  if (diag) {
-    std::fill(p->diag, p->diag + (size_t)batch * hs * DIAG_RAW,
-              std::numeric_limits<double>::quiet_NaN());
-    p->diag_batch = batch;
-    p->diag_hs = hs;
-  }
-  double* diag_dev = diag ? p->diag_dev : nullptr;
-
-  // Algorithm 1: R_0 = H - (-Delta)(0) = eta_c, Z_0 = M(R_0), rho_0, P_0 = Z_0.
-  // R_0 is eta itself for a nonsingular set, read where R_0 is needed (the
-  // first application and the first U/R update, which stores R_1 in R).
-  const double* R0 = p->g.singular ? R : eta;
-  auto head = [&]() {
-    // U_0 = 0 is stored only for the descriptors of iterate 0; R_0 = eta_c
-    // only for a singular set (a nonsingular one reads eta itself)
-    launch_init(p->g, eta, p->g.singular ? R : nullptr, diag ? u : nullptr, part, st,
-                p->hist_dev, hs, batch, G, s);
-    if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-    // spectral sums: Z_0 has zero mean, so P_0 = Z_0 is written by the
-    // application itself and the P update is skipped
-    const int Gdot = precondition(p, L, R0, Z, batch, flags, st, s, part, P);
-    launch_after_pinv(p->g, R0, Z, W, P, part, st, batch, G, 1, tol, flags, s, Gdot, Gdot > 0);
-  };
-  // An iteration in two parts: up to the residual test and certificate,
-  // then preconditioning and the updates that depend on it.
-  // with_cert: the low-mode certificate runs after this iteration's residual
-  // test (only the last iteration of a chunk, where the solve is expected to
-  // stop; earlier ones fall back to the error estimate after the next
-  // application, and their launches are saved)
-  auto iteration_head = [&](bool u0, bool with_cert) {
-    launch_iter_head(p->g, P, W, R, u, part, st, p->hist_dev, hs, batch, G, tol, flags, s, u0,
-                     (u0 && !p->g.singular) ? eta : nullptr);
-    if (diag) launch_diag(p->g, eta, u, part, st, diag_dev, hs, batch, s);
-    if (cert && with_cert)
-      launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
-                  (double*)(base + L.C3), st, batch, tol, s);
-  };
-  auto iteration_tail = [&]() {
-    const int Gdot = precondition(p, L, R, Z, batch, flags, st, s, part);
-    launch_after_pinv(p->g, R, Z, W, P, part, st, batch, G, 0, tol, flags, s, Gdot);
-  };
-  // n iterations; with `split` the last one stops after its residual test
-  // (its second part runs later, only if some right-hand side continues);
-  // `from_start`: the first of them is the solve's first iteration
-  auto iterations = [&](int n, bool split, bool from_start) {
-    for (int q = 0; q < n; ++q) {
-      iteration_head(from_start && q == 0, q == n - 1);
-      if (!(split && q == n - 1)) iteration_tail();
-    }
-  };
-  // exit step: true residual, centering of U, state to the mapped host mirror
-  auto tail = [&]() { launch_finish(p->g, eta, u, part, st, p->st_dev, batch, G, s); };
-
-  // Finds or captures the graph of `key`; returns its index or -1.
-  auto graph_for = [&](const kp_plan::GraphKey& key, auto&& body) -> int {
-    for (size_t e = 0; e < p->graphs.size(); ++e)
-      if (p->graphs[e].key == key) {
-        std::rotate(p->graphs.begin() + e, p->graphs.begin() + e + 1, p->graphs.end());
-        return (int)p->graphs.size() - 1;
-      }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::lock_guard<std::mutex> lk(api_mutex());
-    bool okc = ok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    if (okc) {
-      body();
-      okc = ok(hipStreamEndCapture(s, &graph)) && graph != nullptr;
-    }
-    if (okc) okc = ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipGetLastError();
-    if (!okc) {
-      p->graphs_ok = false;   // capture unavailable: launch directly from now on
-      return -1;
-    }
-    if (p->graphs.size() >= 8) {
-      (void)hipGraphExecDestroy(p->graphs.front().exec);
-      p->graphs.erase(p->graphs.begin());
-    }
-    p->graphs.push_back({key, exec, {}});
-    return (int)p->graphs.size() - 1;
-  };
-
-  // The first chunk of iterations is what the previous solve on this plan
-  // needed (or a guess per precision).  It runs as one captured HIP graph
-  // (cached per plan); when the caller repeats the previous solve's buffers
-  // the whole solve -- start, chunk and exit step -- is one graph.  Any
-  // further iterations run one at a time, each followed by the exit step and
-  // a stream synchronisation.  Kernels of finished right-hand sides return at
-  // once, so a solve that behaves like the previous one takes a single
-  // synchronisation and launches no idle iterations.
-  // Small 2D problems with the FP64 pseudoinverse: the whole solve is one
-  // kernel (the same stopping rules, without the low-mode certificate).
-  const bool small = p->small_ok && p->pc_kind == KP_PRECOND_PINV && !diag &&
-                     !(flags & (KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_ANORM_STOP));
-  if (small) {
-    p->small_last.eta = eta;
-    p->small_last.u = u;
-    p->small_last.batch = batch;
-    p->small_last.max_iter = max_iter;
-    p->small_last.flags = flags;
-    p->small_last.tol = tol;
-    launch_small_solve(p->g, p->small, eta, u, st, p->st_dev, p->hist_dev, hs, batch, tol, max_iter,
-                       flags, s);
-    if (!ok(hipGetLastError())) return KP_EHIP;
-    if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
-    if (p->profiling) p->tracer.collect();
-  } else {
-  const bool use_graphs = p->graphs_ok && !p->profiling && !(flags & KP_FLAG_NO_GRAPH);
-  const bool repeat = eta == p->last_eta && u == p->last_u;
-  p->last_eta = eta;
-  p->last_u = u;
-  int done_iters = 0;
-  int chunk = p->expect_iters > 0 ? p->expect_iters
-              : ((flags & KP_FLAG_NO_PRECOND) ? 8 : ((p->prec == PREC_F64 || p->prec == PREC_I8X7) ? 1 : (p->prec == PREC_BF16 ? 8 : 2)));
-  // a first chunk that ends where the previous solve stopped, before the
-  // last preconditioning, launches no kernels for finished right-hand sides
-  const bool split_first = p->expect_iters > 0 && p->expect_split;
-  bool pending_tail = false;    // second part of a split iteration still owed
-  bool first = true;
-  while (true) {
-    const int n = std::min(chunk, max_iter - done_iters);
-    const bool split = first && split_first && n == chunk;
-    const int nkey = 2 * n + (split ? 1 : 0);
-    bool launched = false;
-    if (first && use_graphs) {
-      if (repeat) {
-        const kp_plan::GraphKey key{1, batch, nkey, flags, hs, tol, u, p->hist_dev, diag_dev, eta};
-        const int gi = graph_for(key, [&]() { head(); iterations(n, split, true); tail(); });
-        if (gi >= 0) {
-          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
-          launched = true;
-        }
-      } else {
-        head();
-        // (the iterations read eta for the descriptors, and as R_0 of a
-        // nonsingular set in the first U/R update)
-        const kp_plan::GraphKey key{0,     batch, nkey,        flags,   hs,
-                                    tol,   u,     p->hist_dev, diag_dev,
-                                    (diag || !p->g.singular) ? eta : nullptr};
-        const int gi = graph_for(key, [&]() { iterations(n, split, true); });
-        if (gi >= 0) {
-          if (!ok(hipGraphLaunch(p->graphs[gi].exec, s))) return KP_EHIP;
-        } else {
-          iterations(n, split, true);
-        }
-        tail();
-        launched = true;
-      }
-    }
-    if (!launched) {
-      if (first) head();
-      if (pending_tail) iteration_tail();
-      iterations(n, split, first);
-      tail();
-    }
-    pending_tail = split;
-    first = false;
-    done_iters += n;
-    if (!ok(hipGetLastError())) return KP_EHIP;
-    if (!ok(hipStreamSynchronize(s))) return KP_EHIP;
-    if (p->profiling) p->tracer.collect();
-    bool all_done = true;
-    for (int b = 0; b < batch; ++b) all_done = all_done && p->st_host[b].done != RUNNING;
-    if (all_done || done_iters >= max_iter) break;
-    chunk = 1;
-  }
-  }   // general path
-  if (res_hist) std::memcpy(res_hist, p->hist, (size_t)batch * hs * sizeof(double));
-
-  int worst = KP_OK;
-  int max_it = 0;
-  for (int b = 0; b < batch; ++b) {
-    const RhsState& x = p->st_host[b];
-    int stt;
-    switch (x.done) {
-      case CONVERGED: case ZERO_RHS: stt = KP_OK; break;
-      case BREAKDOWN: stt = KP_EBREAKDOWN; break;
-      case NONFINITE: stt = KP_ENONFINITE; break;
-      default: stt = KP_NOT_CONVERGED; break;
-    }
-    if (results) {
-      kp_result& r = results[b];
-      r.status = stt;
-      r.iterations = x.iter;
-      r.pinv_applications = x.pinv_count;
-      r.reserved = 0;
-      r.rel_res = x.rel_res;
-      r.true_rel_res = x.true_rel_res;
-      r.err_est = x.err_est;
-      r.removed_mean = x.mean;
-    }
-    if (stt < 0 && (worst >= 0 || stt < worst)) worst = stt;
-    else if (stt == KP_NOT_CONVERGED && worst == KP_OK) worst = stt;
-    if (stt == KP_OK) max_it = std::max(max_it, x.iter);
-  }
-  if (max_it > 0) {
-    p->expect_iters = max_it;
-    // split next time if every right-hand side that took max_it iterations
-    // stopped before preconditioning in its last one
-    bool split = true;
-    for (int b = 0; b < batch; ++b) {
-      const RhsState& x = p->st_host[b];
-      if (x.done == CONVERGED && x.iter == max_it && x.pinv_count > x.iter) split = false;
-    }
-    p->expect_split = split;
-  }
-  return worst;
+int kp_wait(kp_ticket* t) {
+  if (!t) return KP_EINVAL;
+  solve_advance(t, true);
+  const int rc = t->status;
+  if (t->p && t->p->busy == t) t->p->busy = nullptr;
+  delete t;
+  return rc;
 }
 
 int kp_plan_diagnostics(const kp_plan* p, double* out, int batch, int hs, int delay) {
   if (!p || !out || p->diag_batch == 0 || batch != p->diag_batch || hs != p->diag_hs ||
       delay < 1)
     return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   const double nan = std::numeric_limits<double>::quiet_NaN();
   for (int b = 0; b < batch; ++b) {
     const double* raw = p->diag + (size_t)b * hs * DIAG_RAW;
@@ -902,6 +1080,7 @@ int kp_lowrank_table(int n, int bc_n, int q, int bc_q, int rank, double* table) 
 int kp_plan_set_preconditioner(kp_plan* p, int kind, int steps, double omega) {
   if (!p || (kind != KP_PRECOND_PINV && kind != KP_PRECOND_JACOBI && kind != KP_PRECOND_LOWRANK))
     return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (kind == KP_PRECOND_JACOBI &&
       (steps < 1 || steps > 10000 || !(omega >= 1.0) || !std::isfinite(omega)))
     return KP_EINVAL;
@@ -950,6 +1129,7 @@ int kp_plan_set_preconditioner(kp_plan* p, int kind, int steps, double omega) {
 
 int kp_apply_preconditioner(kp_plan* p, const double* R, double* Z, int batch) {
   if (!p || !R || !Z || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (!aligned16(R) || !aligned16(Z)) return KP_EINVAL;
   if (overlap(R, Z, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
   int rc = ensure_workspace(p);
@@ -963,6 +1143,7 @@ int kp_apply_preconditioner(kp_plan* p, const double* R, double* Z, int batch) {
 
 int kp_assemble_rhs(kp_plan* p, const double* eta, double* rhs, int batch, const double* faces) {
   if (!p || !eta || !rhs || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (!aligned16(eta) || !aligned16(rhs)) return KP_EINVAL;
   const size_t vbytes = (size_t)p->g.N * batch * 8;
   if (eta != rhs && overlap(eta, rhs, vbytes)) return KP_EINVAL;
@@ -981,6 +1162,7 @@ int kp_assemble_rhs(kp_plan* p, const double* eta, double* rhs, int batch, const
 
 int kp_field(kp_plan* p, const double* u, double* eps, int batch, const double* faces) {
   if (!p || !u || !eps || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (!aligned16(u) || !aligned16(eps)) return KP_EINVAL;
   const size_t ub = (size_t)p->g.N * batch * 8;
   const char* a = (const char*)u;
@@ -1005,6 +1187,7 @@ const char* kp_strerror(int s) {
     case KP_EHIP: return "HIP runtime error";
     case KP_ENONFINITE: return "non-finite value in right-hand side or iterate";
     case KP_EBREAKDOWN: return "CG breakdown (non-positive curvature or rho)";
+    case KP_EBUSY: return "the plan has a solve in flight (kp_solve_async not yet waited for)";
     default: return "unknown status";
   }
 }
@@ -1015,6 +1198,7 @@ const char* kp_last_error(void) { return t_last_error; }
 
 int kp_plan_autotune(kp_plan* p, int batch, int reps, int* chosen) {
   if (!p || batch < 1 || batch > p->max_batch || reps < 1 || reps > 1000) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   (void)hipGetLastError();
   int rc = ensure_workspace(p);
   if (rc != KP_OK) return rc;
@@ -1072,6 +1256,7 @@ int kp_plan_time_kernel(kp_plan* p, int cls, int batch, int flags, int reps, dou
   if (!p || !avg_ms || batch < 1 || batch > p->max_batch || reps < 1 || reps > 100000 ||
       (flags & ~KP_FLAG_FLEX_BETA))
     return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   const int dim = p->g.dim;
   int q = -1;
   switch (cls) {
@@ -1160,6 +1345,7 @@ int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
 
 int kp_plan_set_tuning(kp_plan* p, const int* cfg, int n) {
   if (!p || !cfg || n != 2 * p->g.dim) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   for (int q = 0; q < n; ++q)
     if (!mp_config_allowed(cfg[q], p->prec) || !mp_config_fits(cfg[q], p->op.n[q % p->g.dim]))
       return KP_EINVAL;
@@ -1175,6 +1361,7 @@ int kp_plan_graph_count(const kp_plan* p) {
 
 int kp_plan_set_profiling(kp_plan* p, int enable) {
   if (!p) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
   if (p->profiling != (enable != 0)) clear_graphs(p);   // captured with or without events
   p->profiling = enable != 0;
   return KP_OK;

@@ -252,7 +252,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 constexpr int STX = 64, RY = 4, STY = RY * (VT / 64);
 constexpr int NXCD = 8;
 
-enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC, ZM_DIAG };
+enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC, ZM_DIAG, ZM_RES };
 
 struct ZGrid {
   int ntx, ntiles;    // tiles along x, tiles per plane
@@ -319,6 +319,9 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 // ZM_DIAG: P is the iterate U_s, h = eta - mean; partials ||h - L U||^2,
 //          sum U, <U, L U>, <U, h> (the descriptors of Experiment 5.4); runs
 //          only for a right-hand side whose iterate s is not yet recorded
+// ZM_RES:  P is a caller's start U_0 (warm start), R receives
+//          R_0 = (eta - mean) - L U_0; partials sum R, ||R||^2, ||U_0||^2,
+//          sum U_0
 template <int MODE>
 __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __restrict__ P,
                                            double* __restrict__ W, double* __restrict__ R,
@@ -360,10 +363,11 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   // U_0 = 0 is never stored: a right-hand side that made no iteration takes
   // its stencil loads from eta (discarded) and writes U = 0 instead, so that
   // no cell is both read through P and written through U
-  const bool uz = MODE == ZM_TRUE && st[rhs].iter == 0;
+  const bool uz = MODE == ZM_TRUE && st[rhs].iter == 0 && !st[rhs].warm;
   const double* p = (uz ? eta : P) + off;
   const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
-  const double mean = (MODE == ZM_TRUE || MODE == ZM_DIAG) ? st[rhs].mean : 0.0;
+  const double mean =
+      (MODE == ZM_TRUE || MODE == ZM_DIAG || MODE == ZM_RES) ? st[rhs].mean : 0.0;
   const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
   // edge-load lanes: lane r < RY fetches the left edge of row r, lane 32 + r
   // the right edge
@@ -384,7 +388,8 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   };
 
   // the other streams of a mode (R and U, or eta, or R) at the cells of plane kk
-  constexpr bool XS = MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG;
+  constexpr bool XS = MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG ||
+                      MODE == ZM_RES;
   auto extra = [&](int kk, double (&a)[RY], double (&b)[RY]) {
     const uint32_t base = (uint32_t)kk * plane;
 #pragma unroll
@@ -477,6 +482,13 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           a1 += cc;
           a2 += cc * wv;
           a3 += cc * h;
+        } else if (MODE == ZM_RES) {
+          const double rr = (ea[r] - mean) - wv;
+          R[idx] = rr;
+          a0 += rr;
+          a1 += rr * rr;
+          a2 += cc * cc;
+          a3 += cc;
         } else if (MODE == ZM_JAC) {
           const double d = diag_1d(i, nx, bcx) + diag_1d(y0 + r, ny, bcy) +
                            (three ? diag_1d(k, nz, bcz) : 0.0);
@@ -519,6 +531,10 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   } else if (MODE == ZM_DIAG) {
     double v[4] = {a0, a1, a2, a3};
     const int sl[4] = {S_SQ, S_SUM, S_DOT, S_AUX};
+    write_partials<4>(v, sl, part, rhs, b);
+  } else if (MODE == ZM_RES) {
+    double v[4] = {a0, a1, a2, a3};
+    const int sl[4] = {S_SUM, S_SQ, S_AUX, S_AUX2};
     write_partials<4>(v, sl, part, rhs, b);
   } else {
     double v[2] = {a0, a1};
@@ -584,7 +600,9 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   RhsState& s = st[rhs];
   s.rsum = v[0];
   s.rr = v[1];
-  s.uu = v[2];
+  // ||U_s||^2 of the zero-mean iterate: the updates have zero mean on a
+  // singular set, so U_s keeps the mean of a warm start U_0 (removed at exit)
+  s.uu = s.warm ? fmax(v[2] - (double)g.N * s.u0mean * s.u0mean, 0.0) : v[2];
   s.iter += 1;
   s.need_cert = 0;   // a certificate applies to this iterate only
   s.rel_res = sqrt(v[1] / s.h2);
@@ -600,18 +618,51 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   } else if ((flags & F_RESIDUAL_ONLY) && s.rel_res <= tol) {
     s.done = CONVERGED;
     return;
-  } else if (!(flags & F_RESIDUAL_ONLY) && s.rel_res <= tol && v[2] > 0.0) {
+  } else if (!(flags & F_RESIDUAL_ONLY) && s.rel_res <= tol && s.uu > 0.0) {
     // the error U_s - u = -L^+ R_s has norm at most ||R_s|| / lambda_min:
     // when this bound already meets tol, the error estimate ||Z_s|| / ||U_s||
     // and the preconditioner application it needs are skipped; otherwise
     // the sharper low-mode bound is tried next
-    const double bound = sqrt(v[1] / v[2]) / g.lam_min;
+    const double bound = sqrt(v[1] / s.uu) / g.lam_min;
     if (bound <= tol) {
       s.err_est = bound;
       s.done = CONVERGED;
       return;
     }
     s.need_cert = (flags & F_CERT) ? 1 : 0;
+  }
+  set_scale(s, v[1], (double)g.N);
+}
+
+// Warm start: the residual of the caller's U_0 (ZM_RES partials) becomes
+// R_0's sums; the start itself may already meet the stopping rule (s = 0).
+__global__ __launch_bounds__(VT) void k_fin_warm(Geom g, const double* part, RhsState* st,
+                                                 double* hist, int hist_stride, int G, double tol,
+                                                 int flags) {
+  const int rhs = blockIdx.x;
+  if (st[rhs].done) return;
+  double v[4];
+  const int sl[4] = {S_SUM, S_SQ, S_AUX, S_AUX2};
+  read_partials<4>(part, rhs, sl, G, v);
+  if (threadIdx.x != 0) return;
+  RhsState& s = st[rhs];
+  s.warm = 1;
+  s.u0mean = g.singular ? v[3] / (double)g.N : 0.0;
+  s.rsum = v[0];
+  s.rr = v[1];
+  s.uu = fmax(v[2] - (double)g.N * s.u0mean * s.u0mean, 0.0);
+  s.rel_res = sqrt(v[1] / s.h2);
+  if (hist) hist[(int64_t)rhs * hist_stride] = s.rel_res;
+  if (!isfinite(s.rel_res) || !isfinite(v[2])) { s.done = NONFINITE; return; }
+  if (!(flags & F_ANORM_STOP) && s.rel_res <= tol) {
+    if (flags & F_RESIDUAL_ONLY) { s.done = CONVERGED; return; }
+    // the error of U_0 is L^+ R_0, at most ||R_0|| / lambda_min
+    const double bound = s.uu > 0.0 ? sqrt(v[1] / s.uu) / g.lam_min : INFINITY;
+    if (bound <= tol) {
+      s.err_est = bound;
+      s.done = CONVERGED;
+      return;
+    }
   }
   set_scale(s, v[1], (double)g.N);
 }
@@ -679,6 +730,21 @@ void launch_init(const Geom& g, const double* eta, double* R, double* U, double*
   trace_end(KC_INIT, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_h, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, G);
+  trace_end(KC_FINALIZE, s);
+}
+
+void launch_warm(const Geom& g, const double* eta, const double* U, double* R, double* part,
+                 RhsState* st, double* hist, int hist_stride, int batch, double tol, int flags,
+                 hipStream_t s) {
+  const ZGrid z = zgrid_for(g);
+  trace_begin(KC_INIT, s);
+  hipLaunchKernelGGL(k_zm<ZM_RES>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z, U,
+                     (double*)nullptr, R, (double*)nullptr, eta, part, (const RhsState*)st, 0.0,
+                     0);
+  trace_end(KC_INIT, s);
+  trace_begin(KC_FINALIZE, s);
+  hipLaunchKernelGGL(k_fin_warm, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride,
+                     z.nblocks, tol, flags);
   trace_end(KC_FINALIZE, s);
 }
 

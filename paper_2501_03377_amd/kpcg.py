@@ -25,6 +25,7 @@ KP_ENOMEM = -2
 KP_EHIP = -3
 KP_ENONFINITE = -4
 KP_EBREAKDOWN = -5
+KP_EBUSY = -6
 
 KP_FLAG_NO_PRECOND = 1
 KP_FLAG_FLEX_BETA = 2
@@ -32,6 +33,7 @@ KP_FLAG_RESIDUAL_ONLY = 4
 KP_FLAG_NO_GRAPH = 8
 KP_FLAG_DIAGNOSTICS = 16
 KP_FLAG_ANORM_STOP = 32
+KP_FLAG_WARM_START = 64
 KP_DIAG_COLUMNS = 7
 # Columns of kp_plan_diagnostics.
 DIAG_COLUMNS = ("true_rel_res", "rel_res", "kappa", "error_proxy", "null_component",
@@ -47,7 +49,7 @@ EXPORTS = (
     "kp_tile_shape", "kp_server_create", "kp_server_submit", "kp_server_poll", "kp_server_now",
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
-    "kp_plan_diagnostics", "kp_lowrank_table",
+    "kp_plan_diagnostics", "kp_lowrank_table", "kp_solve_async", "kp_poll", "kp_wait",
 )
 KERNEL_CLASSES = 18
 
@@ -149,6 +151,10 @@ def _load():
         "kp_apply_laplacian": (i, [vp, vp, vp, i]),
         "kp_apply_pinv": (i, [vp, vp, vp, i]),
         "kp_solve": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(KpResult), pd]),
+        "kp_solve_async": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(KpResult), pd,
+                               ctypes.POINTER(vp)]),
+        "kp_poll": (i, [vp]),
+        "kp_wait": (i, [vp]),
         "kp_strerror": (ctypes.c_char_p, [i]),
         "kp_version": (ctypes.c_char_p, []),
         "kp_plan_set_profiling": (i, [vp, i]),
@@ -253,6 +259,25 @@ def kp_solve(handle, eta_ptr, u_ptr, batch, tol, max_iter, flags, results, hist)
     hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist is not None else None
     return _lib.kp_solve(handle, ctypes.c_void_p(eta_ptr), ctypes.c_void_p(u_ptr), batch,
                          float(tol), int(max_iter), int(flags), results, hp)
+
+
+def kp_solve_async(handle, eta_ptr, u_ptr, batch, tol, max_iter, flags, results, hist):
+    """(status, ticket handle); results and hist must stay alive until
+    kp_wait has returned."""
+    hp = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist is not None else None
+    ticket = ctypes.c_void_p()
+    rc = _lib.kp_solve_async(handle, ctypes.c_void_p(eta_ptr), ctypes.c_void_p(u_ptr), batch,
+                             float(tol), int(max_iter), int(flags), results, hp,
+                             ctypes.byref(ticket))
+    return rc, ticket
+
+
+def kp_poll(ticket):
+    return _lib.kp_poll(ticket)
+
+
+def kp_wait(ticket):
+    return _lib.kp_wait(ticket)
 
 
 def kp_plan_set_profiling(handle, enable):
@@ -554,8 +579,11 @@ class Plan:
 
     def solve(self, eta, tol=1e-10, max_iter=50, flags=0, out=None, raise_on_error=True):
         """Returns (u, results, history, status); results is a list of dicts,
-        history a (batch, max_iter+1) numpy array of ||R_s|| / ||eta_c||."""
+        history a (batch, max_iter+1) numpy array of ||R_s|| / ||eta_c||.
+        With KP_FLAG_WARM_START, `out` holds U_0 on entry."""
         batch = self._check(eta, "eta")
+        if (flags & KP_FLAG_WARM_START) and out is None:
+            raise ValueError("a warm start takes U_0 in `out`")
         u = out if out is not None else _torch().empty_like(eta)
         results = (KpResult * batch)()
         hist = np.zeros((batch, max_iter + 1))
@@ -566,6 +594,23 @@ class Plan:
             raise KpError(rc, "kp_solve")
         return u, [r.as_dict() for r in results], hist, rc
 
+    def solve_async(self, eta, tol=1e-10, max_iter=50, flags=0, out=None):
+        """Enqueues the solve and returns a Ticket at once (kp_solve_async);
+        ticket.poll() is True once it has finished, ticket.wait() returns
+        (u, results, history, status) as solve() does."""
+        batch = self._check(eta, "eta")
+        if (flags & KP_FLAG_WARM_START) and out is None:
+            raise ValueError("a warm start takes U_0 in `out`")
+        u = out if out is not None else _torch().empty_like(eta)
+        results = (KpResult * batch)()
+        hist = np.zeros((batch, max_iter + 1))
+        rc, th = kp_solve_async(self._h, eta.data_ptr(), u.data_ptr(), batch, tol, max_iter,
+                                flags, results, hist)
+        if rc != KP_OK:
+            raise KpError(rc, "kp_solve_async")
+        self._last_shape = (batch, max_iter + 1)
+        return Ticket(th, eta, u, results, hist)
+
     def diagnostics(self, delay=4):
         """Descriptors of every iterate of the last solve, which must have
         used KP_FLAG_DIAGNOSTICS: a (batch, max_iter+1, 7) array with the
@@ -575,6 +620,45 @@ class Plan:
         if rc != KP_OK:
             raise KpError(rc, "kp_plan_diagnostics")
         return out
+
+
+class Ticket:
+    """A solve in flight (kp_solve_async).  Keeps eta, u and the result
+    arrays alive until wait() has returned."""
+
+    def __init__(self, handle, eta, u, results, hist):
+        self._h = handle
+        self._keep = (eta, u, results, hist)
+        self._out = None
+
+    def poll(self):
+        """True once the solve has finished; each call that finds the device
+        idle also enqueues the next iteration of a solve that continues."""
+        if self._h is None:
+            return True
+        rc = kp_poll(self._h)
+        if rc < 0:
+            raise KpError(rc, "kp_poll")
+        return rc == 1
+
+    def wait(self, raise_on_error=True):
+        """Blocks until the solve has finished; (u, results, history, status)."""
+        if self._h is not None:
+            rc = kp_wait(self._h)
+            self._h = None
+            eta, u, results, hist = self._keep
+            self._out = (u, [r.as_dict() for r in results], hist, rc)
+        if self._out[3] < 0 and raise_on_error:
+            raise KpError(self._out[3], "kp_wait")
+        return self._out
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                kp_wait(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 class Server:

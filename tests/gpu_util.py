@@ -17,8 +17,9 @@ def to_host(t):
 
 
 def oracle_solve(eta, bcs):
-    """Converged minimum-norm solution for a device-layout array."""
-    return oracle.solve(eta.T, bcs).u.T
+    """The minimum-norm solution L^+ eta for a device-layout array (the
+    oracle's eigen-expansion; zero-mean for a singular set)."""
+    return oracle.min_norm_solution(eta.T, bcs)[0].T
 
 
 def oracle_laplacian(p, bcs):
@@ -33,6 +34,21 @@ def oracle_pinv(r, bcs):
 def rel(a, b):
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def rel_max(a, b):
+    """max |a - b| / max |b|: the element-wise counterpart of rel."""
+    nb = np.max(np.abs(b)) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (nb if nb > 0 else 1.0)) if a.size else 0.0
+
+
+def assert_close(u, ref, tol, what=""):
+    """The solution parity bar: relative error at most tol both norm-wise,
+    ||u - ref||_2 <= tol ||ref||_2, and element by element,
+    max|u - ref| <= tol max|ref|."""
+    e2, einf = rel(u, ref), rel_max(u, ref)
+    assert e2 <= tol and einf <= tol, (what, e2, einf, tol)
+    return e2, einf
 
 
 def grid_dims(shape):

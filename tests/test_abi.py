@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_strerror():
     from paper_2501_03377_amd import kpcg
     assert "kpcg" in kpcg.kp_version()
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert kpcg.kp_strerror(code) != "unknown status"
 
 
@@ -133,3 +133,16 @@ def test_int8_split_tile_id():
     assert kp_tile_shape(13, PREC["i8x7"])[0] == KP_OK
     assert kp_tile_shape(0, PREC["i8x7"])[0] == KP_EINVAL
     assert kp_tile_shape(13, 5)[0] == KP_EINVAL
+
+
+def test_async_entry_points_reject_null_arguments():
+    # no device work: argument checks only
+    import ctypes
+    from paper_2501_03377_amd import kpcg
+    assert kpcg._lib.kp_poll(None) == kpcg.KP_EINVAL
+    assert kpcg._lib.kp_wait(None) == kpcg.KP_EINVAL
+    t = ctypes.c_void_p(123)
+    rc = kpcg._lib.kp_solve_async(None, None, None, 1, 1e-10, 10, 0, None, None, ctypes.byref(t))
+    assert rc == kpcg.KP_EINVAL and not t.value
+    assert kpcg._lib.kp_solve_async(None, None, None, 1, 1e-10, 10, 0, None, None,
+                                    None) == kpcg.KP_EINVAL

@@ -1,0 +1,262 @@
+"""GPU checks of the C ABI beyond a plain kp_solve: warm starts (Algorithm
+1 from a given U_0), the asynchronous solve (kp_solve_async / kp_poll /
+kp_wait) called through the raw C entry points, the plan's busy state, and
+the breakdown status forced by an indefinite preconditioner."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_close, grid_dims, oracle_solve, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(shape, bcs, prec="f64", max_batch=1):
+    from paper_2501_03377_amd import Plan
+    nx, ny, nz = grid_dims(shape)
+    return Plan(nx, ny, nz, bcs, prec=prec, max_batch=max_batch)
+
+
+# ------------------------------------------------------------ warm start ----
+@pytest.mark.parametrize("bcs", [("D", "N", "P"), ("P", "N", "N"), ("DN", "D")])
+def test_warm_start_at_the_solution_makes_no_iteration(bcs):
+    # U_0 = the answer (plus a null-space constant for a singular set): the
+    # start already meets the stopping rule, no iteration is made, and the
+    # returned u is U_0 (centred for a singular set)
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_WARM_START
+    shape = (12, 10, 16)[-len(bcs):] if len(bcs) == 3 else (24, 20)
+    eta = synth.charge_field(shape, ncharges=80, seed=41)
+    ref = oracle_solve(eta, bcs)
+    shift = 0.75 if oracle.is_singular(bcs) else 0.0
+    plan = _plan(shape, bcs)
+    u0 = to_dev(ref + shift)
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, flags=KP_FLAG_WARM_START, out=u0)
+    r = res[0]
+    assert rc == 0 and r["iterations"] == 0 and r["pinv_applications"] == 0, r
+    assert hist[0, 0] == r["rel_res"] <= 1e-10
+    assert_close(to_host(u), ref, 1e-13, bcs)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec,shape,bcs", [("f64", (20, 24, 32), ("P", "D", "DN")),
+                                            ("f32", (16, 32, 48), ("N", "N", "N")),
+                                            ("i8x7", (32, 32, 48), ("P", "P", "D")),
+                                            ("bf16", (24, 20, 36), ("D", "P", "N")),
+                                            ("f64", (40, 56), ("N", "DN"))])
+def test_warm_start_parity(prec, shape, bcs):
+    # from an arbitrary start: the first residual is that of U_0 (the
+    # oracle's), the answer is the minimum-norm solution to the run's tol
+    from paper_2501_03377_amd import KP_FLAG_FLEX_BETA, KP_FLAG_WARM_START
+    rng = np.random.default_rng(42)
+    eta = synth.charge_field(shape, ncharges=300, seed=43)
+    ref = oracle_solve(eta, bcs)
+    start = ref + 1e-3 * np.abs(ref).max() * rng.standard_normal(shape)
+    fl = KP_FLAG_WARM_START | (KP_FLAG_FLEX_BETA if prec == "bf16" else 0)
+    plan = _plan(shape, bcs, prec=prec)
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=60, flags=fl,
+                                  out=to_dev(start))
+    assert rc == 0, res
+    o = oracle.pcg(eta.T, bcs, precond=None, u0=start.T, fixed_iterations=0)
+    assert abs(hist[0, 0] - o.rec_rel_res[0]) <= 1e-12 * o.rec_rel_res[0]
+    assert res[0]["iterations"] >= 1
+    assert_close(to_host(u), ref, 1e-10, (prec, bcs))
+    plan.close()
+
+
+def test_warm_start_saves_iterations_of_plain_cg():
+    # M = I: a start close to the answer needs fewer iterations than U_0 = 0,
+    # both reaching the answer (residual-only stop, tol 1e-12)
+    from paper_2501_03377_amd import KP_FLAG_NO_PRECOND, KP_FLAG_WARM_START
+    shape, bcs = (16, 20, 24), ("D", "D", "N")
+    eta = synth.charge_field(shape, ncharges=100, seed=44)
+    ref = oracle_solve(eta, bcs)
+    near = ref + 1e-6 * np.random.default_rng(45).standard_normal(shape)
+    plan = _plan(shape, bcs)
+    _, cold, _, rc0 = plan.solve(to_dev(eta), tol=1e-12, max_iter=500, flags=KP_FLAG_NO_PRECOND)
+    u, warm, _, rc1 = plan.solve(to_dev(eta), tol=1e-12, max_iter=500,
+                                 flags=KP_FLAG_NO_PRECOND | KP_FLAG_WARM_START,
+                                 out=to_dev(near))
+    assert rc0 == 0 and rc1 == 0
+    assert warm[0]["iterations"] < cold[0]["iterations"], (warm[0], cold[0])
+    # residual-only stop at 1e-12 with kappa below 10^3
+    assert_close(to_host(u), ref, 1e-8)
+    plan.close()
+
+
+def test_warm_start_batch_and_graph_replay():
+    # a batch with one start at the answer and others away from it; repeated
+    # with the same buffers (whole-solve graph) the results are bitwise equal
+    # to an eager solve, and a zero right-hand side returns 0 whatever U_0
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_NO_GRAPH, KP_FLAG_WARM_START
+    shape, bcs = (16, 24, 20), ("P", "DN", "N")
+    etas = np.stack([synth.charge_field(shape, ncharges=60, seed=46 + b) for b in range(3)]
+                    + [np.zeros(shape)])
+    refs = [oracle_solve(etas[b], bcs) for b in range(4)]
+    rng = np.random.default_rng(47)
+    starts = np.stack([refs[0], refs[1] + 1e-4 * rng.standard_normal(shape),
+                       rng.standard_normal(shape), rng.standard_normal(shape)])
+    plan = _plan(shape, bcs, prec="f32", max_batch=4)
+    e = to_dev(etas)
+    out = torch.empty_like(e)
+    ref_u = None
+    for call, extra in enumerate((KP_FLAG_NO_GRAPH, 0, 0, 0)):
+        out.copy_(to_dev(starts))
+        _, res, hist, rc = plan.solve(e, tol=1e-10, max_iter=40, flags=KP_FLAG_WARM_START | extra,
+                                      out=out)
+        assert rc == 0, res
+        uh = to_host(out)
+        if ref_u is None:
+            ref_u = uh.copy()
+            assert res[0]["iterations"] == 0 and res[1]["iterations"] >= 1
+            assert np.array_equal(uh[3], np.zeros(shape)) and res[3]["iterations"] == 0
+            for b in range(3):
+                assert_close(uh[b], refs[b], 1e-10, b)
+        else:
+            assert np.array_equal(uh, ref_u), call
+    plan.close()
+
+
+# ------------------------------------------------------------- async API ----
+def _raw_solve_async(plan, eta, u, batch, tol, max_iter, flags):
+    from paper_2501_03377_amd import kpcg
+    results = (kpcg.KpResult * batch)()
+    hist = np.zeros((batch, max_iter + 1))
+    rc, ticket = kpcg.kp_solve_async(plan._h, eta.data_ptr(), u.data_ptr(), batch, tol, max_iter,
+                                     flags, results, hist)
+    return rc, ticket, results, hist
+
+
+def test_async_solve_through_the_c_entries():
+    # kp_solve_async returns before the solve has finished; kp_poll reports
+    # 0 until it has, then 1; kp_wait returns its status.  The answer and the
+    # per-RHS results equal kp_solve's on the same plan, bitwise, and the
+    # oracle's to tol.
+    import torch
+    from paper_2501_03377_amd import kpcg
+    shape, bcs = (32, 48, 64), ("P", "P", "DN")
+    etas = np.stack([synth.charge_field(shape, ncharges=400, seed=50 + b) for b in range(2)])
+    plan = _plan(shape, bcs, prec="f32", max_batch=2)
+    e = to_dev(etas)
+    u_sync, res_sync, hist_sync, rc = plan.solve(e, tol=1e-10, max_iter=40)
+    assert rc == 0
+    u = torch.full_like(e, float("nan"))
+    rc, ticket, results, hist = _raw_solve_async(plan, e, u, 2, 1e-10, 40, 0)
+    assert rc == 0 and ticket.value
+    polls = 0
+    while kpcg.kp_poll(ticket) == 0:
+        polls += 1
+        assert polls < 10**7
+    assert kpcg.kp_poll(ticket) == 1
+    assert kpcg.kp_wait(ticket) == 0
+    assert np.array_equal(to_host(u), to_host(u_sync))
+    assert np.array_equal(hist, hist_sync)
+    for b in range(2):
+        assert results[b].as_dict() == res_sync[b]
+        assert_close(to_host(u)[b], oracle_solve(etas[b], bcs), 1e-10, b)
+    plan.close()
+
+
+def test_async_solve_continues_on_poll():
+    # plain CG needs far more iterations than the first chunk (8 on a fresh
+    # plan): the rest is enqueued by kp_poll, one iteration per call that
+    # finds the device idle; the result equals a blocking solve's bitwise
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_NO_PRECOND, Plan, kpcg
+    shape, bcs = (12, 16, 20), ("D", "N", "D")
+    eta = to_dev(synth.charge_field(shape, ncharges=50, seed=52))
+    a = _plan(shape, bcs)
+    u = torch.empty_like(eta)
+    rc, ticket, results, hist = _raw_solve_async(a, eta, u, 1, 1e-11, 400, KP_FLAG_NO_PRECOND)
+    assert rc == 0
+    zeros = 0
+    while True:
+        r = kpcg.kp_poll(ticket)
+        if r == 1:
+            break
+        zeros += 1
+    assert kpcg.kp_wait(ticket) == 0
+    its = results[0].iterations
+    assert its > 20
+    b = _plan(shape, bcs)
+    ub, rb, _, rc = b.solve(eta, tol=1e-11, max_iter=400, flags=KP_FLAG_NO_PRECOND)
+    assert rc == 0 and rb[0]["iterations"] == its
+    assert np.array_equal(to_host(u), to_host(ub))
+    a.close()
+    b.close()
+
+
+def test_busy_plan_refuses_other_calls_until_waited():
+    import torch
+    from paper_2501_03377_amd import KP_EBUSY, kpcg
+    shape, bcs = (16, 16, 32), ("N", "P", "D")
+    eta = to_dev(synth.charge_field(shape, ncharges=40, seed=53))
+    plan = _plan(shape, bcs, prec="f32")
+    u = torch.empty_like(eta)
+    rc, ticket, results, hist = _raw_solve_async(plan, eta, u, 1, 1e-10, 30, 0)
+    assert rc == 0
+    z = torch.empty_like(eta)
+    assert kpcg.kp_apply_pinv(plan._h, eta.data_ptr(), z.data_ptr(), 1) == KP_EBUSY
+    assert kpcg.kp_solve(plan._h, eta.data_ptr(), z.data_ptr(), 1, 1e-10, 30, 0, None,
+                         None) == KP_EBUSY
+    rc2, t2, _, _ = _raw_solve_async(plan, eta, z, 1, 1e-10, 30, 0)
+    assert rc2 == KP_EBUSY and not t2.value
+    assert kpcg.kp_wait(ticket) == 0
+    assert_close(to_host(u), oracle_solve(to_host(eta), bcs), 1e-10)
+    assert kpcg.kp_apply_pinv(plan._h, eta.data_ptr(), z.data_ptr(), 1) == 0
+    # a plan destroyed with a solve in flight finishes it first
+    rc, ticket, results, hist = _raw_solve_async(plan, eta, u, 1, 1e-10, 30, 0)
+    assert rc == 0
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_ticket_wrapper_matches_solve():
+    from paper_2501_03377_amd import KP_FLAG_FLEX_BETA
+    shape, bcs = (24, 32, 40), ("N", "N", "N")
+    eta = to_dev(synth.charge_field(shape, ncharges=200, seed=54))
+    plan = _plan(shape, bcs, prec="bf16")
+    # a first solve sizes the plan's first chunk; the next two take the same
+    # launches (the count of applications depends on where chunks end)
+    plan.solve(eta, tol=1e-10, max_iter=60, flags=KP_FLAG_FLEX_BETA)
+    u1, r1, h1, rc1 = plan.solve(eta, tol=1e-10, max_iter=60, flags=KP_FLAG_FLEX_BETA)
+    t = plan.solve_async(eta, tol=1e-10, max_iter=60, flags=KP_FLAG_FLEX_BETA)
+    while not t.poll():
+        pass
+    u2, r2, h2, rc2 = t.wait()
+    assert rc1 == rc2 == 0 and r1 == r2
+    assert np.array_equal(to_host(u1), to_host(u2)) and np.array_equal(h1, h2)
+    plan.close()
+
+
+# ------------------------------------------------------------- breakdown ----
+def test_indefinite_lowrank_preconditioner_breaks_down():
+    # Sec. 4.3.2: a low-Kronecker-rank approximation may be indefinite.  On a
+    # 100 x 100 (D, DN) grid the rank-3 operator has a negative multiplier on
+    # the eigenmode (1, 99) (pinned on the CPU in test_oracle_lowrank); with
+    # that mode as the right-hand side, rho_0 = <R_0, M R_0> < 0 and the solve
+    # reports KP_EBREAKDOWN before any iteration.  Rank 1 is positive
+    # semidefinite and converges.
+    from paper_2501_03377_amd import KP_EBREAKDOWN
+    from pins import lemma_basis
+    n, q, bcs = 100, 100, ("D", "DN")
+    Qn, _ = lemma_basis(n, "D")
+    Qq, _ = lemma_basis(q, "DN")
+    eta = np.outer(Qn[:, 1], Qq[:, 99]).T.copy()     # device layout (ny, nx)
+    plan = _plan((q, n), bcs)
+    plan.set_preconditioner("lowrank", 3)
+    z = to_host(plan.apply_preconditioner(to_dev(eta)))
+    assert float(np.sum(z * eta)) < 0.0
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=50, raise_on_error=False)
+    assert rc == KP_EBREAKDOWN and res[0]["status"] == KP_EBREAKDOWN, res
+    assert res[0]["iterations"] == 0
+    plan.set_preconditioner("lowrank", 1)
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-12, max_iter=500, raise_on_error=False)
+    assert rc == 0, res
+    assert_close(to_host(u), oracle_solve(eta, bcs), 1e-8)
+    plan.close()

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import grid_dims, rel, to_dev, to_host
+from gpu_util import assert_close, grid_dims, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -81,7 +81,8 @@ def test_mixed_boundary_problem_end_to_end():
     rhs = plan.assemble_rhs(to_dev(np.zeros((ny, nx))), faces)
     u, res, _, rc = plan.solve(rhs, tol=1e-12)
     i = np.arange(1, nx + 1, dtype=float)[None, :]
-    assert rc == 0 and rel(to_host(u), -0.5 * i * np.ones((ny, 1))) <= 1e-10
+    assert rc == 0
+    assert_close(to_host(u), -0.5 * i * np.ones((ny, 1)), 1e-10)
     eps = to_host(plan.field(u, faces))
     assert np.allclose(eps[0], 0.5, atol=1e-9) and np.allclose(eps[1], 0.0, atol=1e-9)
     # a band of charge: GPU potential and field against the oracle
@@ -89,8 +90,9 @@ def test_mixed_boundary_problem_end_to_end():
     eta[:, 15:20] = 1.0
     rhs = plan.assemble_rhs(to_dev(eta), faces)
     u, res, _, rc = plan.solve(rhs, tol=1e-12)
-    ref = oracle.solve(oracle.assemble_rhs(eta.T, ("DN", "P"), faces), ("DN", "P")).u
-    assert rc == 0 and rel(to_host(u), ref.T) <= 1e-10
+    ref = oracle.min_norm_solution(oracle.assemble_rhs(eta.T, ("DN", "P"), faces), ("DN", "P"))[0]
+    assert rc == 0
+    assert_close(to_host(u), ref.T, 1e-10)
     eps = to_host(plan.field(u, faces))
     ref_eps = oracle.field(ref, ("DN", "P"), faces)
     # the band is uniform in y, so the y-component is zero up to rounding:
@@ -107,8 +109,9 @@ def test_nonhomogeneous_3d_solve_in_mixed_precision():
     eta = synth.charge_field(shape, ncharges=200, seed=73)
     plan = _plan(shape, bcs, prec="f32")
     u, res, _, rc = plan.solve(plan.assemble_rhs(to_dev(eta), faces), tol=1e-10)
-    ref = oracle.solve(oracle.assemble_rhs(eta.T, bcs, faces), bcs).u.T
-    assert rc == 0 and rel(to_host(u), ref) <= 1e-10
+    ref = oracle.min_norm_solution(oracle.assemble_rhs(eta.T, bcs, faces), bcs)[0].T
+    assert rc == 0
+    assert_close(to_host(u), ref, 1e-10)
 
 
 def test_periodic_face_data_is_rejected():
@@ -144,7 +147,7 @@ def test_jacobi_solves_match_the_oracle_and_rank_as_in_the_paper():
     from paper_2501_03377_amd import KP_FLAG_NO_PRECOND
     shape, bcs = (16, 24, 20), ("D", "N", "P")
     eta = synth.charge_field(shape, ncharges=60, seed=4)
-    ref = oracle.solve(eta.T, bcs).u.T
+    ref = oracle.min_norm_solution(eta.T, bcs)[0].T
     plan = _plan(shape, bcs)
     u_p, res_p, _, rc = plan.solve(to_dev(eta), tol=1e-10)
     assert rc == 0
@@ -153,8 +156,11 @@ def test_jacobi_solves_match_the_oracle_and_rank_as_in_the_paper():
     plan.set_preconditioner("jacobi", 3, 1.3)
     u_j, res_j, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=1000)
     assert rc == 0
-    for u in (u_p, u_cg, u_j):
-        assert rel(to_host(u), ref) <= 1e-8
+    # the pseudoinverse certifies the error; CG and Jacobi stop on the
+    # residual alone (tol 1e-10, kappa about 5e2 here)
+    assert_close(to_host(u_p), ref, 1e-10)
+    for u in (u_cg, u_j):
+        assert_close(to_host(u), ref, 1e-8)
     it = (res_p[0]["iterations"], res_j[0]["iterations"], res_cg[0]["iterations"])
     assert it[0] <= 3 < it[1] < it[2], it
     plan.set_preconditioner("pinv")

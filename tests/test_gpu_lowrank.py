@@ -58,7 +58,7 @@ def test_solves_rank_as_in_experiment_5_5():
     from paper_2501_03377_amd import KP_FLAG_NO_PRECOND
     shape, bcs = (64, 64), ("D", "D")
     eta = synth.gaussian_blobs_2d(64, 64, 16, 2.0, seed=1)
-    ref = oracle.solve(eta.T, bcs).u.T
+    ref = oracle.min_norm_solution(eta.T, bcs)[0].T
     plan = _plan(shape, bcs)
     its = {}
     for name, setup, flags in [("pinv", ("pinv",), 0), ("lowrank", ("lowrank", 3), 0),

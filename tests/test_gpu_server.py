@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import oracle_solve, rel, to_dev, to_host
+from gpu_util import assert_close, oracle_solve, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +47,7 @@ def test_server_results_match_oracle():
             c = done[k]
             assert c["status"] == 0, c
             u = to_host(outs[k]) if where == "dev" else outs[k]
-            err = rel(u, oracle_solve(etas[k], bcs))
-            assert err <= (1e-10 if prec == "f64" else tol), (k, err, c)
+            assert_close(u, oracle_solve(etas[k], bcs), 1e-10 if prec == "f64" else tol, (k, c))
             assert c["t_submit"] <= c["t_start"] <= c["t_end"]
         st = srv.stats()
         assert st["completed"] == len(cases) and st["plans_created"] == len(cases)
@@ -137,8 +136,7 @@ def test_server_int8_split_requests():
         for k, (shape, bcs) in enumerate(cases):
             c = done[k]
             assert c["status"] == 0 and c["iterations"] == 1, c
-            err = rel(outs[k], oracle_solve(etas[k], bcs))
-            assert err <= 1e-10, (k, err, c)
+            assert_close(outs[k], oracle_solve(etas[k], bcs), 1e-10, (k, c))
         assert srv.stats()["completed"] == len(cases)
     finally:
         srv.close()

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import grid_dims, oracle_solve, rel, to_dev, to_host
+from gpu_util import assert_close, grid_dims, oracle_solve, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +39,8 @@ def test_all_bc_triples_small_f64():
     for bcs in ALL3:
         u, res, hist, rc = _solve(eta, bcs)
         ref = oracle_solve(eta, bcs)
-        err = rel(_zero_mean_if(u, bcs), ref)
-        assert rc == 0 and err <= 1e-10, (bcs, rc, err, res)
+        assert rc == 0, (bcs, rc, res)
+        assert_close(_zero_mean_if(u, bcs), ref, 1e-10, bcs)
         assert res[0]["true_rel_res"] <= 1e-10
 
 
@@ -49,8 +49,8 @@ def test_all_bc_pairs_2d_f64():
     eta = rng.standard_normal((9, 13))
     for bcs in ALL2:
         u, res, hist, rc = _solve(eta, bcs)
-        err = rel(_zero_mean_if(u, bcs), oracle_solve(eta, bcs))
-        assert rc == 0 and err <= 1e-10, (bcs, rc, err)
+        assert rc == 0, (bcs, rc)
+        assert_close(_zero_mean_if(u, bcs), oracle_solve(eta, bcs), 1e-10, bcs)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "bf16x6"])
@@ -64,11 +64,10 @@ def test_multi_tile_ragged(shape, bcs, prec):
     u, res, hist, rc = _solve(eta, bcs, prec=prec, tol=1e-10, max_iter=60,
                               flags=2 if prec == "bf16" else 0)
     ref = oracle_solve(eta, bcs)
-    err = rel(u, ref)
-    print(f"{prec} {shape} {bcs}: iters {res[0]['iterations']} pinv {res[0]['pinv_applications']} "
-          f"err {err:.3e} rel_res {res[0]['rel_res']:.3e} true {res[0]['true_rel_res']:.3e}")
     assert rc == 0, res
-    assert err <= 1e-10, err
+    err = assert_close(u, ref, 1e-10, (prec, shape, bcs))
+    print(f"{prec} {shape} {bcs}: iters {res[0]['iterations']} pinv {res[0]['pinv_applications']} "
+          f"err {err} rel_res {res[0]['rel_res']:.3e} true {res[0]['true_rel_res']:.3e}")
     assert res[0]["true_rel_res"] <= 1e-10
 
 
@@ -76,8 +75,8 @@ def test_2d_64x64_dirichlet_blobs_f64():
     # 2D 64 x 64, Dirichlet on every edge, 16 Gaussian blobs, FP64, tol 1e-12
     eta = synth.gaussian_blobs_2d(64, 64, 16, 2.0, seed=1)
     u, res, hist, rc = _solve(eta, ("D", "D"), prec="f64", tol=1e-12)
-    err = rel(u, oracle_solve(eta, ("D", "D")))
-    assert rc == 0 and err <= 1e-10, (err, res)
+    assert rc == 0, res
+    assert_close(u, oracle_solve(eta, ("D", "D")), 1e-10)
     assert res[0]["rel_res"] <= 1e-12 and res[0]["true_rel_res"] <= 1e-12
 
 
@@ -92,9 +91,9 @@ def test_full_size_256x256x128_ppdn(prec):
         _FULL["eta"] = synth.charge_field((128, 256, 256), seed=2)
         _FULL["sol"] = oracle_solve(_FULL["eta"], ("P", "P", "DN"))
     u, res, hist, rc = _solve(_FULL["eta"], ("P", "P", "DN"), prec=prec, tol=1e-10)
-    err = rel(u, _FULL["sol"])
+    assert rc == 0, res
+    err = assert_close(u, _FULL["sol"], 1e-10, prec)
     print("256x256x128", prec, res[0], err)
-    assert rc == 0 and err <= 1e-10
 
 
 def test_batch_matches_single_f64():
@@ -151,7 +150,8 @@ def test_unpreconditioned_cg():
     eta = synth.charge_field((10, 12, 14), ncharges=50, seed=4)
     u, res, hist, rc = _solve(eta, ("D", "P", "N"), flags=1, max_iter=500, tol=1e-13)
     assert rc == 0 and res[0]["iterations"] > 10
-    assert rel(u, oracle_solve(eta, ("D", "P", "N"))) <= 1e-9
+    # stopped on the residual alone (1e-13): the error is within kappa times it
+    assert_close(u, oracle_solve(eta, ("D", "P", "N")), 1e-9)
 
 
 @pytest.mark.parametrize("prec,profile", [("f32", False), ("f64", True), ("bf16", False)])
@@ -205,6 +205,7 @@ def test_error_bound_stop(shape, bcs):
     uz = _zero_mean_if(u, bcs)
     err = rel(uz, ref)
     assert err <= r["err_est"] <= 1e-10
+    assert_close(uz, ref, 1e-10)
     h = eta - eta.mean() if oracle.is_singular(bcs) else eta
     lam_min = r["rel_res"] * np.linalg.norm(h) / (r["err_est"] * np.linalg.norm(uz))
     ev = np.linalg.eigvalsh(np.asarray(oracle.kronecker_sum(eta.T.shape, bcs)))
@@ -230,11 +231,12 @@ def test_lowmode_certificate_stop(prec, shape, bcs):
     ref = oracle_solve(eta, bcs)
     err = rel(uh, ref)
     assert err <= r["err_est"] <= 1e-10
+    assert_close(uh, ref, 1e-10)
     b = lowmode_error_bound(R, uh.T, bcs, 32)
     assert abs(b - r["err_est"]) <= 1e-3 * b, (b, r["err_est"])
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16", "i8x7"])
 def test_manufactured_solution_512_cube(prec):
     # the 512^3 (P, P, D) grid at full size: eta = L u for a known u (the
     # oracle's stencil, eq. 3.2), so every entry of the solve is checked
@@ -245,10 +247,12 @@ def test_manufactured_solution_512_cube(prec):
         _FULL["u512"] = u
         _FULL["eta512"] = oracle.apply_minus_laplacian(u.T, ("P", "P", "D")).T.copy()
     u = _FULL["u512"]
-    got, res, hist, rc = _solve(_FULL["eta512"], ("P", "P", "D"), prec=prec, tol=1e-10)
+    got, res, hist, rc = _solve(_FULL["eta512"], ("P", "P", "D"), prec=prec, tol=1e-10,
+                                flags=2 if prec == "bf16" else 0)
     r = res[0]
+    print("512^3", prec, r)
     assert rc == 0 and r["true_rel_res"] <= 1e-10, r
-    assert rel(got, u) <= 1e-10, (rel(got, u), r)
+    assert_close(got, u, 1e-10, (prec, r))
 
 
 @pytest.mark.parametrize("shape", [(64, 64), (17, 50), (3, 64), (64, 5)])
@@ -269,11 +273,12 @@ def test_small_2d_one_kernel_solve(shape):
         assert prof["small_solve"][1] == 1 and prof["stencil_dot"][1] == 0, bcs
         uh = to_host(u)
         for b in range(2):
-            ref = oracle_solve(eta[b], bcs)
-            if np.linalg.norm(ref) == 0.0:
+            if b == 1 and oracle.is_singular(bcs):
+                # a constant is all null space: the answer is exactly 0
                 assert np.abs(uh[b]).max() <= 1e-12, bcs
             else:
-                assert rel(_zero_mean_if(uh[b], bcs), ref) <= 1e-10, (bcs, b)
+                ref = oracle_solve(eta[b], bcs)
+                assert_close(_zero_mean_if(uh[b], bcs), ref, 1e-10, (bcs, b))
             assert res[b]["true_rel_res"] <= 1e-12
             assert hist[b, 0] in (0.0, 1.0) and hist[b, res[b]["iterations"]] == res[b]["rel_res"]
         plan.close()
@@ -358,7 +363,7 @@ def test_rhs_without_iterations_returns_zero_over_garbage(prec, bcs):
         assert res[1]["iterations"] == 0 and res[3]["iterations"] == 0
         for b in (0, 2):
             assert res[b]["status"] == 0 and res[b]["iterations"] >= 1
-            assert rel(_zero_mean_if(uh[b], bcs), oracle_solve(eta[b], bcs)) <= 1e-9
+            assert_close(_zero_mean_if(uh[b], bcs), oracle_solve(eta[b], bcs), 1e-10, b)
     plan.close()
 
 
@@ -379,7 +384,7 @@ def test_graph_replay_with_another_eta_buffer(bcs):
     for eta, ref_eta in ((d1, e1), (d2, e2), (d1, e1), (d2, e2)):
         u, res, _, rc = plan.solve(eta, tol=1e-10, max_iter=20, out=u)
         assert rc == 0
-        assert rel(_zero_mean_if(to_host(u), bcs), oracle_solve(ref_eta, bcs)) <= 1e-9
+        assert_close(_zero_mean_if(to_host(u), bcs), oracle_solve(ref_eta, bcs), 1e-10)
     plan.close()
 
 
@@ -426,7 +431,7 @@ def test_solve_with_operator_resident_tiles(prec, cfg):
     for k in range(2):
         assert r1[k]["iterations"] == r0[k]["iterations"], (r1[k], r0[k])
         ref = oracle_solve(eta[k], bcs)
-        bound = 1e-10 if prec == "f64" else 1e-9
-        assert rel(a[k], ref) <= bound
-        assert np.linalg.norm(a[k] - b[k]) <= 1e-9 * np.linalg.norm(b[k])
+        assert_close(a[k], ref, 1e-10, (prec, cfg, k))
+        # both solves are within 1e-10 of the answer
+        assert np.linalg.norm(a[k] - b[k]) <= 2e-10 * np.linalg.norm(b[k])
     plan.close()

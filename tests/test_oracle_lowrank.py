@@ -105,3 +105,24 @@ def test_iteration_ranking_of_experiment_5_5(shape, bcs):
     i_jac = it(JacobiPreconditioner(shape, bcs, 3, 1.3))
     i_cg = it(None)
     assert i_pinv <= 3 < i_lr < i_jac < i_cg, (i_pinv, i_lr, i_jac, i_cg)
+
+
+def test_indefinite_on_a_live_mode():
+    # the low-rank operator can be indefinite away from the null space: on a
+    # 100 x 100 (D, DN) grid the rank-3 approximation of Ghat has a negative
+    # entry at the eigenmode pair (1, 99) (ascending eigenvalues), so that
+    # mode has <v, M v> < 0 and preconditioned CG started on it breaks down
+    # at once (rho_0 < 0); rank 1 stays positive there
+    from pins import lemma_basis
+    n, q, bcs = 100, 100, ("D", "DN")
+    Qn, _ = lemma_basis(n, "D")
+    Qq, _ = lemma_basis(q, "DN")
+    v = np.outer(Qn[:, 1], Qq[:, 99])
+    rq3 = float(np.sum(lowrank_apply(v, lowrank_init((n, q), bcs, 3)) * v))
+    rq1 = float(np.sum(lowrank_apply(v, lowrank_init((n, q), bcs, 1)) * v))
+    assert rq3 < 0.0 < rq1
+    # the same entry of G_r from the SVD of Ghat (Eckart-Young), independently
+    ghat, _, _ = _ghat_closed_form(n, q, bcs)
+    X, sig, Yt = np.linalg.svd(ghat)
+    g3 = (X[:, :3] * sig[:3]) @ Yt[:3]
+    assert abs(g3[1, 99] - rq3) <= 1e-10 * np.abs(g3).max()
