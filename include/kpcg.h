@@ -170,6 +170,26 @@ int kp_apply_laplacian(kp_plan* plan, const double* P, double* W, int batch);
  * is applied.  Uses the plan's workspace.  Enqueue only. */
 int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as kp_apply_pinv with the same kernels and results, but the
+ * intermediate grids of the mode products live in a static device array of
+ * KP_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends; the call allocates nothing (the plan's workspace
+ * is not used or created).  Its address is looked up on the first call on a
+ * device.  Limit: 2 * ceil256(batch * N * e) <= KP_NOALLOC_SCRATCH_BYTES,
+ * e = 8 bytes for F64 and I8X7 plans, 4 for F32 and BF16X6, 2 for BF16
+ * (e.g. 2^22 FP64 unknowns: 256 x 128 x 128, or 128^3 x 2); beyond it the
+ * call returns KP_ENOMEM before any work (kp_last_error says how much was
+ * needed).  The plan's device must be current (KP_EINVAL otherwise).  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other host threads, other streams, plans or processes' streams
+ * still running) race and give wrong results; calls ordered on one stream
+ * are safe.  Enqueue only.  Returns KP_OK, KP_EINVAL, KP_EBUSY, KP_ENOMEM or
+ * KP_EHIP. */
+#define KP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int kp_apply_pinv_noalloc(kp_plan* plan, const double* R, double* Z, int batch);
+
 /* Solves -Delta_FD(u) = eta for `batch` right-hand sides with Algorithm 1
  * from U_0 = 0 (or from the U_0 in u with KP_FLAG_WARM_START) and the
  * pseudoinverse preconditioner (or M = I with KP_FLAG_NO_PRECOND).

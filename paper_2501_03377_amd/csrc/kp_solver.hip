@@ -347,6 +347,34 @@ void clear_graphs(kp_plan* p) {
 
 }  // namespace
 
+// Device scratch of kp_apply_pinv_noalloc, for callers that cannot allocate:
+// the two intermediate grids of the mode products.  Each device the library
+// runs on holds its own copy, at its own address, until the process ends.
+// In host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[KP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+char* g_scratch[kScratchDevices] = {};   // per device: address of its `scratch`
+
+// The current device's copy of `scratch` (dev must be current).
+int noalloc_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kScratchDevices) return KP_EINVAL;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (!ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)))) return KP_EHIP;
+    if (!ptr) return KP_EHIP;
+    g_scratch[dev] = (char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return KP_OK;
+}
+
+}  // namespace
+
 // A solve in flight: the host side of Algorithm 1's outer loop.  The first
 // chunk of iterations (and the exit step) is enqueued at the start; the
 // host then reads the per-RHS done flags once the chunk has finished and
@@ -991,6 +1019,31 @@ int kp_apply_pinv(kp_plan* p, const double* R, double* Z, int batch) {
   char* base = (char*)p->ws;
   TraceScope scope(p);
   pinv_apply(p->op, R, Z, base + L.T0, base + L.T1, batch, nullptr, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int kp_apply_pinv_noalloc(kp_plan* p, const double* R, double* Z, int batch) {
+  if (!p || !R || !Z || batch < 1 || batch > p->max_batch) return KP_EINVAL;
+  if (p->busy) return KP_EBUSY;
+  if (!aligned16(R) || !aligned16(Z)) return KP_EINVAL;
+  if (overlap(R, Z, (size_t)p->g.N * batch * 8)) return KP_EINVAL;
+  // the two intermediate grids of the mode products, back to back
+  const size_t half = align_up((size_t)p->g.N * batch * elem_bytes(p->prec));
+  if (2 * half > (size_t)KP_NOALLOC_SCRATCH_BYTES) {
+    snprintf(t_last_error, sizeof t_last_error,
+             "kp_apply_pinv_noalloc: %zu bytes of scratch needed, the static scratch holds %zu",
+             2 * half, (size_t)KP_NOALLOC_SCRATCH_BYTES);
+    return KP_ENOMEM;
+  }
+  int dev = -1;
+  if (!ok(hipGetDevice(&dev))) return KP_EHIP;
+  if (dev != p->device) return KP_EINVAL;
+  char* base = nullptr;
+  const int rc = noalloc_scratch(dev, &base);
+  if (rc != KP_OK) return rc;
+  (void)hipGetLastError();
+  // no tracer here: its timing events would be created on demand
+  pinv_apply(p->op, R, Z, base, base + half, batch, nullptr, p->stream);
   return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
 }
 

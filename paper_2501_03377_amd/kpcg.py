@@ -50,7 +50,9 @@ EXPORTS = (
     "kp_server_stats_get", "kp_server_destroy", "kp_server_last_error", "kp_last_error",
     "kp_assemble_rhs", "kp_field", "kp_plan_set_preconditioner", "kp_apply_preconditioner",
     "kp_plan_diagnostics", "kp_lowrank_table", "kp_solve_async", "kp_poll", "kp_wait",
+    "kp_apply_pinv_noalloc",
 )
+KP_NOALLOC_SCRATCH_BYTES = 64 << 20
 KERNEL_CLASSES = 18
 
 
@@ -150,6 +152,7 @@ def _load():
         "kp_plan_set_stream": (i, [vp, vp]),
         "kp_apply_laplacian": (i, [vp, vp, vp, i]),
         "kp_apply_pinv": (i, [vp, vp, vp, i]),
+        "kp_apply_pinv_noalloc": (i, [vp, vp, vp, i]),
         "kp_solve": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(KpResult), pd]),
         "kp_solve_async": (i, [vp, vp, vp, i, d, i, i, ctypes.POINTER(KpResult), pd,
                                ctypes.POINTER(vp)]),
@@ -253,6 +256,11 @@ def kp_apply_laplacian(handle, p_ptr, w_ptr, batch):
 
 def kp_apply_pinv(handle, r_ptr, z_ptr, batch):
     return _lib.kp_apply_pinv(handle, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr), batch)
+
+
+def kp_apply_pinv_noalloc(handle, r_ptr, z_ptr, batch):
+    return _lib.kp_apply_pinv_noalloc(handle, ctypes.c_void_p(r_ptr), ctypes.c_void_p(z_ptr),
+                                      batch)
 
 
 def kp_solve(handle, eta_ptr, u_ptr, batch, tol, max_iter, flags, results, hist):
