@@ -78,7 +78,7 @@ WORKLOADS = {
 # record under profiles/ by --ingest-traffic.  Both counters are scaled by
 # what they read for the calibration copy of known size.  The record carries
 # a digest of the kernel sources; once a kernel has changed, traffic is null.
-KERNEL_SOURCES = ("kp_modeprod.hip", "kp_vector.hip", "kp_common.h", "kp_internal.h")
+KERNEL_SOURCES = ("kp_modeprod.hip", "kp_vector.hip", "kp_common.h", "kp_internal.h", "kp_state.h")
 VEC_KERNELS = {"stencil_dot": "kp::k_zm<0>", "update_ur": "kp::k_zm<1>",
                "dot_rz": "kp::k_dot_rz", "update_p": "kp::k_update_p"}
 PRODUCT_ORDER = {3: ("modeprod_x_fwd", "modeprod_y_fwd", "modeprod_z_fwd", "modeprod_x_bwd",

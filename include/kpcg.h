@@ -468,12 +468,17 @@ int kp_plan_graph_count(const kp_plan* plan);
  * eigenvalues of Algs. 4-5, per grid, boundary triple and precision) under an
  * HBM budget, admits a request only when its plan and workspace fit (evicting
  * idle plans least recently used first), and runs `workers` host threads,
- * each with its own HIP stream.  A worker that becomes free takes the oldest
- * queued request together with every queued request of the same plan,
- * tolerance, iteration limit and flags, up to `max_batch`, and solves them as
- * one batch with kp_solve (continuous batching at solve granularity: a slot
- * is refilled as soon as its previous batch completes).  Batched and single
- * solves give bitwise identical results.
+ * each with its own HIP stream.  Continuous batching: a free worker takes the
+ * oldest queued request and opens a batch of `max_batch` slots on that
+ * request's plan; every queued request of the same plan, tolerance,
+ * iteration limit and flags takes a free slot, also while the batch runs:
+ * it starts at the next iteration boundary (its R_0, Z_0 are formed in the
+ * step in which the other slots make an iteration) and leaves the batch, its
+ * answer copied out and its completion posted, at the end of the step in
+ * which its own solve ended.  The batch closes when no slot is busy.  Each
+ * slot runs Algorithm 1 with kp_solve's arithmetic and stopping rules (the
+ * low-mode certificate is tried in every iteration), so a request's result
+ * is bitwise the same alone and in any mix.
  *
  * Timestamps are seconds on the server's monotonic clock (kp_server_now). */
 typedef struct kp_server kp_server;   /* opaque */
@@ -499,14 +504,16 @@ typedef struct {
   int64_t id;
   int32_t status;         /* kp_status of this right-hand side */
   int32_t iterations;
-  int32_t batch;          /* size of the batch it was solved in */
+  int32_t batch;          /* busy slots of its batch when it completed */
   int32_t worker;
   double rel_res, true_rel_res, err_est;
   double t_submit, t_start, t_end;   /* server clock, seconds */
 } kp_completion;
 
 typedef struct {
-  int64_t submitted, completed, batches, plans_created, plans_evicted, rejected;
+  int64_t submitted, completed,
+      batches,            /* continuous batches opened */
+      plans_created, plans_evicted, rejected;
   int32_t plans_cached, queued;
   size_t hbm_used, hbm_high_water, hbm_budget;
 } kp_server_stats;
@@ -518,8 +525,10 @@ typedef struct {
 int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_batch);
 /* Queues a request (the descriptor is copied; eta and u are used later, see
  * kp_request).  Never blocks on the GPU.  Returns KP_OK or KP_EINVAL (bad
- * grid, boundary code, precision, tolerance, flags or null eta; for
- * KP_PREC_I8X7 also an axis that is not a multiple of 16 or exceeds 512). */
+ * grid, boundary code, precision, tolerance or null eta; flags other than
+ * KP_FLAG_NO_PRECOND, KP_FLAG_FLEX_BETA, KP_FLAG_RESIDUAL_ONLY and
+ * KP_FLAG_NO_GRAPH (ignored); for KP_PREC_I8X7 also an axis that is not a
+ * multiple of 16 or exceeds 512). */
 int kp_server_submit(kp_server* srv, const kp_request* req);
 /* Moves up to `max` completions to `out` (host array), waiting up to
  * timeout_s seconds for the first one; returns how many (0 on timeout), or

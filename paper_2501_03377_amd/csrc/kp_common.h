@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "kp_state.h"
 
 namespace kp {
 
@@ -18,46 +19,6 @@ typedef unsigned short u16;
 // Boundary conditions of eq. (3.1).
 enum Bc { BC_P = 0, BC_D = 1, BC_N = 2, BC_DN = 3, BC_ND = 4 };
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X6 = 3, PREC_I8X7 = 4 };
-
-// Termination codes kept per right-hand side on the device.
-enum Done { RUNNING = 0, CONVERGED = 1, BREAKDOWN = 2, NONFINITE = 3, ZERO_RHS = 4 };
-
-// Per right-hand-side scalar state of Algorithm 1, resident on the device so
-// that no iteration needs a host round trip.
-// Delay of the Hestenes-Stiefel error estimate that KP_FLAG_ANORM_STOP uses.
-constexpr int HS_DELAY = 4;
-
-struct RhsState {
-  double h2;          // ||eta_c||^2
-  double mean;        // mean removed from eta (singular operators, eq. 3.6)
-  double rho;         // rho_{s-1} = <R_{s-1}, Z_{s-1}>
-  double alpha;       // alpha_s
-  double beta;        // beta_s
-  double rr;          // ||R_s||^2
-  double rsum;        // sum of the entries of R_s
-  double uu;          // ||U_s||^2
-  double pw;          // <W_s, P_{s-1}>
-  double wsum;        // sum of the entries of W_s
-  double rz;          // <R_s, Z_s> after centering of Z_s
-  double zz;          // ||Z_s||^2 after centering
-  double zmean;       // mean of Z_s (centering, Remark 4.1)
-  double rel_res;     // ||R_s|| / ||eta_c||
-  double err_est;     // ||Z_s|| / ||U_s||
-  double true_rel_res;// ||eta_c - L U|| / ||eta_c|| at exit
-  double umean;       // mean of U removed at exit (singular operators)
-  double scale;       // power-of-two scale applied to the preconditioner input
-  double inv_scale;   // its inverse, applied to the preconditioner output
-  double hs_sum;      // sum of alpha_j rho_{j-1}, j = 1..s (Hestenes-Stiefel terms)
-  double hs_ring[4];  // the last HS_DELAY of those terms, term j at j % HS_DELAY
-  int iter;           // s
-  int done;           // Done code
-  int pinv_count;     // preconditioner applications so far
-  int diag_iter;      // last iterate whose descriptors were recorded (-1: none)
-  int need_cert;      // residual small enough, error bound still to be certified
-  int warm;           // U_0 came from the caller (warm start): kept at exit
-  int pad_;
-  double u0mean;      // mean of U_0 (singular operators: the iterates keep it)
-};
 
 // Reduction slots written by the vector and mode-product kernels, one block
 // partial per slot; reduced in a fixed order for bitwise reproducibility.

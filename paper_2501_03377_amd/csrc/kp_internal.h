@@ -5,6 +5,9 @@
 #include <stdint.h>
 
 #include "kp_common.h"
+#include "kp_slots.h"  // continuous batches (declared for the request server)
+
+struct kp_plan;
 
 namespace kp {
 
@@ -123,8 +126,10 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
 // nonsingular set uses eta itself), U_0 = 0 only when U is not null (the
 // first U/R update takes it as 0 without reading it, the exit step writes it
 // for a right-hand side that made no iteration).
+// slots: a continuous batch (only JOINING right-hand sides start)
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
-                 RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s);
+                 RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s,
+                 int slots = 0);
 // Warm start: R_0 = eta_c - L U_0 with its sums and the stopping rule at
 // s = 0 (after launch_init without R, which gives ||eta_c||).
 void launch_warm(const Geom& g, const double* eta, const double* U, double* R, double* part,
@@ -136,13 +141,20 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
                        double* P, double* part, RhsState* st, int batch, int G, int first,
                        double tol, int flags, hipStream_t s, int Gdot = 0,
                        bool p_written = false);
-// u0: the first iteration of a solve (U_{s-1} = U_0 = 0, not read); r0: if
-// not null, R_{s-1} is read from it (R_0 = eta of a nonsingular set)
+// A right-hand side's first iteration takes U_0 = 0 without reading it
+// (unless it was a warm start); r0: if not null, R_{s-1} is read from it
+// (R_0 = eta of a nonsingular set, in a solve's first iteration).  Right-hand
+// sides without a preconditioned residual yet are skipped.
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, bool u0, const double* r0);
+                      int flags, hipStream_t s, const double* r0);
+// gate: a continuous batch, where only right-hand sides whose solve ended
+// run their exit step, once; the mirror is written for all.
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
-                   RhsState* mirror, int batch, int G, hipStream_t s);
+                   RhsState* mirror, int batch, int G, hipStream_t s, int gate = 0);
+// Slot marks of a continuous batch: slot < 0 empties every slot, else the
+// slot's done code becomes `code` (JOINING or CAPPED).
+void launch_slot_set(RhsState* st, int batch, int slot, int code, hipStream_t s);
 void launch_laplacian(const Geom& g, const double* P, double* W, int batch, int G, hipStream_t s);
 void launch_copy(const Geom& g, const double* src, double* dst, const RhsState* st, int batch,
                  int G, hipStream_t s);

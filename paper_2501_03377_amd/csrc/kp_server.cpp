@@ -1,7 +1,10 @@
 // Request server: a plan cache under an HBM budget, admission control and
-// worker threads that batch queued solves of the same plan (kp_server_* in
-// kpcg.h).  Every solve is kp_solve, i.e. Algorithm 1 with the
-// pseudoinverse preconditioner of Algs. 4-7; this file only schedules them.
+// worker threads that run continuous batches (kp_server_* in kpcg.h).  A
+// worker keeps a batch of max_batch slots running on one plan; a queued
+// request of the same kind takes a free slot at the next iteration boundary
+// and leaves it as soon as its own solve ends.  Every request is Algorithm 1
+// with the pseudoinverse preconditioner of Algs. 4-7, run per slot by the
+// solver (kp_slots.h); this file only schedules.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -16,6 +19,8 @@
 #include <vector>
 
 #include "../../include/kpcg.h"
+#include "kp_budget.h"
+#include "kp_slots.h"
 
 namespace kp {
 std::mutex& api_mutex();   // kp_solver.hip: serialises allocations with graph capture
@@ -68,14 +73,12 @@ struct Worker {
   void* ws = nullptr;         // solver workspace shared by this worker's plans
   size_t ws_bytes = 0;
   int64_t ws_epoch = 0;       // bumped whenever ws is reallocated
-  std::vector<kp_result> res;
 };
 
 }  // namespace
 
 struct kp_server {
   int device = 0;
-  size_t budget = 0;
   int max_batch = 1;
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
@@ -85,7 +88,7 @@ struct kp_server {
   std::deque<kp_completion> done;
   std::vector<PlanEntry*> plans;
   std::vector<Worker> workers;
-  size_t used = 0, high = 0;
+  kp::Budget mem;          // plans, workspaces and staging against the budget
   int running = 0;        // workers holding a plan for a batch
   uint64_t tick = 0;
   kp_server_stats st{};
@@ -123,10 +126,7 @@ void complete(kp_server* s, const Pending& p, int status, const kp_result* res, 
   if (status == KP_ENOMEM) s->st.rejected += 1;
 }
 
-void account(kp_server* s, long long delta) {
-  s->used = (size_t)((long long)s->used + delta);
-  s->high = std::max(s->high, s->used);
-}
+void account(kp_server* s, long long delta) { s->mem.add(delta); }
 
 // Frees idle plans, least recently used first, until `need` more bytes fit the
 // budget.  Called with the lock held; returns the plans to destroy (after
@@ -134,8 +134,7 @@ void account(kp_server* s, long long delta) {
 std::vector<kp_plan*> make_room(kp_server* s, size_t need, bool* fits) {
   std::vector<kp_plan*> victims;
   *fits = true;
-  if (s->budget == 0) return victims;
-  while (s->used + need > s->budget) {
+  while (!s->mem.fits(need)) {
     PlanEntry* lru = nullptr;
     for (PlanEntry* e : s->plans)
       if (!e->busy && (!lru || e->last < lru->last)) lru = e;
@@ -154,29 +153,29 @@ void destroy_plans(std::vector<kp_plan*>& v) {
   v.clear();
 }
 
+// Status of a slot whose solve has ended.
+int slot_status(const kp::RhsState& x) {
+  switch (x.done) {
+    case kp::CONVERGED: case kp::ZERO_RHS: return KP_OK;
+    case kp::BREAKDOWN: return KP_EBREAKDOWN;
+    case kp::NONFINITE: return KP_ENONFINITE;
+    default: return KP_NOT_CONVERGED;
+  }
+}
+
 void worker_main(kp_server* s, int w) {
   (void)hipSetDevice(s->device);
   Worker& me = s->workers[w];
-  me.res.resize(s->max_batch);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
     if (s->queue.empty()) break;   // stopping and drained
 
-    // the oldest request and every queued request that can share its solve
-    std::vector<Pending> batch;
-    batch.push_back(s->queue.front());
+    // the oldest request opens a continuous batch of its kind
+    std::vector<Pending> incoming;
+    incoming.push_back(s->queue.front());
     s->queue.pop_front();
-    for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < s->max_batch;) {
-      if (same_batch(it->r, batch[0].r)) {
-        batch.push_back(*it);
-        it = s->queue.erase(it);
-      } else {
-        ++it;
-      }
-    }
-    const int b = (int)batch.size();
-    const kp_request& r0 = batch[0].r;
+    const kp_request r0 = incoming[0].r;
     const PlanKey key = key_of(r0);
     const size_t vb = vec_bytes(r0);
     const size_t stage_need = 2 * vb * (size_t)s->max_batch;
@@ -248,7 +247,7 @@ void worker_main(kp_server* s, int w) {
       destroy_plans(victims);
       lk.lock();
       const double t = s->now();
-      for (const Pending& p : batch) complete(s, p, fail, nullptr, b, w, t, t);
+      complete(s, incoming[0], fail, nullptr, 1, w, t, t);
       s->cv_done.notify_all();
       s->cv_work.notify_all();
       continue;
@@ -256,29 +255,43 @@ void worker_main(kp_server* s, int w) {
     entry->last = ++s->tick;
     s->running += 1;
     s->st.batches += 1;
+    // the first requests of the batch: every queued one of the same kind
+    for (auto it = s->queue.begin(); it != s->queue.end() && (int)incoming.size() < s->max_batch;) {
+      if (same_batch(it->r, r0)) {
+        incoming.push_back(*it);
+        it = s->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
     lk.unlock();
     destroy_plans(victims);
 
-    // ---- run the batch on this worker's stream (no lock held) ----
-    const double t_start = s->now();
+    // ---- buffers of this worker (no lock held; accounting under it) ----
     int rc = KP_OK;
-    const char* failed = nullptr;   // failing step outside kp_solve
+    const char* failed = nullptr;   // failing step
     if (me.stage_bytes < stage_need) {
       std::lock_guard<std::mutex> alk(kp::api_mutex());
       if (me.stage) (void)hipFree(me.stage);
       me.stage = nullptr;
-      me.stage_bytes = 0;
-      if (hipMalloc((void**)&me.stage, stage_need) == hipSuccess) me.stage_bytes = stage_need;
-      else { rc = KP_ENOMEM; failed = "hipMalloc of the batch staging buffer"; }
+      const bool okm = hipMalloc((void**)&me.stage, stage_need) == hipSuccess;
+      {
+        std::lock_guard<std::mutex> mlk(s->mu);
+        me.stage_bytes = kp::regrow(s->mem, me.stage_bytes, stage_need, okm);
+      }
+      if (!okm) { me.stage = nullptr; rc = KP_ENOMEM; failed = "hipMalloc of the slot buffers"; }
     }
     if (rc == KP_OK && me.ws_bytes < ws_need) {
       std::lock_guard<std::mutex> alk(kp::api_mutex());
       if (me.ws) (void)hipFree(me.ws);
       me.ws = nullptr;
-      me.ws_bytes = 0;
       me.ws_epoch += 1;
-      if (hipMalloc(&me.ws, ws_need) == hipSuccess) me.ws_bytes = ws_need;
-      else { rc = KP_ENOMEM; failed = "hipMalloc of the worker workspace"; }
+      const bool okm = hipMalloc(&me.ws, ws_need) == hipSuccess;
+      {
+        std::lock_guard<std::mutex> mlk(s->mu);
+        me.ws_bytes = kp::regrow(s->mem, me.ws_bytes, ws_need, okm);
+      }
+      if (!okm) { me.ws = nullptr; rc = KP_ENOMEM; failed = "hipMalloc of the worker workspace"; }
     }
     if (rc == KP_OK && entry->ws_epoch != me.ws_epoch) {
       // rebinding drops the plan's captured graphs (they point into the old buffer)
@@ -289,56 +302,110 @@ void worker_main(kp_server* s, int w) {
     const size_t n = vb / sizeof(double);
     double* eta_b = me.stage;
     double* u_b = me.stage + n * (size_t)s->max_batch;
-    const double* eta = eta_b;
     if (rc == KP_OK) {
       kp_plan_set_stream(entry->plan, me.stream);
-      if (b == 1 && r0.mem == KP_MEM_DEVICE) {
-        eta = r0.eta;      // read in place
-      } else {
-        for (int i = 0; i < b && rc == KP_OK; ++i) {
-          const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyHostToDevice
-                                                                : hipMemcpyDeviceToDevice;
-          if (hipMemcpyAsync(eta_b + n * i, batch[i].r.eta, vb, k, me.stream) != hipSuccess) {
-            rc = KP_EHIP;
-            failed = "hipMemcpyAsync of a right-hand side";
-          }
-        }
-      }
+      rc = kp::slots_open(entry->plan, eta_b, u_b, r0.tol, r0.flags & ~KP_FLAG_NO_GRAPH);
+      if (rc != KP_OK) failed = "slots_open";
     }
-    if (rc == KP_OK) {
-      // the solution always goes to the worker's buffer, so captured
-      // iteration graphs are reused from batch to batch
-      rc = kp_solve(entry->plan, eta, u_b, b, r0.tol, r0.max_iter, r0.flags & ~KP_FLAG_NO_GRAPH,
-                    me.res.data(), nullptr);
-      if (rc >= 0) {
-        for (int i = 0; i < b; ++i) {
-          if (!batch[i].r.u) continue;
-          const hipMemcpyKind k = batch[i].r.mem == KP_MEM_HOST ? hipMemcpyDeviceToHost
-                                                                : hipMemcpyDeviceToDevice;
-          if (hipMemcpyAsync(batch[i].r.u, u_b + n * i, vb, k, me.stream) != hipSuccess) {
-            rc = KP_EHIP;
-            failed = "hipMemcpyAsync of a solution";
-          }
-        }
-        if (hipStreamSynchronize(me.stream) != hipSuccess) {
+
+    // ---- the continuous batch: steps until no slot is busy ----
+    std::vector<Pending> req(s->max_batch);
+    std::vector<char> busy(s->max_batch, 0);
+    std::vector<double> t_start(s->max_batch, 0.0);
+    int active = 0;
+    std::vector<int> fin;
+    for (;;) {
+      // newcomers take free slots; they start at this step
+      for (const Pending& p : incoming) {
+        int slot = 0;
+        while (busy[slot]) ++slot;
+        req[slot] = p;
+        busy[slot] = 1;
+        active += 1;
+        t_start[slot] = s->now();
+        if (rc != KP_OK) continue;
+        const hipMemcpyKind k =
+            p.r.mem == KP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+        if (hipMemcpyAsync(eta_b + n * slot, p.r.eta, vb, k, me.stream) != hipSuccess) {
           rc = KP_EHIP;
-          failed = "hipStreamSynchronize after the solution copies";
+          failed = "hipMemcpyAsync of a right-hand side";
+        } else if ((rc = kp::slots_mark(entry->plan, slot, kp::JOINING)) != KP_OK) {
+          failed = "slots_mark";
         }
       }
+      incoming.clear();
+      if (active == 0) break;
+      const kp::RhsState* m = nullptr;
+      if (rc == KP_OK && (rc = kp::slots_step(entry->plan)) != KP_OK) failed = "slots_step";
+      if (rc == KP_OK && !(m = kp::slots_wait(entry->plan))) {
+        rc = KP_EHIP;
+        failed = "slots_wait";
+      }
+      // slots whose solve ended (with their exit step) leave; their answers
+      // are copied out before the completion is posted
+      fin.clear();
+      for (int slot = 0; slot < s->max_batch && rc == KP_OK; ++slot) {
+        if (!busy[slot]) continue;
+        const kp::RhsState& x = m[slot];
+        if (kp::terminal(x.done) && x.exit_gen == 2) {
+          fin.push_back(slot);
+          const kp_request& r = req[slot].r;
+          if (r.u) {
+            const hipMemcpyKind k =
+                r.mem == KP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+            if (hipMemcpyAsync(r.u, u_b + n * slot, vb, k, me.stream) != hipSuccess) {
+              rc = KP_EHIP;
+              failed = "hipMemcpyAsync of a solution";
+            }
+          }
+        } else if (x.done == kp::RUNNING && x.iter >= r0.max_iter) {
+          if ((rc = kp::slots_mark(entry->plan, slot, kp::CAPPED)) != KP_OK)
+            failed = "slots_mark";
+        }
+      }
+      if (rc == KP_OK && !fin.empty() && hipStreamSynchronize(me.stream) != hipSuccess) {
+        rc = KP_EHIP;
+        failed = "hipStreamSynchronize after the solution copies";
+      }
+      lk.lock();
+      const double t_end = s->now();
+      if (rc != KP_OK) {
+        // every request still in the batch fails; no newcomer joins
+        snprintf(s->last_error, sizeof s->last_error, "continuous batch on worker %d: %s (%s)",
+                 w, failed ? failed : "?", kp_last_error());
+        for (int slot = 0; slot < s->max_batch; ++slot)
+          if (busy[slot]) complete(s, req[slot], rc, nullptr, active, w, t_start[slot], t_end);
+        s->cv_done.notify_all();
+        lk.unlock();
+        break;
+      }
+      for (int slot : fin) {
+        const kp::RhsState& x = m[slot];
+        kp_result res{};
+        res.iterations = x.iter;
+        res.rel_res = x.rel_res;
+        res.true_rel_res = x.true_rel_res;
+        res.err_est = x.err_est;
+        complete(s, req[slot], slot_status(x), &res, active, w, t_start[slot], t_end);
+        busy[slot] = 0;
+        active -= 1;
+      }
+      if (!fin.empty()) s->cv_done.notify_all();
+      // queued requests of the same kind take the free slots
+      for (auto it = s->queue.begin();
+           it != s->queue.end() && active + (int)incoming.size() < s->max_batch;) {
+        if (same_batch(it->r, r0)) {
+          incoming.push_back(*it);
+          it = s->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      lk.unlock();
     }
-    const double t_end = s->now();
-    char why[256] = "";
-    if (rc < 0)
-      snprintf(why, sizeof why, "batch of %d on worker %d: %s (status %d)", b, w,
-               failed ? failed : kp_last_error(), rc);
+    if (entry->plan) kp::slots_close(entry->plan);
 
     lk.lock();
-    if (why[0]) std::memcpy(s->last_error, why, sizeof why);
-    for (int i = 0; i < b; ++i) {
-      const bool per_rhs = rc >= 0;
-      complete(s, batch[i], per_rhs ? me.res[i].status : rc, per_rhs ? &me.res[i] : nullptr, b,
-               w, t_start, t_end);
-    }
     entry->busy = false;
     entry->last = ++s->tick;
     s->running -= 1;
@@ -380,7 +447,7 @@ int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_ba
   *out = nullptr;
   kp_server* s = new kp_server();
   if (hipGetDevice(&s->device) != hipSuccess) { delete s; return KP_EHIP; }
-  s->budget = hbm_budget;
+  s->mem.limit = hbm_budget;
   s->max_batch = max_batch;
   s->t0 = std::chrono::steady_clock::now();
   s->workers.resize(workers);
@@ -431,9 +498,9 @@ int kp_server_stats_get(kp_server* s, kp_server_stats* out) {
   *out = s->st;
   out->plans_cached = (int32_t)s->plans.size();
   out->queued = (int32_t)s->queue.size();
-  out->hbm_used = s->used;
-  out->hbm_high_water = s->high;
-  out->hbm_budget = s->budget;
+  out->hbm_used = s->mem.used;
+  out->hbm_high_water = s->mem.high;
+  out->hbm_budget = s->mem.limit;
   return KP_OK;
 }
 

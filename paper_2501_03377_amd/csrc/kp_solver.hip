@@ -151,6 +151,13 @@ struct kp_plan {
   } small_last;
   double* lr_dev = nullptr;           // G_r of the low-rank preconditioner, [ny][nx] (2D)
   int lr_rank = 0;                    // its rank (0: not built)
+  struct {                            // continuous batch (the request server)
+    bool open = false;
+    const double* eta = nullptr;      // max_batch slots of eta and u, caller-owned
+    double* u = nullptr;
+    double tol = 0.0;
+    int flags = 0;
+  } slot;
 };
 
 namespace {
@@ -479,7 +486,7 @@ struct SolveRun {
   void iteration_head(bool first_iter, bool with_cert) {
     const bool u0 = first_iter && !t->warm;
     launch_iter_head(p->g, P, W, R, t->u, part, st, p->hist_dev, t->hs, t->batch, G, t->tol,
-                     t->flags, s, u0, (u0 && !p->g.singular) ? t->eta : nullptr);
+                     t->flags, s, (u0 && !p->g.singular) ? t->eta : nullptr);
     if (t->diag) launch_diag(p->g, t->eta, t->u, part, st, diag_dev, t->hs, t->batch, s);
     if (t->cert && with_cert)
       launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
@@ -753,6 +760,107 @@ int solve_advance(kp_ticket* t, bool block) {
 }
 
 }  // namespace
+
+// ------------------------------------------------- continuous batches ----
+// The request server keeps one batch of max_batch slots running on a plan:
+// every slot is a right-hand side at its own stage of Algorithm 1 (or empty).
+// Each step is one iteration for the running slots, the start (R_0, Z_0,
+// rho_0, P_0) for slots that joined since the last step, and the exit step
+// (true residual, centring) for slots whose solve ended in it.  All of it
+// is the same arithmetic per right-hand side as kp_solve's, with the
+// low-mode certificate tried in every iteration, so a slot's result does not
+// depend on the other slots, on when it joined or on the slot it took.
+namespace kp {
+
+int slots_open(kp_plan* p, const double* eta, double* u, double tol, int flags) {
+  if (!p || !eta || !u || !(tol > 0.0) || p->busy) return KP_EINVAL;
+  // (small 2D plans run the general kernels here too, not the one-kernel solve)
+  if (p->pc_kind != KP_PRECOND_PINV) return KP_EINVAL;
+  if (flags & ~(KP_FLAG_NO_PRECOND | KP_FLAG_FLEX_BETA | KP_FLAG_RESIDUAL_ONLY)) return KP_EINVAL;
+  int rc = ensure_workspace(p);
+  if (rc != KP_OK) return rc;
+  if (flags & KP_FLAG_NO_PRECOND) flags |= KP_FLAG_RESIDUAL_ONLY;
+  if (!(flags & KP_FLAG_RESIDUAL_ONLY)) flags |= F_CERT;
+  p->slot.open = true;
+  p->slot.eta = eta;
+  p->slot.u = u;
+  p->slot.tol = tol;
+  p->slot.flags = flags;
+  const Layout L = layout_for(p, p->max_batch);
+  (void)hipGetLastError();
+  launch_slot_set((RhsState*)((char*)p->ws + L.st), p->max_batch, -1, IDLE, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+int slots_mark(kp_plan* p, int slot, int code) {
+  if (!p || !p->slot.open || slot < 0 || slot >= p->max_batch) return KP_EINVAL;
+  const Layout L = layout_for(p, p->max_batch);
+  launch_slot_set((RhsState*)((char*)p->ws + L.st), p->max_batch, slot, code, p->stream);
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+// Enqueues one step on the plan's private stream after the plan's stream
+// (where the slots' right-hand sides were staged and marked), as one
+// captured graph where possible.
+int slots_step(kp_plan* p) {
+  if (!p || !p->slot.open) return KP_EINVAL;
+  kp_ticket t;
+  t.p = p;
+  t.eta = p->slot.eta;
+  t.u = p->slot.u;
+  t.batch = p->max_batch;
+  t.tol = p->slot.tol;
+  t.flags = p->slot.flags;
+  t.hs = 1;
+  t.cert = (t.flags & F_CERT) != 0;
+  SolveRun run(&t);
+  run.R0 = run.R;   // every slot's R_0 = eta_c is stored
+  auto body = [&]() {
+    launch_init(p->g, t.eta, run.R, nullptr, run.part, run.st, nullptr, 0, t.batch, run.G,
+                run.s, 1);
+    launch_iter_head(p->g, run.P, run.W, run.R, t.u, run.part, run.st, nullptr, 0, t.batch,
+                     run.G, t.tol, t.flags, run.s, nullptr);
+    if (t.cert)
+      launch_cert(p->g, p->cert, run.R, (double*)(run.base + run.L.C1),
+                  (double*)(run.base + run.L.C2), (double*)(run.base + run.L.C3), run.st,
+                  t.batch, t.tol, run.s);
+    const int Gdot = precondition(p, run.L, run.R, run.Z, t.batch, t.flags, run.st, run.s,
+                                  run.part);
+    launch_after_pinv(p->g, run.R, run.Z, run.W, run.P, run.part, run.st, t.batch, run.G, 0,
+                      t.tol, t.flags, run.s, Gdot, false);
+    launch_finish(p->g, t.eta, t.u, run.part, run.st, p->st_dev, t.batch, run.G, run.s, 1);
+  };
+  (void)hipGetLastError();
+  if (!ok(hipEventRecord(p->ev_in, p->stream)) || !ok(hipStreamWaitEvent(run.s, p->ev_in, 0)))
+    return KP_EHIP;
+  TraceScope scope(p);
+  bool launched = false;
+  if (p->graphs_ok && !p->profiling) {
+    const kp_plan::GraphKey key{2, t.batch, 0, t.flags, 1, t.tol, t.u, nullptr, nullptr, t.eta};
+    const int gi = run.graph_for(key, body);
+    if (gi >= 0) {
+      if (!ok(hipGraphLaunch(p->graphs[gi].exec, run.s))) return KP_EHIP;
+      launched = true;
+    }
+  }
+  if (!launched) body();
+  return ok(hipGetLastError()) ? KP_OK : KP_EHIP;
+}
+
+// Waits for the last step; the slots' states (max_batch entries) are then
+// in the host mirror.
+const RhsState* slots_wait(kp_plan* p) {
+  if (!p || !p->slot.open) return nullptr;
+  if (!ok(hipStreamSynchronize(p->own))) return nullptr;
+  if (p->profiling) p->tracer.collect();
+  return p->st_host;
+}
+
+void slots_close(kp_plan* p) {
+  if (p) p->slot.open = false;
+}
+
+}  // namespace kp
 
 extern "C" {
 

@@ -82,9 +82,13 @@ __device__ __forceinline__ void set_scale(RhsState& s, double sq, double N) {
 }
 
 // ----------------------------------------------------------------- init ----
+// slots: a continuous batch, where only JOINING right-hand sides start (the
+// others are left as they are); otherwise every right-hand side starts.
 __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict__ eta,
-                                                double* part, int G) {
+                                                double* part, int G, const RhsState* st,
+                                                int slots) {
   const int rhs = blockIdx.y;
+  if (slots && st[rhs].done != JOINING) return;
   const double* e = eta + (int64_t)rhs * g.N;
   double v[1] = {0.0};
 #pragma unroll 4
@@ -93,8 +97,10 @@ __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict
   write_partials<1>(v, sl, part, rhs, blockIdx.x);
 }
 
-__global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, RhsState* st, int G) {
+__global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, RhsState* st, int G,
+                                                 int slots) {
   const int rhs = blockIdx.x;
+  if (slots && st[rhs].done != JOINING) return;
   double v[1] = {0.0};
   const int sl[1] = {S_SUM};
   if (g.singular) read_partials<1>(part, rhs, sl, G, v);   // no mean to remove otherwise
@@ -107,10 +113,18 @@ __global__ __launch_bounds__(VT) void k_fin_mean(Geom g, const double* part, Rhs
   }
 }
 
+// A right-hand side that started in this launch sequence (state reset, no
+// preconditioner application yet).
+__device__ __forceinline__ bool fresh(const RhsState& s) {
+  return s.done == RUNNING && s.pinv_count == 0 && s.iter == 0;
+}
+
 __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restrict__ eta,
                                                    double* __restrict__ R, double* __restrict__ U,
-                                                   double* part, const RhsState* st, int G) {
+                                                   double* part, const RhsState* st, int G,
+                                                   int slots) {
   const int rhs = blockIdx.y;
+  if (slots && !fresh(st[rhs])) return;
   const int64_t off = (int64_t)rhs * g.N;
   const double m = st[rhs].mean;
   double v[2] = {0.0, 0.0};
@@ -128,8 +142,9 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
 }
 
 __global__ __launch_bounds__(VT) void k_fin_h(Geom g, const double* part, RhsState* st,
-                                              double* hist, int hist_stride, int G) {
+                                              double* hist, int hist_stride, int G, int slots) {
   const int rhs = blockIdx.x;
+  if (slots && !fresh(st[rhs])) return;
   double v[2];
   const int sl[2] = {S_SUM, S_SQ};
   read_partials<2>(part, rhs, sl, G, v);
@@ -182,6 +197,9 @@ __global__ __launch_bounds__(VT) void k_fin_rho(Geom g, const double* part, RhsS
   read_partials<4>(part, rhs, sl, G, v);
   if (threadIdx.x != 0) return;
   RhsState& s = st[rhs];
+  // the first application of this right-hand side's solve (in a continuous
+  // batch it may come while other right-hand sides iterate)
+  first = first || s.pinv_count == 0;
   const double N = (double)g.N;
   const double zmean = g.singular ? v[1] / N : 0.0;        // Remark 4.1
   const double rz = v[0] - zmean * s.rsum;                 // <R, Z - mean>
@@ -220,7 +238,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
   if (st[rhs].done) return;
   const int64_t off = (int64_t)rhs * g.N;
   const double zm = st[rhs].zmean, b = st[rhs].beta;
-  if (first) {
+  if (first || st[rhs].iter == 0) {   // P_0 = Z_0 (a right-hand side that just started)
   #pragma unroll 4
   for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT)
       P[off + i] = Z[off + i] - zm;
@@ -306,7 +324,8 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 
 // ZM_PW:   partials <L P, P>, sum L P; W = L P stored when W != nullptr
 // ZM_UR:   U += alpha P, R -= alpha L P; partials sum R, ||R||^2, ||U||^2;
-//          with u0 the previous U is 0 (the first iteration) and is not read;
+//          in a right-hand side's first iteration the previous U is 0 and is
+//          not read (unless a warm start supplied it);
 //          with eta the previous R is read from eta (R_0 of a nonsingular set)
 // ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U; a right-hand
 //          side that made no iteration has U = 0, which is written to U here
@@ -327,11 +346,18 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
                                            double* __restrict__ W, double* __restrict__ R,
                                            double* __restrict__ U, const double* __restrict__ eta,
                                            double* part, const RhsState* st, double omega,
-                                           int u0) {
+                                           int gate) {
   const int rhs = blockIdx.y;
   if (MODE == ZM_DIAG) {
     if (st[rhs].iter <= st[rhs].diag_iter) return;
-  } else if (MODE != ZM_TRUE && MODE != ZM_LAP && st && st[rhs].done) {
+  } else if (MODE == ZM_TRUE) {
+    // exit step; with `gate`, only right-hand sides whose solve ended and
+    // whose exit step has not run
+    if (gate && !(terminal(st[rhs].done) && st[rhs].exit_gen == 0)) return;
+  } else if (MODE != ZM_LAP && st && (st[rhs].done || (MODE != ZM_JAC && MODE != ZM_RES &&
+                                                       st[rhs].pinv_count == 0))) {
+    // (an iteration needs the right-hand side's first preconditioned
+    // residual: a continuous batch starts requests between iterations)
     return;
   }
   const int b = blockIdx.x;
@@ -366,6 +392,9 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   const bool uz = MODE == ZM_TRUE && st[rhs].iter == 0 && !st[rhs].warm;
   const double* p = (uz ? eta : P) + off;
   const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
+  // U/R update of a right-hand side's first iteration: U_0 = 0 is not read
+  // (unless a warm start supplied it)
+  const bool ufirst = MODE == ZM_UR && st[rhs].iter == 0 && !st[rhs].warm;
   const double mean =
       (MODE == ZM_TRUE || MODE == ZM_DIAG || MODE == ZM_RES) ? st[rhs].mean : 0.0;
   const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
@@ -397,7 +426,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
       const int64_t idx = off + base + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
       if (MODE == ZM_UR) {
         a[r] = eta ? eta[idx] : R[idx];   // R_0 = eta (nonsingular) is never stored
-        b[r] = u0 ? 0.0 : U[idx];
+        b[r] = ufirst ? 0.0 : U[idx];
       } else if (MODE == ZM_JAC) {
         a[r] = R[idx];
       } else {
@@ -570,7 +599,7 @@ bool zgrid_fits(const Geom& g) { return zgrid_for(g).nblocks <= GMAX; }
 
 __global__ __launch_bounds__(VT) void k_fin_alpha(Geom g, const double* part, RhsState* st, int G) {
   const int rhs = blockIdx.x;
-  if (st[rhs].done) return;
+  if (st[rhs].done || st[rhs].pinv_count == 0) return;   // as the stencil pass
   double v[2];
   const int sl[2] = {S_DOT, S_SUM};
   read_partials<2>(part, rhs, sl, G, v);
@@ -592,7 +621,7 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
                                                 double* hist, int hist_stride, int G, double tol,
                                                 int flags) {
   const int rhs = blockIdx.x;
-  if (st[rhs].done) return;
+  if (st[rhs].done || st[rhs].pinv_count == 0) return;   // as the U/R update
   double v[3];
   const int sl[3] = {S_SUM, S_SQ, S_AUX};
   read_partials<3>(part, rhs, sl, G, v);
@@ -668,17 +697,48 @@ __global__ __launch_bounds__(VT) void k_fin_warm(Geom g, const double* part, Rhs
 }
 
 // --------------------------------------------------------------- finish ----
+// gate: a continuous batch, where only right-hand sides whose solve ended
+// and whose exit step is due are processed (exit_gen 0 -> 1); the host
+// mirror is written for every right-hand side either way.
 __global__ __launch_bounds__(VT) void k_fin_true(Geom g, const double* part, RhsState* st, int G,
-                                                 RhsState* mirror) {
+                                                 RhsState* mirror, int gate) {
   const int rhs = blockIdx.x;
-  double v[2];
+  const bool run = !gate || (terminal(st[rhs].done) && st[rhs].exit_gen == 0);
+  double v[2] = {0.0, 0.0};
   const int sl[2] = {S_SQ, S_SUM};
-  read_partials<2>(part, rhs, sl, G, v);
+  if (run) read_partials<2>(part, rhs, sl, G, v);
   if (threadIdx.x != 0) return;
   RhsState& s = st[rhs];
-  s.true_rel_res = s.h2 > 0.0 ? sqrt(v[0] / s.h2) : 0.0;
-  s.umean = g.singular ? v[1] / (double)g.N : 0.0;
+  if (run) {
+    s.true_rel_res = s.h2 > 0.0 ? sqrt(v[0] / s.h2) : 0.0;
+    s.umean = g.singular ? v[1] / (double)g.N : 0.0;
+    if (gate) s.exit_gen = g.singular ? 1 : 2;   // centring of U still due, or done
+  }
   if (mirror) mirror[rhs] = s;   // host-mapped copy read after the stream sync
+}
+
+// gated exit of a singular set: the centring of U has run (exit_gen 1 -> 2)
+__global__ void k_exit_done(RhsState* st, RhsState* mirror, int batch) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= batch || st[rhs].exit_gen != 1) return;
+  st[rhs].exit_gen = 2;
+  if (mirror) mirror[rhs] = st[rhs];
+}
+
+// Empties every slot of a continuous batch, or marks one slot (JOINING: a
+// request starts at the next step; CAPPED: stop at the iteration limit).
+__global__ void k_slot_set(RhsState* st, int batch, int slot, int code) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= batch) return;
+  if (slot < 0) {
+    RhsState s = {};
+    s.done = IDLE;
+    s.exit_gen = 2;
+    st[rhs] = s;
+  } else if (rhs == slot) {
+    st[rhs].done = code;
+    if (code == CAPPED) st[rhs].exit_gen = 0;
+  }
 }
 
 // Z = R for M = I (a kernel rather than a device copy, so that it can sit in
@@ -694,8 +754,9 @@ __global__ __launch_bounds__(VT) void k_copy(Geom g, const double* __restrict__ 
 }
 
 __global__ __launch_bounds__(VT) void k_center_u(Geom g, double* __restrict__ U, const RhsState* st,
-                                                 int G) {
+                                                 int G, int gate) {
   const int rhs = blockIdx.y;
+  if (gate && st[rhs].exit_gen != 1) return;
   const int64_t off = (int64_t)rhs * g.N;
   const double m = st[rhs].umean;
 #pragma unroll 4
@@ -715,21 +776,25 @@ int vec_blocks(int64_t N, int batch) {
 }
 
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
-                 RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s) {
+                 RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s,
+                 int slots) {
   dim3 grid(G, batch);
   if (g.singular) {   // the mean of eta (eq. 3.6); a nonsingular set keeps eta as it is
     trace_begin(KC_INIT, s);
-    hipLaunchKernelGGL(k_eta_sum, grid, dim3(VT), 0, s, g, eta, part, G);
+    hipLaunchKernelGGL(k_eta_sum, grid, dim3(VT), 0, s, g, eta, part, G, (const RhsState*)st,
+                       slots);
     trace_end(KC_INIT, s);
   }
   trace_begin(KC_FINALIZE, s);
-  hipLaunchKernelGGL(k_fin_mean, dim3(batch), dim3(VT), 0, s, g, part, st, G);
+  hipLaunchKernelGGL(k_fin_mean, dim3(batch), dim3(VT), 0, s, g, part, st, G, slots);
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_INIT, s);
-  hipLaunchKernelGGL(k_eta_center, grid, dim3(VT), 0, s, g, eta, R, U, part, st, G);
+  hipLaunchKernelGGL(k_eta_center, grid, dim3(VT), 0, s, g, eta, R, U, part, (const RhsState*)st,
+                     G, slots);
   trace_end(KC_INIT, s);
   trace_begin(KC_FINALIZE, s);
-  hipLaunchKernelGGL(k_fin_h, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, G);
+  hipLaunchKernelGGL(k_fin_h, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, G,
+                     slots);
   trace_end(KC_FINALIZE, s);
 }
 
@@ -770,7 +835,7 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, bool u0, const double* r0) {
+                      int flags, hipStream_t s, const double* r0) {
   const ZGrid z = zgrid_for(g);
   const int Gz = z.nblocks;
   dim3 zgrid(z.nblocks, batch);
@@ -785,7 +850,7 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
   trace_end(KC_FINALIZE, s);
   trace_begin(KC_UPDATE_UR, s);
   hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
-                     R, U, r0, part, (const RhsState*)st, 0.0, u0 ? 1 : 0);
+                     R, U, r0, part, (const RhsState*)st, 0.0, 0);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,
@@ -795,16 +860,25 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
 }
 
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,
-                   RhsState* mirror, int batch, int G, hipStream_t s) {
+                   RhsState* mirror, int batch, int G, hipStream_t s, int gate) {
   const ZGrid z = zgrid_for(g);
   const int Gz = z.nblocks;
   trace_begin(KC_FINISH, s);
   hipLaunchKernelGGL(k_zm<ZM_TRUE>, dim3(z.nblocks, batch), dim3(VT), 0, s, g, z,
                      (const double*)U, (double*)nullptr, (double*)nullptr, U, eta, part,
-                     (const RhsState*)st, 0.0, 0);
-  hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, Gz, mirror);
-  if (g.singular) hipLaunchKernelGGL(k_center_u, dim3(G, batch), dim3(VT), 0, s, g, U, st, G);
+                     (const RhsState*)st, 0.0, gate);
+  hipLaunchKernelGGL(k_fin_true, dim3(batch), dim3(VT), 0, s, g, part, st, Gz, mirror, gate);
+  if (g.singular) {
+    hipLaunchKernelGGL(k_center_u, dim3(G, batch), dim3(VT), 0, s, g, U, (const RhsState*)st, G,
+                       gate);
+    if (gate)
+      hipLaunchKernelGGL(k_exit_done, dim3((batch + 63) / 64), dim3(64), 0, s, st, mirror, batch);
+  }
   trace_end(KC_FINISH, s);
+}
+
+void launch_slot_set(RhsState* st, int batch, int slot, int code, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_set, dim3((batch + 63) / 64), dim3(64), 0, s, st, batch, slot, code);
 }
 
 void launch_copy(const Geom& g, const double* src, double* dst, const RhsState* st, int batch,
@@ -1191,6 +1265,8 @@ __global__ void k_timing_states(RhsState* st, int batch) {
   s.scale = 1.0;
   s.inv_scale = 1.0;
   s.done = RUNNING;
+  s.iter = 1;          // an iteration past the first (reads U)
+  s.pinv_count = 1;
   st[b] = s;
 }
 

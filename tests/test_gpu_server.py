@@ -140,3 +140,84 @@ def test_server_int8_split_requests():
         assert srv.stats()["completed"] == len(cases)
     finally:
         srv.close()
+
+
+def test_requests_join_a_running_batch_and_leave_on_their_own():
+    # continuous batching: plain CG (hundreds of iterations); requests of the
+    # same kind submitted while the first is being solved take free slots at
+    # the next iteration boundary, before the first has finished, and each
+    # leaves when its own solve ends.  Every result is bitwise that of the
+    # same request alone and matches the oracle.
+    import time
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_NO_PRECOND, Server
+    shape, bcs = (32, 32, 32), ("D", "N", "D")
+    etas = [synth.charge_field(shape, ncharges=60, seed=1700 + k) for k in range(3)]
+    kw = dict(tol=1e-12, prec="f64", flags=KP_FLAG_NO_PRECOND, max_iter=3000)
+    srv = Server(hbm_budget=0, workers=1, max_batch=4)
+    try:
+        us = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        srv.submit(0, to_dev(etas[0]), bcs, u=us[0], **kw)
+        time.sleep(0.005)
+        for k in (1, 2):
+            srv.submit(k, to_dev(etas[k]), bcs, u=us[k], **kw)
+        done = _drain(srv, 3)
+        first = done[0]
+        assert first["status"] == 0 and first["iterations"] > 100, first
+        for k in (1, 2):
+            c = done[k]
+            assert c["status"] == 0, c
+            assert c["worker"] == first["worker"]
+            assert first["t_start"] < c["t_start"] < first["t_end"], (first, c)
+        assert max(c["batch"] for c in done.values()) >= 2
+        mix = [to_host(u) for u in us]
+        for k in range(3):
+            u = torch.empty(shape, dtype=torch.float64, device="cuda")
+            srv.submit(10 + k, to_dev(etas[k]), bcs, u=u, **kw)
+            c = _drain(srv, 1)[10 + k]
+            assert c["batch"] == 1 and c["iterations"] == done[k]["iterations"], (c, done[k])
+            assert np.array_equal(to_host(u), mix[k]), k
+            # stopped on the residual alone (1e-12), kappa about 10^3
+            assert_close(mix[k], oracle_solve(etas[k], bcs), 1e-8, k)
+    finally:
+        srv.close()
+
+
+def test_two_workers_mixed_plans_alone_equals_mix():
+    # two workers serve three kinds of request (grid, boundary conditions,
+    # precision) at once, each in its own continuous batch; every result is
+    # bitwise that of the same request served alone, and within its
+    # tolerance of the oracle
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_FLEX_BETA, Server
+    kinds = [((32, 32, 48), ("P", "P", "DN"), "i8x7", 0, 1e-10),
+             ((20, 24, 28), ("N", "N", "N"), "bf16", KP_FLAG_FLEX_BETA, 1e-10),
+             ((16, 20, 24), ("D", "P", "N"), "f64", 0, 1e-10),
+             ((24, 24, 24), ("DN", "D", "P"), "f32", 0, 1e-8)]
+    reqs = [(k % len(kinds), 1800 + k) for k in range(16)]
+    srv = Server(hbm_budget=0, workers=2, max_batch=3)
+    try:
+        outs, etas = {}, {}
+        for rid, (kind, seed) in enumerate(reqs):
+            shape, bcs, prec, fl, tol = kinds[kind]
+            etas[rid] = synth.charge_field(shape, ncharges=100, seed=seed)
+            outs[rid] = torch.empty(shape, dtype=torch.float64, device="cuda")
+            srv.submit(rid, to_dev(etas[rid]), bcs, tol=tol, prec=prec, flags=fl, u=outs[rid])
+        done = _drain(srv, len(reqs))
+        assert all(c["status"] == 0 for c in done.values()), done
+        assert len({c["worker"] for c in done.values()}) == 2
+        # some requests of different kinds ran at the same time on the two workers
+        ivs = [(c["t_start"], c["t_end"], c["worker"], reqs[i][0]) for i, c in done.items()]
+        assert any(a[2] != b[2] and a[3] != b[3] and a[0] < b[1] and b[0] < a[1]
+                   for a in ivs for b in ivs)
+        mix = {rid: to_host(u) for rid, u in outs.items()}
+        for rid, (kind, seed) in enumerate(reqs):
+            shape, bcs, prec, fl, tol = kinds[kind]
+            u = torch.empty(shape, dtype=torch.float64, device="cuda")
+            srv.submit(1000 + rid, to_dev(etas[rid]), bcs, tol=tol, prec=prec, flags=fl, u=u)
+            c = _drain(srv, 1)[1000 + rid]
+            assert c["batch"] == 1 and c["iterations"] == done[rid]["iterations"]
+            assert np.array_equal(to_host(u), mix[rid]), (rid, prec)
+            assert_close(mix[rid], oracle_solve(etas[rid], bcs), tol, (rid, prec))
+    finally:
+        srv.close()
