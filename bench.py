@@ -126,11 +126,14 @@ def launch_identity(cls, prec, grid, batch, tuning):
     K = grid["xyz".index(cls.split("_")[1])]
     rows = nx * ny * nz // K
     if prec == "i8x7":
-        # one kernel for every product: k-blocks of 64 per wave, split over
-        # two waves above 256; one block of 4 (8) waves per 64 rows
-        ks = 2 if K > 256 else 1
-        kbw = -(-(-(-K // 64)) // ks)
-        return f"kp::mp_oz<{kbw}, {ks}>|{-(-rows // 64) * batch * 256 * ks}"
+        # k-blocks of 64 per wave; up to 256 one block of 4 waves per 64 rows,
+        # above it split over two waves per row group, one block of 4 waves
+        # per 32 rows, the epilogue kind (1: the Hadamard factor) a parameter
+        nkb = -(-K // 64)
+        if K <= 256:
+            return f"kp::mp_oz<{nkb}, 1>|{-(-rows // 64) * batch * 256}"
+        epi = 1 if q == dim - 1 else 0
+        return f"kp::mp_ozh<{-(-nkb // 2)}, {epi}>|{-(-rows // 32) * batch * 256}"
     tc = {"f64": "double", "f32": "float", "bf16": "__bf16", "bf16x6": "float"}[prec]
     ti = "double" if q == 0 else tc
     to = "double" if q == 2 * dim - 1 else tc

@@ -702,10 +702,18 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 //   worst, far below what FP64 preconditioning needs (one CG iteration).
 // The data is read from HBM once and digitised in registers (16 consecutive
 // k per lane and k-block of 64); the operator digits stream through LDS one
-// column fragment (16 columns) at a time, double-buffered.  Block = 4 row
-// groups of 16 rows (64 rows); above K = 256 the k-blocks are split over two
-// waves per row group (KS = 2, eight waves), whose int32 sums are added
-// exactly through LDS.  A row with a non-finite value yields NaN outputs.
+// column fragment (16 columns) at a time.  Two kernels:
+//   mp_oz (K <= 256): blocks of 4 waves x 16 rows, two blocks per CU, the
+//     operator fragment double-buffered through registers.
+//   mp_ozh (K > 256): the k-blocks split over two waves per row group (their
+//     int32 sums added exactly through LDS), blocks of 2 row groups (32 rows,
+//     4 waves) so that two blocks share a CU and one block's data loads,
+//     operator refill and epilogue overlap the other's matrix-core work; the
+//     operator fragment single-buffered and refilled straight from memory
+//     into LDS (no registers) while the finishing wave runs the epilogue.
+// Both need K % 16 == 0 and rows % 16 == 0 (every extent of an int8 split
+// plan is a multiple of 16).  A row with a non-finite value yields NaN
+// outputs.
 // ---------------------------------------------------------------------------
 constexpr int OZ_S = 7;
 constexpr int OZ_BAD = 0x40000000;    // exponent marker of a non-finite row
@@ -721,34 +729,14 @@ static size_t oz_digit_bytes(int K) {
   return (size_t)((K + 15) / 16) * oz_split(K) * oz_kb_per_wave(K) * OZ_S * 64 * 16;
 }
 
-template <int KBW, int KS>
-__global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
-    const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
-    double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
-    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
-    int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
-  constexpr int NT = 256 * KS;
-  constexpr int SU = KS * KBW * OZ_S * 64;      // 16-byte units per column fragment
-  constexpr int UPT = (SU + NT - 1) / NT;
-  __shared__ u4 lds[2][SU];
-  __shared__ double hmax[KS][4][16];
-  __shared__ v4i xch[KS == 2 ? 4 : 1][OZ_S][64];
-  __shared__ double fred[NT / 64][2];
-
-  const int rhs = blockIdx.y;
-  if (st && st[rhs].done) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, l16 = lane & 15;
-  const int wr = wave & 3, h = wave >> 2;       // row group, k half
-  const int r0 = blockIdx.x * 64 + wr * 16;
-  const int r = r0 + l16;
-  const double* xr = X + (int64_t)rhs * N + (int64_t)(r < rows ? r : 0) * K;
-  const int kb0 = h * KBW;
-
-  // the lane's values, read once; the row's maximum and finiteness
-  d2 raw[KBW][8];
-  double mx = 0.0;
-  int bad = 0;
+// The lane's 16 consecutive values of each of its KBW k-blocks (from kb0)
+// of one row, read once, with their largest magnitude and whether any is not
+// finite.  k-blocks past K (padding of the split) read as zeros.
+template <int KBW>
+__device__ __forceinline__ void oz_load(const double* xr, int kb0, int K, int g,
+                                        d2 (&raw)[KBW][8], double& mx, int& bad) {
+  mx = 0.0;
+  bad = 0;
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb) {
     const int k0 = (kb0 + kb) * 64 + 16 * g;
@@ -761,29 +749,26 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
       mx = fmax(mx, fmax(a, b));
     }
   }
-  mx = fmax(mx, __shfl_xor(mx, 16, 64));
-  mx = fmax(mx, __shfl_xor(mx, 32, 64));
-  bad |= __shfl_xor(bad, 16, 64);
-  bad |= __shfl_xor(bad, 32, 64);
-  if constexpr (KS == 2) {
-    if (g == 0) hmax[h][wr][l16] = bad ? INFINITY : mx;
-    __syncthreads();
-    const double o = hmax[h ^ 1][wr][l16];
-    bad |= !(o <= DBL_MAX);
-    mx = fmax(mx, o);
-  }
-  int e = 0;
-  if (mx > 0.0) (void)frexp(mx, &e);           // |x| < 2^e on the row
-  e = max(e, -1021);                            // images of subnormal rows fit 49 bits too
+}
 
-  // Digits from the bit pattern: the image F = floor(|x| 2^(49 - e)) < 2^49
-  // is the 53-bit significand shifted right by e + 1026 - max(ef, 1) >= 4
-  // (ef the biased exponent field; a non-finite row shifts everything out);
-  // its 7-bit fields from the top are the digit magnitudes, which take the
-  // sign of x (negated two values at a time on 16-bit halves).  These are
-  // the digits of truncating |x| 2^-e one base-128 place at a time.
-  const int cshift = bad ? 4096 : e + 1026;
-  v4i xa[KBW][OZ_S];
+// The row's exponent e (|x| < 2^e) from its largest magnitude.
+__device__ __forceinline__ int oz_exponent(double mx) {
+  int e = 0;
+  if (mx > 0.0) (void)frexp(mx, &e);
+  return max(e, -1021);                         // images of subnormal rows fit 49 bits too
+}
+
+// Digits from the bit pattern: the image F = floor(|x| 2^(49 - e)) < 2^49 is
+// the 53-bit significand shifted right by e + 1026 - max(ef, 1) >= 4 (ef the
+// biased exponent field; cshift = e + 1026, or past 63 for a non-finite row,
+// which shifts everything out); its 7-bit fields from the top are the digit
+// magnitudes, which take the sign of x (negated two values at a time on
+// 16-bit halves).  These are the digits of truncating |x| 2^-e one base-128
+// place at a time.  xa[kb][s] holds digit s of the lane's 16 values of
+// k-block kb, four to a dword.
+template <int KBW>
+__device__ __forceinline__ void oz_digits(const d2 (&raw)[KBW][8], int cshift,
+                                          v4i (&xa)[KBW][OZ_S]) {
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb)
 #pragma unroll
@@ -823,6 +808,71 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
                                                   __builtin_bit_cast(unsigned, p01), 0x06040200u);
       }
     }
+}
+
+// The digit products of k-block kb into the diagonal sums acc[d], d = i + s;
+// consecutive products update different diagonals.
+__device__ __forceinline__ void oz_products(const v4i (&a)[OZ_S], const v4i (&b)[OZ_S],
+                                            v4i (&acc)[OZ_S]) {
+#pragma unroll
+  for (int i = 0; i < OZ_S; ++i)
+#pragma unroll
+    for (int s = 0; s + i < OZ_S; ++s)
+      acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[s], acc[i + s], 0, 0, 0);
+}
+
+// One output from its exact diagonal sums a[d]: sum_d 128^-d a[d] (Horner,
+// low diagonals first), scaled by 2^(e + f - 14); NaN for a non-finite row.
+__device__ __forceinline__ double oz_value(const int (&a)[OZ_S], int e, int f) {
+  double val = (double)a[OZ_S - 1];
+#pragma unroll
+  for (int d = OZ_S - 2; d >= 0; --d) val = (double)a[d] + val * (1.0 / 128.0);
+  return e == OZ_BAD ? NAN : ldexp(val, e + f - 14);
+}
+
+template <int KBW, int KS>
+__global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
+    const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
+    double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
+  constexpr int NT = 256 * KS;
+  constexpr int SU = KS * KBW * OZ_S * 64;      // 16-byte units per column fragment
+  constexpr int UPT = (SU + NT - 1) / NT;
+  __shared__ u4 lds[2][SU];
+  __shared__ double hmax[KS][4][16];
+  __shared__ v4i xch[KS == 2 ? 4 : 1][OZ_S][64];
+  __shared__ double fred[NT / 64][2];
+
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wr = wave & 3, h = wave >> 2;       // row group, k half
+  const int r0 = blockIdx.x * 64 + wr * 16;
+  const int r = r0 + l16;
+  const double* xr = X + (int64_t)rhs * N + (int64_t)(r < rows ? r : 0) * K;
+  const int kb0 = h * KBW;
+
+  // the lane's values, read once; the row's maximum and finiteness
+  d2 raw[KBW][8];
+  double mx;
+  int bad;
+  oz_load<KBW>(xr, kb0, K, g, raw, mx, bad);
+  mx = fmax(mx, __shfl_xor(mx, 16, 64));
+  mx = fmax(mx, __shfl_xor(mx, 32, 64));
+  bad |= __shfl_xor(bad, 16, 64);
+  bad |= __shfl_xor(bad, 32, 64);
+  if constexpr (KS == 2) {
+    if (g == 0) hmax[h][wr][l16] = bad ? INFINITY : mx;
+    __syncthreads();
+    const double o = hmax[h ^ 1][wr][l16];
+    bad |= !(o <= DBL_MAX);
+    mx = fmax(mx, o);
+  }
+  const int e = oz_exponent(mx);
+  v4i xa[KBW][OZ_S];
+  oz_digits<KBW>(raw, bad ? 4096 : e + 1026, xa);
   // exponents of this lane's output rows 4g + v (held by lane 4g + v)
   const int eo = bad ? OZ_BAD : e;
   int erow[4];
@@ -860,12 +910,7 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
         const u4 u = lds[buf][((kb0 + kb) * OZ_S + s) * 64 + lane];
         b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
       }
-      // consecutive products update different diagonals
-#pragma unroll
-      for (int i = 0; i < OZ_S; ++i)
-#pragma unroll
-        for (int s = 0; s + i < OZ_S; ++s)
-          acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xa[kb][i], b[s], acc[i + s], 0, 0, 0);
+      oz_products(xa[kb], b, acc);
     }
     if constexpr (KS == 2) {
       if (h == 1) {
@@ -886,10 +931,10 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = r0 + 4 * g + v;
-        double val = (double)acc[OZ_S - 1][v];
+        int a[OZ_S];
 #pragma unroll
-        for (int d = OZ_S - 2; d >= 0; --d) val = (double)acc[d][v] + val * (1.0 / 128.0);
-        val = erow[v] == OZ_BAD ? NAN : ldexp(val, erow[v] + f - 14);
+        for (int d = 0; d < OZ_S; ++d) a[d] = acc[d][v];
+        double val = oz_value(a, erow[v], f);
         const double rhat = val;
         if (lc) val *= ghat(rowsum[v] + lcn);
         if (gt) val *= gt[(int64_t)n * rows + (rr < rows ? rr : 0)];
@@ -920,6 +965,168 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     if (lane == 0) {
       fred[wave][0] = fs[0];
       fred[wave][1] = fs[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t0 = 0.0, t1 = 0.0;
+      for (int w = 0; w < NT / 64; ++w) {
+        t0 += fred[w][0];
+        t1 += fred[w][1];
+      }
+      slot_ptr(rpart, rhs, S_DOT)[blockIdx.x] = t0;
+      slot_ptr(rpart, rhs, S_SUM)[blockIdx.x] = 0.0;
+      slot_ptr(rpart, rhs, S_SQ)[blockIdx.x] = t1;
+      slot_ptr(rpart, rhs, S_AUX2)[blockIdx.x] = 0.0;
+    }
+  }
+}
+
+// K > 256: 32 rows per block (row group wr = wave & 1, k half h = wave >> 1).
+// EPI: 0 plain, 1 the Hadamard factor Ghat from the eigenvalue sums (la, lb
+// over the rows, lc over the columns; rpart, when given, takes the spectral
+// <R, Z> and ||Z||^2), 2 the Hadamard factor from the table gt [K][rows].
+// The k half (j & 1) finishes fragment j, the other hands it its sums.
+template <int KBW, int EPI>
+__global__ __launch_bounds__(256, 2) void mp_ozh(
+    const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
+    double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
+  constexpr int NT = 256;
+  constexpr int SU = 2 * KBW * OZ_S * 64;       // 16-byte units per column fragment
+  constexpr int UPT = (SU + NT - 1) / NT;
+  __shared__ u4 lds[SU];
+  __shared__ double hmax[2][2][16];
+  __shared__ v4i xch[2][OZ_S][64];
+  __shared__ double fred[NT / 64][2];
+
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wr = wave & 1, h = wave >> 1;
+  const int r0 = blockIdx.x * 32 + wr * 16;
+  const int r = r0 + l16;
+  const double* xr = X + (int64_t)rhs * N + (int64_t)(r < rows ? r : 0) * K;
+  const int kb0 = h * KBW;
+  const int nfr = K / 16;
+
+  // operator digits of fragment j into LDS without registers: each wave moves
+  // 64 consecutive 16-byte units (the builtin writes lane l's 16 bytes at the
+  // wave-uniform LDS address + 16 l), so a wave's chunk lies wholly inside or
+  // wholly past the fragment
+  auto stage = [&](int j) {
+    const u4* src = Bpk + (int64_t)j * SU;
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int u0 = (tid & ~63) + q * NT;
+      if (u0 < SU)
+        __builtin_amdgcn_global_load_lds((const void*)(src + u0 + lane),
+                                         (__attribute__((address_space(3))) void*)&lds[u0], 16,
+                                         0, 0);
+    }
+  };
+  stage(0);                                     // in flight while the data loads
+
+  d2 raw[KBW][8];
+  double mx;
+  int bad;
+  oz_load<KBW>(xr, kb0, K, g, raw, mx, bad);
+  mx = fmax(mx, __shfl_xor(mx, 16, 64));
+  mx = fmax(mx, __shfl_xor(mx, 32, 64));
+  bad |= __shfl_xor(bad, 16, 64);
+  bad |= __shfl_xor(bad, 32, 64);
+  if (g == 0) hmax[h][wr][l16] = bad ? INFINITY : mx;
+  __syncthreads();
+  {
+    const double o = hmax[h ^ 1][wr][l16];
+    bad |= !(o <= DBL_MAX);
+    mx = fmax(mx, o);
+  }
+  const int e = oz_exponent(mx);
+  v4i xa[KBW][OZ_S];
+  oz_digits<KBW>(raw, bad ? 4096 : e + 1026, xa);
+  const int eo = bad ? OZ_BAD : e;
+  int erow[4];
+  double rowsum[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    erow[v] = __shfl(eo, 4 * g + v, 64);
+    const int rr = r0 + 4 * g + v, rc = rr < rows ? rr : 0;
+    rowsum[v] = EPI == 1 ? la[rc % a1] + (lb ? lb[rc / a1] : 0.0) : 0.0;
+  }
+  __builtin_amdgcn_s_waitcnt(0);                // the first fragment has landed
+  __syncthreads();
+
+  double* Yb = Y + (int64_t)rhs * N;
+  const bool rows_ok = r0 < rows;               // the row group lies inside (rows % 16 == 0)
+  double fs0 = 0.0, fs1 = 0.0;                  // spectral <R, Z> and ||Z||^2
+  for (int j = 0; j < nfr; ++j) {
+    const int n = 16 * j + l16;
+    v4i acc[OZ_S];
+#pragma unroll
+    for (int d = 0; d < OZ_S; ++d) acc[d] = (v4i){0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < KBW; ++kb) {
+      v4i b[OZ_S];
+#pragma unroll
+      for (int s = 0; s < OZ_S; ++s) {
+        const u4 u = lds[((kb0 + kb) * OZ_S + s) * 64 + lane];
+        b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+      }
+      oz_products(xa[kb], b, acc);
+    }
+    const int fh = j & 1;
+    if (h != fh) {
+#pragma unroll
+      for (int d = 0; d < OZ_S; ++d) xch[wr][d][lane] = acc[d];
+    }
+    __syncthreads();                            // the fragment's digits are consumed
+    if (j + 1 < nfr) stage(j + 1);
+    if (h == fh) {
+      const int f = fexp[n];
+      const double lcn = EPI == 1 ? lc[n] : 0.0;
+      double gv[4] = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (EPI == 2) {
+        const d2* src =
+            reinterpret_cast<const d2*>(gt + (int64_t)n * rows + (rows_ok ? r0 + 4 * g : 0));
+        const d2 t0 = src[0], t1 = src[1];
+        gv[0] = t0.x; gv[1] = t0.y; gv[2] = t1.x; gv[3] = t1.y;
+      }
+#pragma unroll
+      for (int d = 0; d < OZ_S; ++d) acc[d] += xch[wr][d][lane];
+      double out[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int a[OZ_S];
+#pragma unroll
+        for (int d = 0; d < OZ_S; ++d) a[d] = acc[d][v];
+        double val = oz_value(a, erow[v], f);
+        const double rhat = val;
+        if constexpr (EPI == 1) {
+          val *= ghat(rowsum[v] + lcn);
+          fs0 += rows_ok ? rhat * val : 0.0;
+          fs1 += rows_ok ? val * val : 0.0;
+        }
+        if constexpr (EPI == 2) val *= gv[v];
+        out[v] = val;
+      }
+      if (rows_ok) {
+        double* dst = Yb + (int64_t)n * rows + r0 + 4 * g;
+        *reinterpret_cast<d2*>(dst) = (d2){out[0], out[1]};
+        *reinterpret_cast<d2*>(dst + 2) = (d2){out[2], out[3]};
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);              // the next fragment has landed
+    __syncthreads();
+  }
+  if (EPI == 1 && rpart) {
+    // fixed-order block reduction: lanes, then waves in order
+    fs0 = wave_sum(fs0);
+    fs1 = wave_sum(fs1);
+    if (lane == 0) {
+      fred[wave][0] = fs0;
+      fred[wave][1] = fs1;
     }
     __syncthreads();
     if (tid == 0) {
@@ -967,6 +1174,9 @@ static void oz_pack(const double* B, int K, void* dst) {
   }
 }
 
+// Rows per block of the int8 split product for a K x K operator.
+static int oz_block_rows(int K) { return oz_split(K) == 2 ? 32 : 64; }
+
 static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
                       const RhsState* st, const double* la, const double* lb, const double* lc,
                       int a1, const double* gt, double* rpart, hipStream_t s) {
@@ -974,10 +1184,15 @@ static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* 
   const int rows = (int)(op.N / K);
   const char* Bp = (const char*)(fwd ? op.Bf[ax] : op.Bb[ax]);
   const int* fx = (const int*)(Bp + oz_digit_bytes(K));
-  dim3 grid((rows + 63) / 64, batch);
+  const int br = oz_block_rows(K);
+  dim3 grid((rows + br - 1) / br, batch);
   const int kbw = oz_kb_per_wave(K), ks = oz_split(K);
 #define KP_OZ(W, S_)                                                                         \
   hipLaunchKernelGGL((mp_oz<W, S_>), grid, dim3(256 * S_), 0, s, (const u4*)Bp, fx,          \
+                     (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
+                     gt, rpart)
+#define KP_OZH(W, E)                                                                         \
+  hipLaunchKernelGGL((mp_ozh<W, E>), grid, dim3(256), 0, s, (const u4*)Bp, fx,               \
                      (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
                      gt, rpart)
   if (ks == 1) {
@@ -988,10 +1203,19 @@ static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* 
       default: KP_OZ(4, 1); break;
     }
   } else {
-    if (kbw == 3) KP_OZ(3, 2);
-    else KP_OZ(4, 2);
+    const int epi = lc ? 1 : (gt ? 2 : 0);
+    if (kbw == 3) {
+      if (epi == 1) KP_OZH(3, 1);
+      else if (epi == 2) KP_OZH(3, 2);
+      else KP_OZH(3, 0);
+    } else {
+      if (epi == 1) KP_OZH(4, 1);
+      else if (epi == 2) KP_OZH(4, 2);
+      else KP_OZH(4, 0);
+    }
   }
 #undef KP_OZ
+#undef KP_OZH
 }
 
 
@@ -1335,8 +1559,9 @@ int pinv_ghat_blocks(const PinvOps& op) {
   const int q = op.dim - 1, ax = q;
   const int K = op.n[ax];
   const int64_t rows = op.N / K;
-  if (op.prec == PREC_I8X7) {   // mp_oz: one block per 64 rows
-    const int64_t t = (rows + 63) / 64;
+  if (op.prec == PREC_I8X7) {   // one block per 64 (K <= 256) or 32 rows
+    const int br = oz_block_rows(K);
+    const int64_t t = (rows + br - 1) / br;
     return t > (1 << 30) ? (1 << 30) : (int)t;
   }
   const int CH = op.prec == PREC_F64 || op.prec == PREC_F32 ? 4 : 8;

@@ -28,7 +28,9 @@ def _plan(shape, bcs, prec="f64", max_batch=1):
                                                  ((64, 64), ("D", "D"), 3, "bf16x6"),
                                                  # the int8 split carries the G_r table too
                                                  ((48, 64), ("D", "N"), 3, "i8x7"),
-                                                 ((80, 32), ("N", "P"), 5, "i8x7")])
+                                                 ((80, 32), ("N", "P"), 5, "i8x7"),
+                                                 # the table on a split axis (K > 256)
+                                                 ((320, 32), ("D", "N"), 3, "i8x7")])
 def test_apply_parity(shape, bcs, rank, prec):
     rng = np.random.default_rng(90)
     batch = 2
