@@ -821,6 +821,18 @@ __device__ __forceinline__ void oz_products(const v4i (&a)[OZ_S], const v4i (&b)
       acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[s], acc[i + s], 0, 0, 0);
 }
 
+// Ghat for the int8 split epilogues: the hardware reciprocal estimate and two
+// Newton steps r <- r + r (1 - s r), each squaring the relative error, reach
+// FP64 accuracy (within an ulp of 1/s) without the IEEE division sequence.
+__device__ __forceinline__ double ghat_fast(double s) {
+  double r = __builtin_amdgcn_rcp(s);
+  double e = fma(-s, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-s, r, 1.0);
+  r = fma(r, e, r);
+  return fabs(s) < 1e-13 ? 0.0 : r;
+}
+
 // One output from its exact diagonal sums a[d]: sum_d 128^-d a[d] (Horner,
 // low diagonals first), scaled by 2^(e + f - 14); NaN for a non-finite row.
 __device__ __forceinline__ double oz_value(const int (&a)[OZ_S], int e, int f) {
@@ -936,7 +948,7 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
         for (int d = 0; d < OZ_S; ++d) a[d] = acc[d][v];
         double val = oz_value(a, erow[v], f);
         const double rhat = val;
-        if (lc) val *= ghat(rowsum[v] + lcn);
+        if (lc) val *= ghat_fast(rowsum[v] + lcn);
         if (gt) val *= gt[(int64_t)n * rows + (rr < rows ? rr : 0)];
         if (rpart && rr < rows) {
           fs[0] += rhat * val;
@@ -1104,7 +1116,7 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
         double val = oz_value(a, erow[v], f);
         const double rhat = val;
         if constexpr (EPI == 1) {
-          val *= ghat(rowsum[v] + lcn);
+          val *= ghat_fast(rowsum[v] + lcn);
           fs0 += rows_ok ? rhat * val : 0.0;
           fs1 += rows_ok ? val * val : 0.0;
         }
