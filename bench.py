@@ -193,6 +193,91 @@ def ingest_traffic(workload, fetch_dir, write_dir, command):
     return rec
 
 
+# matrix-core rates per CU per cycle by operand type (dense, the published
+# MI355X peaks at 2.4 GHz over 256 CUs): ops counted as the profiler's
+# SQ_INSTS_VALU_MFMA_MOPS_* (units of 512 operations)
+MFMA_OPS_PER_CU_CYCLE = {"F64": 128.0, "F32": 256.0, "BF16": 4096.0, "I8": 8192.0}
+NUM_XCD, NUM_CU, SIMD_PER_CU = 8, 256, 4
+
+
+def profiler_kernel_name(name):
+    """The profiler's kernel name in the form launch_identity uses.  rocprofv3
+    leaves most templates with __bf16 arguments mangled, and demangles the
+    operand pair (__bf16, double) as 'bool _Accum'; both are rewritten."""
+    import re
+    m = re.match(r"_ZN2kp(\d+)(mp_kernel|mp_res)I(.*?E)EEv", name)
+    if m:
+        args, rest = [], m.group(3)
+        while rest:
+            t = re.match(r"Li(\d+)E|Lb([01])E|DF16b|d|f", rest)
+            if not t:
+                return name
+            tok = t.group(0)
+            args.append(t.group(1) if t.group(1) else ("true" if t.group(2) == "1" else "false")
+                        if t.group(2) else {"DF16b": "__bf16", "d": "double", "f": "float"}[tok])
+            rest = rest[len(tok):]
+        return f"kp::{m.group(2)}<{', '.join(args)}>"
+    name = re.sub(r"^kp::(mp_kernel|mp_res)<(\d+), bool _Accum, ", r"kp::\1<\2, __bf16, double, ",
+                  name.replace("void ", "").strip())
+    return name
+
+
+def ingest_mfma(counter_dir, bench_log, workload, prec):
+    """Per mode-product kernel of one counter run: dispatches, duration, the
+    clock GRBM_GUI_ACTIVE implies, the matrix-core busy fraction
+    (SQ_VALU_MFMA_BUSY_CYCLES over SIMD-cycles) and the operations per
+    CU-cycle of each operand type against its peak; as markdown rows.  The
+    products a kernel served come from the tile choices in the JSON line of
+    the profiled bench run (bench_log)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(counter_dir, "**", "*counter_collection.csv"), recursive=True)[0]
+    disp = {}
+    for r in csv.DictReader(open(f)):
+        name = profiler_kernel_name(r["Kernel_Name"].split("(")[0].replace("void ", "").strip())
+        if not any(t in name for t in ("mp_kernel", "mp_res", "mp_oz")):
+            continue
+        d = disp.setdefault(r["Dispatch_Id"], {"key": f"{name}|{r['Grid_Size']}", "c": {},
+                                               "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    wl = WORKLOADS[workload]
+    line = [ln for ln in open(bench_log) if ln.startswith("{")][-1]
+    tiles = json.loads(line)["config"]["tile_configs"]
+    names = {}
+    for cls in PRODUCT_ORDER[3 if wl["grid"][2] > 1 else 2]:
+        ident = launch_identity(cls, prec, wl["grid"], wl["batch"], tiles)
+        names.setdefault(ident, []).append(cls.replace("modeprod_", ""))
+    agg = {}
+    for d in disp.values():
+        a = agg.setdefault(d["key"], {"n": 0, "ns": 0.0, "c": {}})
+        a["n"] += 1
+        a["ns"] += d["ns"]
+        for k, v in d["c"].items():
+            a["c"][k] = a["c"].get(k, 0.0) + v
+    rows = []
+    for key, a in sorted(agg.items(), key=lambda t: -t[1]["ns"]):
+        n, c = a["n"], a["c"]
+        gui = c.get("GRBM_GUI_ACTIVE", 0.0) / n / NUM_XCD          # cycles of one XCD
+        if gui <= 0:
+            continue
+        us = a["ns"] / n / 1e3
+        busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / n / (gui * NUM_CU * SIMD_PER_CU)
+        parts = []
+        for t, peak in MFMA_OPS_PER_CU_CYCLE.items():
+            ops = c.get(f"SQ_INSTS_VALU_MFMA_MOPS_{t}", 0.0) / n * 512.0
+            if ops > 0:
+                parts.append(f"{t} {ops / (gui * NUM_CU):.1f} ops/CU-cycle = {ops / (gui * NUM_CU) / peak:.3f} of peak")
+        cls = names.get(key)
+        hbm = "-"
+        if cls:
+            by = product_bytes("modeprod_" + cls[0], prec, wl["grid"]) * wl["batch"]
+            hbm = f"{by / (us * 1e-6) / 1e9:.0f} GB/s = {by / (us * 1e-6) / 1e9 / PEAK['hbm_GBs']:.3f}"
+        kname, grid = key.rsplit("|", 1)
+        rows.append(f"| `{kname}` ({grid} threads) | {', '.join(cls or ['(tuning trial)'])} | {n} | {us:.1f} | "
+                    f"{gui / us / 1e3:.2f} | {busy:.3f} | {'; '.join(parts) or '-'} | {hbm} |")
+    return rows
+
+
 def measured_traffic(workload, identity):
     """HBM bytes per launch of a kernel from the workload's traffic record, or
     None when there is no record, the kernel is not in it or has changed."""
@@ -585,7 +670,17 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 256 MiB three times, the reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
+    ap.add_argument("--ingest-mfma", nargs=2, metavar=("COUNTER_DIR", "BENCH_LOG"),
+                    help="print the matrix-core counters of a rocprofv3 run of this workload "
+                         "and --prec per mode-product kernel (markdown rows), then exit")
     args = ap.parse_args()
+    if args.ingest_mfma:
+        prec = args.prec or WORKLOADS[args.workload]["prec"]
+        print("| kernel | products | dispatches | avg us | GRBM cycles/ns | MFMA busy | "
+              "ops per CU-cycle (of peak) | algorithmic HBM (of 8 TB/s) |")
+        print("|---|---|---|---|---|---|---|---|")
+        print("\n".join(ingest_mfma(*args.ingest_mfma, args.workload, prec)))
+        return
     if args.ingest_traffic:
         rec = ingest_traffic(args.workload, *args.ingest_traffic, args.ingest_command)
         print(f"wrote {traffic_path(args.workload)}: {len(rec['kernels'])} kernels")
