@@ -472,10 +472,14 @@ int kp_plan_graph_count(const kp_plan* plan);
  * oldest queued request and opens a batch of `max_batch` slots on that
  * request's plan; every queued request of the same plan, tolerance,
  * iteration limit and flags takes a free slot, also while the batch runs:
- * it starts at the next iteration boundary (its R_0, Z_0 are formed in the
- * step in which the other slots make an iteration) and leaves the batch, its
- * answer copied out and its completion posted, at the end of the step in
- * which its own solve ended.  The batch closes when no slot is busy.  Each
+ * it starts at the next step (its R_0, Z_0 are formed in the step in which
+ * the other slots make an iteration) and leaves the batch, its answer copied
+ * out and its completion posted, at the end of the step in which its own
+ * solve ended.  A step is one iteration while a request of the batch's kind
+ * waits for a slot, otherwise it runs until the first slot is expected to
+ * end (by the iteration count of the plan's previous solve), at most four
+ * iterations: fewer host round trips per solve.  The batch closes when no
+ * slot is busy.  Each
  * slot runs Algorithm 1 with kp_solve's arithmetic and stopping rules (the
  * low-mode certificate is tried in every iteration), so a request's result
  * is bitwise the same alone and in any mix.

@@ -63,6 +63,7 @@ struct PlanEntry {
   uint64_t last = 0;     // use tick, for LRU eviction
   size_t bytes = 0;      // resident operators
   int64_t ws_epoch = -1; // owner's workspace generation the plan is bound to
+  int expect = 0;        // iterations the plan's last solve made (0: none yet)
 };
 
 struct Worker {
@@ -102,6 +103,13 @@ struct kp_server {
 };
 
 namespace {
+
+// Most iterations per step of a continuous batch that no queued request
+// waits to join: a step then runs until the first slot is expected to end
+// (by the iteration count of the plan's last solve), so a solve takes few
+// host round trips; a newcomer waits at most that long for a free slot.  A
+// step's results do not depend on its length.
+constexpr int kStepIters = 4;
 
 size_t vec_bytes(const kp_request& r) { return (size_t)r.nx * r.ny * r.nz * sizeof(double); }
 
@@ -256,13 +264,17 @@ void worker_main(kp_server* s, int w) {
     s->running += 1;
     s->st.batches += 1;
     // the first requests of the batch: every queued one of the same kind
-    for (auto it = s->queue.begin(); it != s->queue.end() && (int)incoming.size() < s->max_batch;) {
+    bool waiting = false;   // a request of this kind is left queued
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
       if (same_batch(it->r, r0)) {
-        incoming.push_back(*it);
-        it = s->queue.erase(it);
-      } else {
-        ++it;
+        if ((int)incoming.size() < s->max_batch) {
+          incoming.push_back(*it);
+          it = s->queue.erase(it);
+          continue;
+        }
+        waiting = true;
       }
+      ++it;
     }
     lk.unlock();
     destroy_plans(victims);
@@ -312,6 +324,8 @@ void worker_main(kp_server* s, int w) {
     std::vector<Pending> req(s->max_batch);
     std::vector<char> busy(s->max_batch, 0);
     std::vector<double> t_start(s->max_batch, 0.0);
+    std::vector<int> iter_of(s->max_batch, 0);   // iterations made, from the last step
+    std::vector<char> joined(s->max_batch, 0);   // starts in the next step
     int active = 0;
     std::vector<int> fin;
     for (;;) {
@@ -321,6 +335,8 @@ void worker_main(kp_server* s, int w) {
         while (busy[slot]) ++slot;
         req[slot] = p;
         busy[slot] = 1;
+        iter_of[slot] = 0;
+        joined[slot] = 1;
         active += 1;
         t_start[slot] = s->now();
         if (rc != KP_OK) continue;
@@ -335,8 +351,25 @@ void worker_main(kp_server* s, int w) {
       }
       incoming.clear();
       if (active == 0) break;
+      // one iteration per step while a request of this kind waits for a slot;
+      // otherwise up to the first expected exit (a joining slot first takes
+      // its start), at most kStepIters, within every slot's iteration cap
+      int iters = (waiting || entry->expect == 0) ? 1 : kStepIters;
+      for (int slot = 0; slot < s->max_batch; ++slot) {
+        if (!busy[slot]) continue;
+        const int left = entry->expect - iter_of[slot] + (joined[slot] ? 1 : 0);
+        iters = std::min(iters, std::max(1, left));
+        iters = std::min(iters, std::max(1, r0.max_iter - iter_of[slot]));
+      }
+      // launches cover the slots up to the last busy one (newcomers take the
+      // lowest free slots)
+      int nslots = 0;
+      for (int slot = 0; slot < s->max_batch; ++slot)
+        if (busy[slot]) nslots = slot + 1;
       const kp::RhsState* m = nullptr;
-      if (rc == KP_OK && (rc = kp::slots_step(entry->plan)) != KP_OK) failed = "slots_step";
+      if (rc == KP_OK && (rc = kp::slots_step(entry->plan, iters, nslots)) != KP_OK)
+        failed = "slots_step";
+      std::fill(joined.begin(), joined.end(), 0);
       if (rc == KP_OK && !(m = kp::slots_wait(entry->plan))) {
         rc = KP_EHIP;
         failed = "slots_wait";
@@ -347,6 +380,7 @@ void worker_main(kp_server* s, int w) {
       for (int slot = 0; slot < s->max_batch && rc == KP_OK; ++slot) {
         if (!busy[slot]) continue;
         const kp::RhsState& x = m[slot];
+        iter_of[slot] = x.iter;
         if (kp::terminal(x.done) && x.exit_gen == 2) {
           fin.push_back(slot);
           const kp_request& r = req[slot].r;
@@ -381,6 +415,7 @@ void worker_main(kp_server* s, int w) {
       }
       for (int slot : fin) {
         const kp::RhsState& x = m[slot];
+        entry->expect = x.iter;
         kp_result res{};
         res.iterations = x.iter;
         res.rel_res = x.rel_res;
@@ -392,14 +427,17 @@ void worker_main(kp_server* s, int w) {
       }
       if (!fin.empty()) s->cv_done.notify_all();
       // queued requests of the same kind take the free slots
-      for (auto it = s->queue.begin();
-           it != s->queue.end() && active + (int)incoming.size() < s->max_batch;) {
+      waiting = false;
+      for (auto it = s->queue.begin(); it != s->queue.end();) {
         if (same_batch(it->r, r0)) {
-          incoming.push_back(*it);
-          it = s->queue.erase(it);
-        } else {
-          ++it;
+          if (active + (int)incoming.size() < s->max_batch) {
+            incoming.push_back(*it);
+            it = s->queue.erase(it);
+            continue;
+          }
+          waiting = true;
         }
+        ++it;
       }
       lk.unlock();
     }

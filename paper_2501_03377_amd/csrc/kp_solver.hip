@@ -443,8 +443,10 @@ struct SolveRun {
   double* diag_dev;
   const double* R0;
 
-  explicit SolveRun(kp_ticket* t_) : t(t_), p(t_->p) {
-    L = layout_for(p, t->batch);
+  // layout_batch: the batch the workspace is laid out for when it differs
+  // from the batch launched over (a continuous batch's first slots)
+  explicit SolveRun(kp_ticket* t_, int layout_batch = 0) : t(t_), p(t_->p) {
+    L = layout_for(p, layout_batch ? layout_batch : t->batch);
     base = (char*)p->ws;
     R = (double*)(base + L.R);
     P = (double*)(base + L.P);
@@ -764,12 +766,14 @@ int solve_advance(kp_ticket* t, bool block) {
 // ------------------------------------------------- continuous batches ----
 // The request server keeps one batch of max_batch slots running on a plan:
 // every slot is a right-hand side at its own stage of Algorithm 1 (or empty).
-// Each step is one iteration for the running slots, the start (R_0, Z_0,
-// rho_0, P_0) for slots that joined since the last step, and the exit step
-// (true residual, centring) for slots whose solve ended in it.  All of it
+// A step is the start (R_0, Z_0, rho_0, P_0) for slots that joined since the
+// last step, then one or more iterations for the running slots, then the
+// exit step (true residual, centring) for slots whose solve ended in it (a
+// slot that ends early in a step is skipped by the rest of it).  All of it
 // is the same arithmetic per right-hand side as kp_solve's, with the
 // low-mode certificate tried in every iteration, so a slot's result does not
-// depend on the other slots, on when it joined or on the slot it took.
+// depend on the other slots, on when it joined, on the slot it took or on
+// how the iterations were grouped into steps.
 namespace kp {
 
 int slots_open(kp_plan* p, const double* eta, double* u, double tol, int flags) {
@@ -802,32 +806,35 @@ int slots_mark(kp_plan* p, int slot, int code) {
 // Enqueues one step on the plan's private stream after the plan's stream
 // (where the slots' right-hand sides were staged and marked), as one
 // captured graph where possible.
-int slots_step(kp_plan* p) {
-  if (!p || !p->slot.open) return KP_EINVAL;
+int slots_step(kp_plan* p, int iters, int nslots) {
+  if (!p || !p->slot.open || iters < 1 || iters > 8 || nslots < 0 || nslots > p->max_batch)
+    return KP_EINVAL;
   kp_ticket t;
   t.p = p;
   t.eta = p->slot.eta;
   t.u = p->slot.u;
-  t.batch = p->max_batch;
+  t.batch = nslots ? nslots : p->max_batch;   // slots past it are left as they are
   t.tol = p->slot.tol;
   t.flags = p->slot.flags;
   t.hs = 1;
   t.cert = (t.flags & F_CERT) != 0;
-  SolveRun run(&t);
+  SolveRun run(&t, p->max_batch);   // the slots' states sit in the max_batch layout
   run.R0 = run.R;   // every slot's R_0 = eta_c is stored
   auto body = [&]() {
     launch_init(p->g, t.eta, run.R, nullptr, run.part, run.st, nullptr, 0, t.batch, run.G,
                 run.s, 1);
-    launch_iter_head(p->g, run.P, run.W, run.R, t.u, run.part, run.st, nullptr, 0, t.batch,
-                     run.G, t.tol, t.flags, run.s, nullptr);
-    if (t.cert)
-      launch_cert(p->g, p->cert, run.R, (double*)(run.base + run.L.C1),
-                  (double*)(run.base + run.L.C2), (double*)(run.base + run.L.C3), run.st,
-                  t.batch, t.tol, run.s);
-    const int Gdot = precondition(p, run.L, run.R, run.Z, t.batch, t.flags, run.st, run.s,
-                                  run.part);
-    launch_after_pinv(p->g, run.R, run.Z, run.W, run.P, run.part, run.st, t.batch, run.G, 0,
-                      t.tol, t.flags, run.s, Gdot, false);
+    for (int i = 0; i < iters; ++i) {
+      launch_iter_head(p->g, run.P, run.W, run.R, t.u, run.part, run.st, nullptr, 0, t.batch,
+                       run.G, t.tol, t.flags, run.s, nullptr);
+      if (t.cert)
+        launch_cert(p->g, p->cert, run.R, (double*)(run.base + run.L.C1),
+                    (double*)(run.base + run.L.C2), (double*)(run.base + run.L.C3), run.st,
+                    t.batch, t.tol, run.s);
+      const int Gdot = precondition(p, run.L, run.R, run.Z, t.batch, t.flags, run.st, run.s,
+                                    run.part);
+      launch_after_pinv(p->g, run.R, run.Z, run.W, run.P, run.part, run.st, t.batch, run.G, 0,
+                        t.tol, t.flags, run.s, Gdot, false);
+    }
     launch_finish(p->g, t.eta, t.u, run.part, run.st, p->st_dev, t.batch, run.G, run.s, 1);
   };
   (void)hipGetLastError();
@@ -836,7 +843,8 @@ int slots_step(kp_plan* p) {
   TraceScope scope(p);
   bool launched = false;
   if (p->graphs_ok && !p->profiling) {
-    const kp_plan::GraphKey key{2, t.batch, 0, t.flags, 1, t.tol, t.u, nullptr, nullptr, t.eta};
+    const kp_plan::GraphKey key{2, t.batch, iters, t.flags, 1, t.tol, t.u, nullptr, nullptr,
+                                t.eta};
     const int gi = run.graph_for(key, body);
     if (gi >= 0) {
       if (!ok(hipGraphLaunch(p->graphs[gi].exec, run.s))) return KP_EHIP;

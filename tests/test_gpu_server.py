@@ -221,3 +221,36 @@ def test_two_workers_mixed_plans_alone_equals_mix():
             assert_close(mix[rid], oracle_solve(etas[rid], bcs), tol, (rid, prec))
     finally:
         srv.close()
+
+
+def test_step_length_does_not_change_results():
+    # a continuous batch steps one iteration at a time while a request of its
+    # kind waits for a slot (here max_batch = 1 with two queued behind the
+    # first), and up to four at a time otherwise (the last request, and every
+    # request served alone): plain CG, tens of iterations, bitwise equal
+    # either way; an iteration cap that is not a multiple of four is met
+    # exactly
+    import torch
+    from paper_2501_03377_amd import KP_FLAG_NO_PRECOND, KP_NOT_CONVERGED, Server
+    shape, bcs = (16, 20, 24), ("D", "N", "P")
+    etas = [synth.charge_field(shape, ncharges=50, seed=1900 + k) for k in range(3)]
+    kw = dict(tol=1e-10, prec="f64", flags=KP_FLAG_NO_PRECOND, max_iter=500)
+    srv = Server(hbm_budget=0, workers=1, max_batch=1)
+    try:
+        outs = [torch.empty(shape, dtype=torch.float64, device="cuda") for _ in range(3)]
+        for k in range(3):
+            srv.submit(k, to_dev(etas[k]), bcs, u=outs[k], **kw)
+        done = _drain(srv, 3)
+        assert all(c["status"] == 0 and c["iterations"] > 20 for c in done.values()), done
+        for k in range(3):
+            u = torch.empty(shape, dtype=torch.float64, device="cuda")
+            srv.submit(10 + k, to_dev(etas[k]), bcs, u=u, **kw)
+            c = _drain(srv, 1)[10 + k]
+            assert c["iterations"] == done[k]["iterations"], (c, done[k])
+            assert np.array_equal(to_host(u), to_host(outs[k])), k
+        u = torch.empty(shape, dtype=torch.float64, device="cuda")
+        srv.submit(99, to_dev(etas[0]), bcs, u=u, **dict(kw, max_iter=7))
+        c = _drain(srv, 1)[99]
+        assert c["status"] == KP_NOT_CONVERGED and c["iterations"] == 7, c
+    finally:
+        srv.close()
