@@ -40,6 +40,7 @@ if ROOT not in sys.path:
 
 METRIC = "3D solves/s at rel-res 1e-10, mixed vs FP64 PCG; p50/p99 latency"
 COPY_CAL_BYTES = 256 << 20     # bytes read (and written) by the calibration copy
+COPY_CAL_RUNS = 3               # times it runs, first of the run's device copies
 # TFLOP/s; bf16x6 counts the FP32-equivalent flops of a product, whose
 # emulation issues six BF16 matrix-core products: its ceiling is 2500 / 6;
 # i8x7 counts the FP64-equivalent flops, each of which costs 28 int8
@@ -168,20 +169,24 @@ def ingest_traffic(workload, fetch_dir, write_dir, command):
 
     def read(d, counter):
         f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
-        acc, copy_max = {}, 0.0
+        acc, copies = {}, []
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] != counter:
                 continue
             name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
             v = float(r["Counter_Value"])
             if "copyBuffer" in name:
-                copy_max = max(copy_max, v)
+                copies.append((int(r["Dispatch_Id"]), v))
                 continue
             key = f"{name}|{r['Grid_Size']}" if "mp_kernel" in name else name
             t = acc.setdefault(key, [0.0, 0])
             t[0] += v
             t[1] += 1
-        return {k: t[0] / t[1] for k, t in acc.items()}, copy_max
+        # the calibration copies are the run's first device copies (issued
+        # before anything else is copied); later copies move the workload's
+        # own data and have other sizes
+        cal = [v for _, v in sorted(copies)[:COPY_CAL_RUNS]]
+        return {k: t[0] / t[1] for k, t in acc.items()}, (sum(cal) / len(cal) if cal else 0.0)
 
     fetch, copy_fetch = read(fetch_dir, "FETCH_SIZE")
     write, copy_write = read(write_dir, "WRITE_SIZE")
@@ -708,7 +713,7 @@ def main():
     if args.copy_calibration:
         src = torch.ones(COPY_CAL_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
+        for _ in range(COPY_CAL_RUNS):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
