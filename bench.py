@@ -178,7 +178,9 @@ def ingest_traffic(workload, fetch_dir, write_dir, command):
             if "copyBuffer" in name:
                 copies.append((int(r["Dispatch_Id"]), v))
                 continue
-            key = f"{name}|{r['Grid_Size']}" if "mp_kernel" in name else name
+            name = profiler_kernel_name(name)
+            # mode products by name and total threads, as launch_identity names them
+            key = f"{name}|{r['Grid_Size']}" if name.startswith("kp::mp_") else name
             t = acc.setdefault(key, [0.0, 0])
             t[0] += v
             t[1] += 1
