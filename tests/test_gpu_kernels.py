@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import grid_dims, oracle_laplacian, oracle_pinv, rel, to_dev, to_host
+from gpu_util import (assert_close, grid_dims, oracle_laplacian, oracle_pinv, rel, to_dev,
+                      to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -77,9 +78,8 @@ def test_pinv_parity(shape, bcs, prec):
     plan = _plan(shape, bcs, prec=prec)
     z = to_host(plan.apply_pinv(to_dev(r)))
     ref = oracle_pinv(r, bcs)
-    err = rel(z, ref)
-    print(f"pinv {prec} {shape} {bcs}: rel err {err:.3e}")
-    assert err <= PINV_TOL[prec], err
+    err = assert_close(z, ref, PINV_TOL[prec])
+    print(f"pinv {prec} {shape} {bcs}: rel err (2-norm, max) {err[0]:.3e} {err[1]:.3e}")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -90,8 +90,7 @@ def test_pinv_all_bc_triples_small(prec):
     for bcs in ALL3:
         plan = _plan(shape, bcs, prec=prec)
         z = to_host(plan.apply_pinv(to_dev(r)))
-        err = rel(z, oracle_pinv(r, bcs))
-        assert err <= PINV_TOL[prec], (bcs, err)
+        assert_close(z, oracle_pinv(r, bcs), PINV_TOL[prec], bcs)
         plan.close()
 
 
@@ -147,7 +146,7 @@ def test_tile_shapes_are_bitwise_identical(prec, shape):
     ref = to_host(plan.apply_pinv(r))
     rh = to_host(r)
     for b in range(2):
-        assert rel(ref[b], oracle_pinv(rh[b], ("P", "D", "N"))) <= PINV_TOL[prec]
+        assert_close(ref[b], oracle_pinv(rh[b], ("P", "D", "N")), PINV_TOL[prec], b)
     for cfg in range(23):
         rc = kp_plan_set_tuning(plan._h, [cfg] * 6)
         if cfg not in TILE_CONFIGS[prec]:
@@ -168,7 +167,7 @@ def test_autotune_keeps_results():
     assert len(cfg) == 6
     after = to_host(plan.apply_pinv(to_dev(r)))
     assert np.array_equal(before, after)
-    assert rel(after, oracle_pinv(r, ("P", "P", "DN"))) <= PINV_TOL["f32"]
+    assert_close(after, oracle_pinv(r, ("P", "P", "DN")), PINV_TOL["f32"])
 
 
 @pytest.mark.parametrize("shape,bcs,prec", [((16, 48, 96), ("P", "P", "DN"), "f32"),

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import grid_dims, rel, to_dev, to_host
+from gpu_util import assert_close, grid_dims, to_dev, to_host
 from oracle.lowrank import lowrank_apply, lowrank_init
 
 pytestmark = pytest.mark.gpu
@@ -41,7 +41,7 @@ def test_apply_parity(shape, bcs, rank, prec):
     pairs = lowrank_init(shape[::-1], bcs, rank)
     for b in range(batch):
         ref = lowrank_apply(r[b].T, pairs).T
-        assert rel(z[b], ref) <= PREC_TOL[prec], (b, rel(z[b], ref))
+        assert_close(z[b], ref, PREC_TOL[prec], b)
 
 
 def test_full_rank_is_the_pseudoinverse():
@@ -51,7 +51,7 @@ def test_full_rank_is_the_pseudoinverse():
     z_pinv = to_host(plan.apply_preconditioner(to_dev(r)))
     plan.set_preconditioner("lowrank", 9)
     z_lr = to_host(plan.apply_preconditioner(to_dev(r)))
-    assert rel(z_lr, z_pinv) <= 1e-13
+    assert_close(z_lr, z_pinv, 1e-13)
     plan.set_preconditioner("pinv")
     assert np.array_equal(to_host(plan.apply_preconditioner(to_dev(r))), z_pinv)
 
@@ -68,7 +68,7 @@ def test_solves_rank_as_in_experiment_5_5():
         plan.set_preconditioner(*setup)
         u, res, _, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=2000, flags=flags)
         assert rc == 0, name
-        assert rel(to_host(u), ref) <= 1e-8, name
+        assert_close(to_host(u), ref, 1e-8, name)
         its[name] = res[0]["iterations"]
     assert its["pinv"] <= 3 < its["lowrank"] < its["jacobi"] < its["cg"], its
 
