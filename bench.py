@@ -456,6 +456,34 @@ def cpu_baseline(wl, eta, budget_s=25.0):
     }
 
 
+def stream_ceiling():
+    """Streaming rates this GPU reaches with torch's own kernels over 1 GiB
+    FP64 tensors: a device copy (16 B per element moved) and a sum (8 B read
+    per element).  A practical ceiling for the HBM-bound passes, beside the
+    published 8 TB/s peak that the roofline fraction is taken against."""
+    import torch
+    n = 1 << 27
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    rates = {}
+    for name, fn, bytes_per in (("copy", lambda: y.copy_(x), 16), ("read", lambda: x.sum(), 8)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        e1.synchronize()
+        rates[name] = bytes_per * n / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_GBs": round(rates["copy"], 1), "read_GBs": round(rates["read"], 1),
+            "copy_frac_of_peak": round(rates["copy"] / PEAK["hbm_GBs"], 4),
+            "read_frac_of_peak": round(rates["read"] / PEAK["hbm_GBs"], 4),
+            "how": "torch copy_ and sum over 1 GiB FP64 tensors, 10 launches between HIP events"}
+
+
 def rel_errors(u, ref):
     """(||u - ref||_2 / ||ref||_2, max|u - ref| / max|ref|)."""
     d = u - ref
@@ -861,6 +889,7 @@ def main():
     elif traffic is not None and dom in MODEPROD:
         roof["traffic_over_algorithmic_bytes"] = round(
             traffic / (product_bytes(dom, prec, wl["grid"]) * batch), 3)
+    ceiling = stream_ceiling()
     if dom == "small_solve":
         # one workgroup, hence one of the 256 compute units, per right-hand side
         cus = min(batch, 256)
@@ -900,6 +929,7 @@ def main():
         "plan_ms": round(m["plan_ms"], 3), "autotune_ms": round(m["tune_ms"], 1),
         "ms_per_step_profiled": 1000.0 * m["Tp"] / steps,
         "roofline": roof,
+        "stream_ceiling": ceiling,
         "kernels": kernels,
     }
 
