@@ -43,13 +43,16 @@ COPY_CAL_BYTES = 256 << 20     # bytes read (and written) by the calibration cop
 COPY_CAL_RUNS = 3               # times it runs, first of the run's device copies
 # TFLOP/s; bf16x6 counts the FP32-equivalent flops of a product, whose
 # emulation issues six BF16 matrix-core products: its ceiling is 2500 / 6;
-# i8x7 counts the FP64-equivalent flops, each of which costs 28 int8
-# matrix-core operations (5000 TOP/s dense): its ceiling is 5000 / 28
+# i8x7 and i8x6 count the FP64-equivalent flops, each of which costs 28 or
+# 21 int8 matrix-core operations (5000 TOP/s dense): their ceilings are
+# 5000 / 28 and 5000 / 21
+INT8_PRODUCTS = {"i8x7": 28, "i8x6": 21}
 PEAK = {"hbm_GBs": 8000.0, "f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x6": 2500.0 / 6,
-        "i8x7": 5000.0 / 28}
+        "i8x7": 5000.0 / 28, "i8x6": 5000.0 / 21}
 DTYPE = {"f32": "f64+f32", "f64": "f64", "bf16": "f64+bf16", "bf16x6": "f64+bf16x6",
-         "i8x7": "f64+i8x7"}
-PRECS = ("f64", "f32", "bf16", "bf16x6", "i8x7")
+         "i8x7": "f64+i8x7", "i8x6": "f64+i8x6"}
+PRECS = ("f64", "f32", "bf16", "bf16x6", "i8x7", "i8x6")
+FP64_ACCURATE = ("f64", "i8x7", "i8x6")
 MODEPROD = ("modeprod_z_fwd", "modeprod_y_fwd", "modeprod_x_fwd", "modeprod_x_bwd",
             "modeprod_y_bwd", "modeprod_z_bwd")
 
@@ -101,14 +104,14 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def i8x7_fits(grid):
-    """The int8 split preconditioner needs every axis a multiple of 16 and at
+def int8_fits(grid):
+    """The int8 split preconditioners need every axis a multiple of 16 and at
     most 512."""
     return all(n % 16 == 0 and n <= 512 for n in grid if n > 1)
 
 
 def pid_of(prec):
-    return {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3, "i8x7": 4}[prec]
+    return {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3, "i8x7": 4, "i8x6": 5}[prec]
 
 
 def launch_identity(cls, prec, grid, batch, tuning):
@@ -126,15 +129,16 @@ def launch_identity(cls, prec, grid, batch, tuning):
     q = PRODUCT_ORDER[dim].index(cls)
     K = grid["xyz".index(cls.split("_")[1])]
     rows = nx * ny * nz // K
-    if prec == "i8x7":
+    if prec in INT8_PRODUCTS:
         # k-blocks of 64 per wave; up to 256 one block of 4 waves per 64 rows,
         # above it split over two waves per row group, one block of 4 waves
-        # per 32 rows, the epilogue kind (1: the Hadamard factor) a parameter
-        nkb = -(-K // 64)
+        # per 32 rows, the epilogue kind (1: the Hadamard factor) and the
+        # digit count parameters
+        nkb, S = -(-K // 64), 7 if prec == "i8x7" else 6
         if K <= 256:
-            return f"kp::mp_oz<{nkb}, 1>|{-(-rows // 64) * batch * 256}"
+            return f"kp::mp_oz<{nkb}, 1, {S}>|{-(-rows // 64) * batch * 256}"
         epi = 1 if q == dim - 1 else 0
-        return f"kp::mp_ozh<{-(-nkb // 2)}, {epi}>|{-(-rows // 32) * batch * 256}"
+        return f"kp::mp_ozh<{-(-nkb // 2)}, {epi}, {S}>|{-(-rows // 32) * batch * 256}"
     tc = {"f64": "double", "f32": "float", "bf16": "__bf16", "bf16x6": "float"}[prec]
     ti = "double" if q == 0 else tc
     to = "double" if q == 2 * dim - 1 else tc
@@ -386,7 +390,7 @@ def launch_work(name, grid, batch, flex=False):
     return "byte", batch * words[name] * 8.0 * N
 
 
-ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x6": 4, "i8x7": 8}
+ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x6": 4, "i8x7": 8, "i8x6": 8}
 
 
 def product_bytes(name, prec, grid):
@@ -622,8 +626,8 @@ def serving_bench(args):
     if not args.no_compare:
         # the same stream with the FP64 preconditioner, and with its int8
         # split where every grid allows it
-        for p in ("f64", "i8x7"):
-            if p == prec or (p == "i8x7" and not all(i8x7_fits(g) for g in grids)):
+        for p in ("f64", "i8x7", "i8x6"):
+            if p == prec or (p in INT8_PRODUCTS and not all(int8_fits(g) for g in grids)):
                 continue
             log(f"closed loop, {'FP64' if p == 'f64' else p.upper()} preconditioner")
             srv = Server(hbm_budget=budget, workers=args.workers, max_batch=args.max_batch)
@@ -761,7 +765,7 @@ def main():
                 continue
             avg_us = 1000.0 * ms / cnt
             kind, work = solve_work(name, wl["grid"], results, p == "bf16",
-                                    p in ("f64", "i8x7"))
+                                    p in FP64_ACCURATE)
             units = work * nsolves / cnt            # algorithmic work per launch
             entry = {"avg_us": round(avg_us, 2), "launches": cnt, "total_ms": round(ms, 3)}
             if kind == "flop":
@@ -851,15 +855,16 @@ def main():
     dom, dom_ms, dom_reps = m["dom"]
     kind, units = launch_work(dom, wl["grid"], batch, prec == "bf16")
     if kind is None:            # one launch per solve: the solve's work
-        kind, units = solve_work(dom, wl["grid"], res, prec == "bf16", prec in ("f64", "i8x7"))
+        kind, units = solve_work(dom, wl["grid"], res, prec == "bf16", prec in FP64_ACCURATE)
     rate = units / (dom_ms * 1e-3)
     ident = launch_identity(dom, prec, wl["grid"], batch, m["tuning"])
     traffic = measured_traffic(args.workload, ident)
-    if kind == "flop" and prec == "i8x7":
-        # the int8 split issues 28 exact int8 digit products for every FP64
-        # multiply-add of the contraction: its matrix-core work is 28 x the
-        # algorithmic flops, priced against the published dense int8 peak
-        ops = 28.0 * rate
+    if kind == "flop" and prec in INT8_PRODUCTS:
+        # the int8 split issues 28 (i8x7) or 21 (i8x6) exact int8 digit
+        # products for every FP64 multiply-add of the contraction: its
+        # matrix-core work is that many times the algorithmic flops, priced
+        # against the published dense int8 peak
+        ops = INT8_PRODUCTS[prec] * rate
         roof = {"bound": "mfma", "achieved": round(ops / 1e12, 1), "peak": 5000.0,
                 "unit": "TOP/s", "frac": round(ops / 1e12 / 5000.0, 4),
                 "mfma_dtype": "int8",
@@ -936,7 +941,7 @@ def main():
     if not args.no_compare:
         comp = {}
         for p in PRECS:
-            if p == prec or (p == "i8x7" and not i8x7_fits(wl["grid"])):
+            if p == prec or (p in INT8_PRODUCTS and not int8_fits(wl["grid"])):
                 continue
             c = measure(p, max(3, steps // 4))
             comp[p] = {"solves_per_s": batch * len(c["lat"]) / c["T"],

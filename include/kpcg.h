@@ -60,11 +60,17 @@ enum kp_bc { KP_BC_P = 0, KP_BC_D = 1, KP_BC_N = 2, KP_BC_DN = 3, KP_BC_ND = 4 }
  * 7-bit integer digits; the 28 digit products i + j <= 6 (0-based) are summed
  * exactly in int32 and recombined in FP64, the dropped terms and digits
  * being about 2^-49 relative; intermediates are FP64 and nothing is scaled
- * per right-hand side.  I8X7 plans need every axis a multiple of 16 and at
- * most 512 (kp_plan_create returns KP_EINVAL otherwise).  The Hadamard
- * factor of eq. (4.6) is always applied in at least FP32. */
+ * per right-hand side.  I8X6 does the same with six balanced base-256
+ * digits in [-128, 127] (the image of every value truncated to 47 bits and
+ * split with carries, so the dropped parts have either sign) and the 21
+ * products i + j <= 5, a quarter fewer matrix-core operations than I8X7 at
+ * about the same accuracy (each dropped product is at most 2^-48 relative
+ * and they take either sign).  I8X7 and I8X6 plans need every axis a multiple
+ * of 16 and at most 512 (kp_plan_create returns KP_EINVAL otherwise).  The
+ * Hadamard factor of eq. (4.6) is always applied in at least FP32. */
 enum kp_prec {
-  KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2, KP_PREC_BF16X6 = 3, KP_PREC_I8X7 = 4
+  KP_PREC_F64 = 0, KP_PREC_F32 = 1, KP_PREC_BF16 = 2, KP_PREC_BF16X6 = 3, KP_PREC_I8X7 = 4,
+  KP_PREC_I8X6 = 5
 };
 
 enum kp_status {
@@ -178,7 +184,7 @@ int kp_apply_pinv(kp_plan* plan, const double* R, double* Z, int batch);
  * until the process ends; the call allocates nothing (the plan's workspace
  * is not used or created).  Its address is looked up on the first call on a
  * device.  Limit: 2 * ceil256(batch * N * e) <= KP_NOALLOC_SCRATCH_BYTES,
- * e = 8 bytes for F64 and I8X7 plans, 4 for F32 and BF16X6, 2 for BF16
+ * e = 8 bytes for F64, I8X7 and I8X6 plans, 4 for F32 and BF16X6, 2 for BF16
  * (e.g. 2^22 FP64 unknowns: 256 x 128 x 128, or 128^3 x 2); beyond it the
  * call returns KP_ENOMEM before any work (kp_last_error says how much was
  * needed).  The plan's device must be current (KP_EINVAL otherwise).  Every
@@ -393,8 +399,8 @@ int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
  * keep the whole operator in LDS and sweep row tiles with persistent blocks;
  * they serve contractions of length at most 128 only (kp_plan_set_tuning
  * refuses them for a longer axis, the autotuner skips them there).  I8X7
- * products all run one kernel (64 rows per block, one 16-column fragment
- * per step); its plans accept and report id 13 only. */
+ * and I8X6 products run their own kernels (one 16-column fragment per step);
+ * their plans accept and report id 13 only. */
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
 
 /* Per-kernel timing (the library's tracing facility).  When enabled, every
@@ -531,8 +537,8 @@ int kp_server_create(kp_server** out, size_t hbm_budget, int workers, int max_ba
  * kp_request).  Never blocks on the GPU.  Returns KP_OK or KP_EINVAL (bad
  * grid, boundary code, precision, tolerance or null eta; flags other than
  * KP_FLAG_NO_PRECOND, KP_FLAG_FLEX_BETA, KP_FLAG_RESIDUAL_ONLY and
- * KP_FLAG_NO_GRAPH (ignored); for KP_PREC_I8X7 also an axis that is not a
- * multiple of 16 or exceeds 512). */
+ * KP_FLAG_NO_GRAPH (ignored); for KP_PREC_I8X7 and KP_PREC_I8X6 also an
+ * axis that is not a multiple of 16 or exceeds 512). */
 int kp_server_submit(kp_server* srv, const kp_request* req);
 /* Moves up to `max` completions to `out` (host array), waiting up to
  * timeout_s seconds for the first one; returns how many (0 on timeout), or

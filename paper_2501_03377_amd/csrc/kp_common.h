@@ -18,7 +18,11 @@ typedef unsigned short u16;
 
 // Boundary conditions of eq. (3.1).
 enum Bc { BC_P = 0, BC_D = 1, BC_N = 2, BC_DN = 3, BC_ND = 4 };
-enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X6 = 3, PREC_I8X7 = 4 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2, PREC_BF16X6 = 3, PREC_I8X7 = 4, PREC_I8X6 = 5 };
+
+// The FP64-accurate splits on the int8 matrix cores, and their digit counts.
+__host__ __device__ constexpr bool prec_int8(int p) { return p == PREC_I8X7 || p == PREC_I8X6; }
+__host__ __device__ constexpr int prec_digits(int p) { return p == PREC_I8X6 ? 6 : 7; }
 
 // Reduction slots written by the vector and mode-product kernels, one block
 // partial per slot; reduced in a fixed order for bitwise reproducibility.

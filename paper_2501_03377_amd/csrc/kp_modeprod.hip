@@ -87,6 +87,9 @@ template <> struct MT<PREC_BF16X6> {
 template <> struct MT<PREC_I8X7> {
   using tc = double;
 };
+template <> struct MT<PREC_I8X6> {
+  using tc = double;
+};
 
 // Block = WR x WC waves (WR = 4 row groups, WC column groups); each wave owns
 // WM row fragments x WN column fragments of 16 x 16.
@@ -681,25 +684,36 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 }
 
 // ---------------------------------------------------------------------------
-// FP64-accurate products on the int8 matrix cores (PREC_I8X7), after the
-// splitting idea of Ozaki et al.: every value is a short sum of small
-// integers times powers of two, the integer products are exact on the
-// matrix cores, and only their recombination rounds.
-//   Data: each row r of X (its K values along the contracted axis) gets the
-//   power of two 2^e_r with |x| < 2^e_r and is cut into OZ_S = 7 digits,
+// FP64-accurate products on the int8 matrix cores (PREC_I8X7, PREC_I8X6),
+// after the splitting idea of Ozaki et al.: every value is a short sum of
+// small integers times powers of two, the integer products are exact on the
+// matrix cores, and only their recombination rounds.  S digits per value:
+//   S = 7 (I8X7).  Each row r of X (its K values along the contracted axis)
+//   gets the power of two 2^e_r with |x| < 2^e_r and is cut into 7 digits,
 //       x = 2^e_r sum_i a_i 128^-(i+1),  a_i integers in [-127, 127]
 //   (truncation at every step, so all digits carry the sign of x and a
 //   small value has small digits; the remainder after the seventh is below
-//   2^(e_r - 49)).  Digits of one sign matter: with two's complement digits
-//   a small negative value has large low digits, and the dropped products
-//   below would then carry the full 2^-49 scale for every such value.
+//   2^(e_r - 49)).  Digits of one sign matter here: with two's complement
+//   digits a small negative value has large low digits, and the dropped
+//   products below would then carry the full 2^-49 scale for every such
+//   value.
+//   S = 6 (I8X6).  2^e_r with |x| < 2^e_r * 126/128, the image
+//   F = trunc(x 2^(47 - e_r)) (|F| < 126 * 2^40) and its balanced base-256
+//   digits, low to high with carries,
+//       F = sum_i d_i 256^(5-i),  d_i in [-128, 127], |d_0| <= 126,
+//   so x = 2^(e_r - 47) sum_i d_i 256^(5-i) up to the truncation (below
+//   2^(e_r - 47)).  A small value still has small digits (its high digits
+//   are zero), and the digits below a cut take either sign, so the dropped
+//   products cancel rather than add.
 //   Operator: column n of B likewise with 2^f_n, packed at plan time.
-//   Product: the digit products with i + j < OZ_S are summed exactly in
-//   int32 by v_mfma_i32_16x16x64_i8, one accumulator per diagonal d = i + j
-//   (|sum| <= 7 * 127^2 * K < 2^31 for K <= 512), and recombined in FP64,
-//       y = 2^(e_r + f_n - 14) sum_d 128^-d acc_d.
-//   The error per output is a few units of 2^-49 K max|x_r| max|b_n| at
-//   worst, far below what FP64 preconditioning needs (one CG iteration).
+//   Product: the digit products with i + j < S are summed exactly in int32
+//   by v_mfma_i32_16x16x64_i8, one accumulator per diagonal d = i + j
+//   (|sum| <= 7 * 128^2 * K < 2^31 for K <= 512), and recombined in FP64,
+//       y = 2^(e_r + f_n - 14) sum_d base^-d acc_d,  base 128 or 256
+//   (for S = 6 the two 2^-47 and the 256^10 of the top diagonal give the
+//   same 2^-14).  The error per output is a few units of 2^-49 (S = 7) or
+//   2^-48 (S = 6) K max|x_r| max|b_n| at worst, far below what FP64
+//   preconditioning needs (one CG iteration).
 // The data is read from HBM once and digitised in registers (16 consecutive
 // k per lane and k-block of 64); the operator digits stream through LDS one
 // column fragment (16 columns) at a time.  Two kernels:
@@ -715,7 +729,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 // plan is a multiple of 16).  A row with a non-finite value yields NaN
 // outputs.
 // ---------------------------------------------------------------------------
-constexpr int OZ_S = 7;
+constexpr int OZ_SMAX = 7;            // most digits per value
 constexpr int OZ_BAD = 0x40000000;    // exponent marker of a non-finite row
 
 static int oz_split(int K) { return K > 256 ? 2 : 1; }
@@ -723,10 +737,10 @@ static int oz_kb_per_wave(int K) {
   const int nkb = (K + 63) / 64, ks = oz_split(K);
   return (nkb + ks - 1) / ks;
 }
-// bytes of the operator digits: column fragments x padded k-blocks x digits
+// bytes of the operator digits: column fragments x padded k-blocks x S digits
 // x 64 lanes x 16 bytes; the column exponents (int32) follow
-static size_t oz_digit_bytes(int K) {
-  return (size_t)((K + 15) / 16) * oz_split(K) * oz_kb_per_wave(K) * OZ_S * 64 * 16;
+static size_t oz_digit_bytes(int K, int S) {
+  return (size_t)((K + 15) / 16) * oz_split(K) * oz_kb_per_wave(K) * S * 64 * 16;
 }
 
 // The lane's 16 consecutive values of each of its KBW k-blocks (from kb0)
@@ -751,12 +765,24 @@ __device__ __forceinline__ void oz_load(const double* xr, int kb0, int K, int g,
   }
 }
 
-// The row's exponent e (|x| < 2^e) from its largest magnitude.
+// The row's exponent e from its largest magnitude: |x| < 2^e (S = 7), and
+// |x| < 2^e * 126/128 for the balanced split (S = 6), whose top digit must
+// stay below 127 after the carries.
+template <int S>
 __device__ __forceinline__ int oz_exponent(double mx) {
   int e = 0;
-  if (mx > 0.0) (void)frexp(mx, &e);
-  return max(e, -1021);                         // images of subnormal rows fit 49 bits too
+  if (mx > 0.0) {
+    const double m = frexp(mx, &e);
+    if (S == 6 && m >= 0.984375) ++e;
+  }
+  return max(e, -1021);                         // images of subnormal rows fit too
 }
+
+// The right shift of the 53-bit significand that gives a value's image,
+// plus the biased exponent field: 49 - e bits (S = 7) or 47 - e (S = 6)
+// below the binary point.
+template <int S>
+__device__ __forceinline__ int oz_cshift(int e) { return e + (S == 7 ? 1026 : 1028); }
 
 // Digits from the bit pattern: the image F = floor(|x| 2^(49 - e)) < 2^49 is
 // the 53-bit significand shifted right by e + 1026 - max(ef, 1) >= 4 (ef the
@@ -767,13 +793,13 @@ __device__ __forceinline__ int oz_exponent(double mx) {
 // place at a time.  xa[kb][s] holds digit s of the lane's 16 values of
 // k-block kb, four to a dword.
 template <int KBW>
-__device__ __forceinline__ void oz_digits(const d2 (&raw)[KBW][8], int cshift,
-                                          v4i (&xa)[KBW][OZ_S]) {
+__device__ __forceinline__ void oz_digits7(const d2 (&raw)[KBW][8], int cshift,
+                                           v4i (&xa)[KBW][OZ_SMAX]) {
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb)
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-      unsigned u[OZ_S][4], sg[4];
+      unsigned u[7][4], sg[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const d2 pr = raw[kb][2 * w + (c >> 1)];
@@ -797,7 +823,7 @@ __device__ __forceinline__ void oz_digits(const d2 (&raw)[KBW][8], int cshift,
       const unsigned m01 = (sg[0] & 0xffffu) | (sg[1] & 0xffff0000u);
       const unsigned m23 = (sg[2] & 0xffffu) | (sg[3] & 0xffff0000u);
 #pragma unroll
-      for (int s = 0; s < OZ_S; ++s) {
+      for (int s = 0; s < 7; ++s) {
         // (d ^ m) - m on each 16-bit half negates where m is all ones; the
         // low bytes of the four signed digits then make one dword
         const u16x2 p01 = __builtin_bit_cast(u16x2, (u[s][0] | (u[s][1] << 16)) ^ m01) -
@@ -810,14 +836,69 @@ __device__ __forceinline__ void oz_digits(const d2 (&raw)[KBW][8], int cshift,
     }
 }
 
-// The digit products of k-block kb into the diagonal sums acc[d], d = i + s;
-// consecutive products update different diagonals.
-__device__ __forceinline__ void oz_products(const v4i (&a)[OZ_S], const v4i (&b)[OZ_S],
-                                            v4i (&acc)[OZ_S]) {
+// Balanced digits (S = 6) from the same kind of image, F = floor(|x|
+// 2^(47 - e)) (the significand shifted right by cshift - max(ef, 1) >= 6),
+// signed.  Adding 128 to each of its five low bytes in one 64-bit add,
+// G = F + 0x8080808080, turns every low digit d into the byte d + 128 (the
+// digits in [-128, 127] of an integer are unique, and d + 128 is its byte of
+// G), so XOR 0x80 gives the two's complement digit, four at a time; the top
+// digit is G >> 40 (arithmetic), at most 126 in magnitude.  A 4 x 4 byte
+// transpose (v_perm_b32) then gathers digit s of the lane's four values.
+template <int KBW>
+__device__ __forceinline__ void oz_digits6(const d2 (&raw)[KBW][8], int cshift,
+                                           v4i (&xa)[KBW][OZ_SMAX]) {
 #pragma unroll
-  for (int i = 0; i < OZ_S; ++i)
+  for (int kb = 0; kb < KBW; ++kb)
 #pragma unroll
-    for (int s = 0; s + i < OZ_S; ++s)
+    for (int w = 0; w < 4; ++w) {
+      unsigned lo[4], hi[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const d2 pr = raw[kb][2 * w + (c >> 1)];
+        const uint64_t bits = (uint64_t)__double_as_longlong((c & 1) ? pr.y : pr.x);
+        const unsigned h = (unsigned)(bits >> 32);
+        const unsigned ef = (h >> 20) & 0x7ffu;
+        const unsigned sh = (unsigned)min(cshift - (int)max(ef, 1u), 63);
+        const uint64_t sig = ((uint64_t)((h & 0xfffffu) | (min(ef, 1u) << 20)) << 32) |
+                             (bits & 0xffffffffull);
+        const uint64_t F = sig >> sh;
+        const uint64_t m = (uint64_t)(int64_t)((int)h >> 31);   // 0 or all ones
+        const uint64_t G = ((F ^ m) - m) + 0x8080808080ull;
+        lo[c] = (unsigned)G ^ 0x80808080u;      // digits 5, 4, 3, 2 (bytes 0..3)
+        hi[c] = (unsigned)(G >> 32);            // byte 0: digit 1 + 128, byte 1: digit 0
+      }
+      // byte k of value c -> byte c of dword k (two rounds of byte pairs)
+      const unsigned l01a = __builtin_amdgcn_perm(lo[1], lo[0], 0x05010400u);
+      const unsigned l01b = __builtin_amdgcn_perm(lo[1], lo[0], 0x07030602u);
+      const unsigned l23a = __builtin_amdgcn_perm(lo[3], lo[2], 0x05010400u);
+      const unsigned l23b = __builtin_amdgcn_perm(lo[3], lo[2], 0x07030602u);
+      xa[kb][5][w] = (int)__builtin_amdgcn_perm(l23a, l01a, 0x05040100u);
+      xa[kb][4][w] = (int)__builtin_amdgcn_perm(l23a, l01a, 0x07060302u);
+      xa[kb][3][w] = (int)__builtin_amdgcn_perm(l23b, l01b, 0x05040100u);
+      xa[kb][2][w] = (int)__builtin_amdgcn_perm(l23b, l01b, 0x07060302u);
+      const unsigned h01 = __builtin_amdgcn_perm(hi[1], hi[0], 0x05010400u);
+      const unsigned h23 = __builtin_amdgcn_perm(hi[3], hi[2], 0x05010400u);
+      xa[kb][1][w] = (int)(__builtin_amdgcn_perm(h23, h01, 0x05040100u) ^ 0x80808080u);
+      xa[kb][0][w] = (int)__builtin_amdgcn_perm(h23, h01, 0x07060302u);
+    }
+}
+
+template <int KBW, int S>
+__device__ __forceinline__ void oz_digits(const d2 (&raw)[KBW][8], int cshift,
+                                          v4i (&xa)[KBW][OZ_SMAX]) {
+  if constexpr (S == 7) oz_digits7<KBW>(raw, cshift, xa);
+  else oz_digits6<KBW>(raw, cshift, xa);
+}
+
+// The digit products of k-block kb into the diagonal sums acc[d], d = i + s,
+// for i + s < S; consecutive products update different diagonals.
+template <int S>
+__device__ __forceinline__ void oz_products(const v4i (&a)[OZ_SMAX], const v4i (&b)[OZ_SMAX],
+                                            v4i (&acc)[OZ_SMAX]) {
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int s = 0; s + i < S; ++s)
       acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[s], acc[i + s], 0, 0, 0);
 }
 
@@ -833,27 +914,30 @@ __device__ __forceinline__ double ghat_fast(double s) {
   return fabs(s) < 1e-13 ? 0.0 : r;
 }
 
-// One output from its exact diagonal sums a[d]: sum_d 128^-d a[d] (Horner,
-// low diagonals first), scaled by 2^(e + f - 14); NaN for a non-finite row.
-__device__ __forceinline__ double oz_value(const int (&a)[OZ_S], int e, int f) {
-  double val = (double)a[OZ_S - 1];
+// One output from its exact diagonal sums a[d]: sum_d base^-d a[d] (Horner,
+// low diagonals first; base 128 for S = 7, 256 for S = 6), scaled by
+// 2^(e + f - 14); NaN for a non-finite row.
+template <int S>
+__device__ __forceinline__ double oz_value(const int (&a)[OZ_SMAX], int e, int f) {
+  constexpr double inv = S == 7 ? 1.0 / 128.0 : 1.0 / 256.0;
+  double val = (double)a[S - 1];
 #pragma unroll
-  for (int d = OZ_S - 2; d >= 0; --d) val = (double)a[d] + val * (1.0 / 128.0);
+  for (int d = S - 2; d >= 0; --d) val = (double)a[d] + val * inv;
   return e == OZ_BAD ? NAN : ldexp(val, e + f - 14);
 }
 
-template <int KBW, int KS>
+template <int KBW, int KS, int S>
 __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
     double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
     const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
     int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
   constexpr int NT = 256 * KS;
-  constexpr int SU = KS * KBW * OZ_S * 64;      // 16-byte units per column fragment
+  constexpr int SU = KS * KBW * S * 64;      // 16-byte units per column fragment
   constexpr int UPT = (SU + NT - 1) / NT;
   __shared__ u4 lds[2][SU];
   __shared__ double hmax[KS][4][16];
-  __shared__ v4i xch[KS == 2 ? 4 : 1][OZ_S][64];
+  __shared__ v4i xch[KS == 2 ? 4 : 1][S][64];
   __shared__ double fred[NT / 64][2];
 
   const int rhs = blockIdx.y;
@@ -882,9 +966,9 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     bad |= !(o <= DBL_MAX);
     mx = fmax(mx, o);
   }
-  const int e = oz_exponent(mx);
-  v4i xa[KBW][OZ_S];
-  oz_digits<KBW>(raw, bad ? 4096 : e + 1026, xa);
+  const int e = oz_exponent<S>(mx);
+  v4i xa[KBW][OZ_SMAX];
+  oz_digits<KBW, S>(raw, bad ? 4096 : oz_cshift<S>(e), xa);
   // exponents of this lane's output rows 4g + v (held by lane 4g + v)
   const int eo = bad ? OZ_BAD : e;
   int erow[4];
@@ -911,28 +995,28 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     const int64_t nxt = (int64_t)min(j + 1, nfr - 1) * SU;   // past the last: a reload
 #pragma unroll
     for (int q = 0; q < UPT; ++q) breg[q] = Bpk[nxt + min(tid + q * NT, SU - 1)];
-    v4i acc[OZ_S];
+    v4i acc[OZ_SMAX];
 #pragma unroll
-    for (int d = 0; d < OZ_S; ++d) acc[d] = (v4i){0, 0, 0, 0};
+    for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
 #pragma unroll
     for (int kb = 0; kb < KBW; ++kb) {
-      v4i b[OZ_S];
+      v4i b[OZ_SMAX];
 #pragma unroll
-      for (int s = 0; s < OZ_S; ++s) {
-        const u4 u = lds[buf][((kb0 + kb) * OZ_S + s) * 64 + lane];
+      for (int s = 0; s < S; ++s) {
+        const u4 u = lds[buf][((kb0 + kb) * S + s) * 64 + lane];
         b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
       }
-      oz_products(xa[kb], b, acc);
+      oz_products<S>(xa[kb], b, acc);
     }
     if constexpr (KS == 2) {
       if (h == 1) {
 #pragma unroll
-        for (int d = 0; d < OZ_S; ++d) xch[wr][d][lane] = acc[d];
+        for (int d = 0; d < S; ++d) xch[wr][d][lane] = acc[d];
       }
       __syncthreads();
       if (h == 0) {
 #pragma unroll
-        for (int d = 0; d < OZ_S; ++d) acc[d] += xch[wr][d][lane];
+        for (int d = 0; d < S; ++d) acc[d] += xch[wr][d][lane];
       }
     }
     const int n = 16 * j + l16;
@@ -943,10 +1027,10 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = r0 + 4 * g + v;
-        int a[OZ_S];
+        int a[OZ_SMAX];
 #pragma unroll
-        for (int d = 0; d < OZ_S; ++d) a[d] = acc[d][v];
-        double val = oz_value(a, erow[v], f);
+        for (int d = 0; d < S; ++d) a[d] = acc[d][v];
+        double val = oz_value<S>(a, erow[v], f);
         const double rhat = val;
         if (lc) val *= ghat_fast(rowsum[v] + lcn);
         if (gt) val *= gt[(int64_t)n * rows + (rr < rows ? rr : 0)];
@@ -998,18 +1082,18 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
 // over the rows, lc over the columns; rpart, when given, takes the spectral
 // <R, Z> and ||Z||^2), 2 the Hadamard factor from the table gt [K][rows].
 // The k half (j & 1) finishes fragment j, the other hands it its sums.
-template <int KBW, int EPI>
+template <int KBW, int EPI, int S>
 __global__ __launch_bounds__(256, 2) void mp_ozh(
     const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
     double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
     const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
     int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
   constexpr int NT = 256;
-  constexpr int SU = 2 * KBW * OZ_S * 64;       // 16-byte units per column fragment
+  constexpr int SU = 2 * KBW * S * 64;       // 16-byte units per column fragment
   constexpr int UPT = (SU + NT - 1) / NT;
   __shared__ u4 lds[SU];
   __shared__ double hmax[2][2][16];
-  __shared__ v4i xch[2][OZ_S][64];
+  __shared__ v4i xch[2][S][64];
   __shared__ double fred[NT / 64][2];
 
   const int rhs = blockIdx.y;
@@ -1055,9 +1139,9 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
     bad |= !(o <= DBL_MAX);
     mx = fmax(mx, o);
   }
-  const int e = oz_exponent(mx);
-  v4i xa[KBW][OZ_S];
-  oz_digits<KBW>(raw, bad ? 4096 : e + 1026, xa);
+  const int e = oz_exponent<S>(mx);
+  v4i xa[KBW][OZ_SMAX];
+  oz_digits<KBW, S>(raw, bad ? 4096 : oz_cshift<S>(e), xa);
   const int eo = bad ? OZ_BAD : e;
   int erow[4];
   double rowsum[4];
@@ -1075,23 +1159,23 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   double fs0 = 0.0, fs1 = 0.0;                  // spectral <R, Z> and ||Z||^2
   for (int j = 0; j < nfr; ++j) {
     const int n = 16 * j + l16;
-    v4i acc[OZ_S];
+    v4i acc[OZ_SMAX];
 #pragma unroll
-    for (int d = 0; d < OZ_S; ++d) acc[d] = (v4i){0, 0, 0, 0};
+    for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
 #pragma unroll
     for (int kb = 0; kb < KBW; ++kb) {
-      v4i b[OZ_S];
+      v4i b[OZ_SMAX];
 #pragma unroll
-      for (int s = 0; s < OZ_S; ++s) {
-        const u4 u = lds[((kb0 + kb) * OZ_S + s) * 64 + lane];
+      for (int s = 0; s < S; ++s) {
+        const u4 u = lds[((kb0 + kb) * S + s) * 64 + lane];
         b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
       }
-      oz_products(xa[kb], b, acc);
+      oz_products<S>(xa[kb], b, acc);
     }
     const int fh = j & 1;
     if (h != fh) {
 #pragma unroll
-      for (int d = 0; d < OZ_S; ++d) xch[wr][d][lane] = acc[d];
+      for (int d = 0; d < S; ++d) xch[wr][d][lane] = acc[d];
     }
     __syncthreads();                            // the fragment's digits are consumed
     if (j + 1 < nfr) stage(j + 1);
@@ -1106,14 +1190,14 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
         gv[0] = t0.x; gv[1] = t0.y; gv[2] = t1.x; gv[3] = t1.y;
       }
 #pragma unroll
-      for (int d = 0; d < OZ_S; ++d) acc[d] += xch[wr][d][lane];
+      for (int d = 0; d < S; ++d) acc[d] += xch[wr][d][lane];
       double out[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int a[OZ_S];
+        int a[OZ_SMAX];
 #pragma unroll
-        for (int d = 0; d < OZ_S; ++d) a[d] = acc[d][v];
-        double val = oz_value(a, erow[v], f);
+        for (int d = 0; d < S; ++d) a[d] = acc[d][v];
+        double val = oz_value<S>(a, erow[v], f);
         const double rhat = val;
         if constexpr (EPI == 1) {
           val *= ghat_fast(rowsum[v] + lcn);
@@ -1155,13 +1239,17 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   }
 }
 
-// Packs B (K x K, row-major, FP64) as the digits read by mp_oz: for column
-// fragment j, k-block kb (padded to the split), digit s and lane 16 g + c,
-// 16 bytes hold digit s of B[64 kb + 16 g + b][16 j + c], b = 0..15; then
-// the K column exponents f_n (max_k |B[k][n]| < 2^f_n).
-static void oz_pack(const double* B, int K, void* dst) {
+// Packs B (K x K, row-major, FP64) as the S digits read by mp_oz and mp_ozh:
+// for column fragment j, k-block kb (padded to the split), digit s and lane
+// 16 g + c, 16 bytes hold digit s of B[64 kb + 16 g + b][16 j + c],
+// b = 0..15; then the K column exponents f_n.  S = 7: the truncated base-128
+// digits of B 2^-f_n (max_k |B[k][n]| < 2^f_n).  S = 6: the balanced
+// base-256 digits of the integer image trunc(B 2^(47 - f_n)) (max_k |B[k][n]|
+// < 2^f_n * 126/128), low to high; the digits in [-128, 127] of an integer
+// are unique, so they are those the device takes from its data.
+static void oz_pack(const double* B, int K, int S, void* dst) {
   const int nkb = oz_split(K) * oz_kb_per_wave(K);
-  const size_t db = oz_digit_bytes(K);
+  const size_t db = oz_digit_bytes(K, S);
   int8_t* o = (int8_t*)dst;
   for (size_t i = 0; i < db; ++i) o[i] = 0;
   int* fx = (int*)(o + db);
@@ -1169,18 +1257,35 @@ static void oz_pack(const double* B, int K, void* dst) {
     double mx = 0.0;
     for (int k = 0; k < K; ++k) mx = std::max(mx, std::fabs(B[(size_t)k * K + n]));
     int f = 0;
-    if (mx > 0.0) (void)std::frexp(mx, &f);
+    if (mx > 0.0) {
+      const double m = std::frexp(mx, &f);
+      if (S == 6 && m >= 0.984375) ++f;
+    }
     fx[n] = f;
     const int j = n / 16, c = n % 16;
     for (int k = 0; k < K; ++k) {
-      double t = std::ldexp(B[(size_t)k * K + n], -f);
       const int kb = k / 64, g = (k % 64) / 16, b = k % 16;
-      for (int s = 0; s < OZ_S; ++s) {
-        t *= 128.0;
-        const double d = std::trunc(t);
-        t -= d;
-        const size_t unit = (((size_t)j * nkb + kb) * OZ_S + s) * 64 + 16 * g + c;
-        o[unit * 16 + b] = (int8_t)(int)d;
+      int dg[OZ_SMAX] = {0, 0, 0, 0, 0, 0, 0};
+      if (S == 7) {
+        double t = std::ldexp(B[(size_t)k * K + n], -f);
+        for (int q = 0; q < 7; ++q) {
+          t *= 128.0;
+          const double d = std::trunc(t);
+          t -= d;
+          dg[q] = (int)d;
+        }
+      } else {
+        int64_t F = (int64_t)std::trunc(std::ldexp(B[(size_t)k * K + n], 47 - f));
+        for (int q = 5; q >= 1; --q) {
+          const int64_t d = ((F + 128) & 255) - 128;
+          dg[q] = (int)d;
+          F = (F - d) / 256;                    // exact
+        }
+        dg[0] = (int)F;                         // |F| <= 126
+      }
+      for (int q = 0; q < S; ++q) {
+        const size_t unit = (((size_t)j * nkb + kb) * S + q) * 64 + 16 * g + c;
+        o[unit * 16 + b] = (int8_t)dg[q];
       }
     }
   }
@@ -1189,22 +1294,23 @@ static void oz_pack(const double* B, int K, void* dst) {
 // Rows per block of the int8 split product for a K x K operator.
 static int oz_block_rows(int K) { return oz_split(K) == 2 ? 32 : 64; }
 
-static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
+template <int S>
+static void launch_oz_t(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
                       const RhsState* st, const double* la, const double* lb, const double* lc,
                       int a1, const double* gt, double* rpart, hipStream_t s) {
   const int K = op.n[ax];
   const int rows = (int)(op.N / K);
   const char* Bp = (const char*)(fwd ? op.Bf[ax] : op.Bb[ax]);
-  const int* fx = (const int*)(Bp + oz_digit_bytes(K));
+  const int* fx = (const int*)(Bp + oz_digit_bytes(K, S));
   const int br = oz_block_rows(K);
   dim3 grid((rows + br - 1) / br, batch);
   const int kbw = oz_kb_per_wave(K), ks = oz_split(K);
 #define KP_OZ(W, S_)                                                                         \
-  hipLaunchKernelGGL((mp_oz<W, S_>), grid, dim3(256 * S_), 0, s, (const u4*)Bp, fx,          \
+  hipLaunchKernelGGL((mp_oz<W, S_, S>), grid, dim3(256 * S_), 0, s, (const u4*)Bp, fx,          \
                      (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
                      gt, rpart)
 #define KP_OZH(W, E)                                                                         \
-  hipLaunchKernelGGL((mp_ozh<W, E>), grid, dim3(256), 0, s, (const u4*)Bp, fx,               \
+  hipLaunchKernelGGL((mp_ozh<W, E, S>), grid, dim3(256), 0, s, (const u4*)Bp, fx,               \
                      (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
                      gt, rpart)
   if (ks == 1) {
@@ -1228,6 +1334,15 @@ static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* 
   }
 #undef KP_OZ
 #undef KP_OZH
+}
+
+static void launch_oz(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
+                      const RhsState* st, const double* la, const double* lb, const double* lc,
+                      int a1, const double* gt, double* rpart, hipStream_t s) {
+  if (prec_digits(op.prec) == 6)
+    launch_oz_t<6>(op, ax, fwd, X, Y, batch, st, la, lb, lc, a1, gt, rpart, s);
+  else
+    launch_oz_t<7>(op, ax, fwd, X, Y, batch, st, la, lb, lc, a1, gt, rpart, s);
 }
 
 
@@ -1264,7 +1379,7 @@ bool mp_config_fits(int id, int K) { return !mp_config_resident(id) || K <= 128;
 // fragments of 4 or more columns, in BF16 the 16 x 2 tile).
 bool mp_config_allowed(int id, int prec) {
   if (id < 0 || id >= kNumCfgs) return false;
-  if (prec == PREC_I8X7) return id == kOzCfg;   // one kernel serves every product
+  if (prec_int8(prec)) return id == kOzCfg;     // one kernel serves every product
   if (prec == PREC_F64) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
   if (prec == PREC_BF16) return id != 16;
   if (prec == PREC_BF16X6) return !(id == 3 || id == 7 || id == 11 || (id >= 15 && id <= 17));
@@ -1279,7 +1394,7 @@ void mp_config(int id, int* wn, int* wm, int* wc) {
 // block width covers K most tightly (eight waves per block), else the widest
 // single-group tile.
 int mp_default_config(int K, int prec) {
-  if (prec == PREC_I8X7) return kOzCfg;
+  if (prec_int8(prec)) return kOzCfg;
   const int frags = (K + 15) / 16;
   int best = -1, best_cb = 1 << 30;
   for (int id = 0; id < kNumCfgs; ++id) {
@@ -1303,7 +1418,7 @@ static void packed_geometry(int K, int prec, int* npk, int* nkb) {
 }
 
 size_t mp_packed_bytes(int K, int prec) {
-  if (prec == PREC_I8X7) return oz_digit_bytes(K) + (size_t)K * sizeof(int);
+  if (prec_int8(prec)) return oz_digit_bytes(K, prec_digits(prec)) + (size_t)K * sizeof(int);
   int npk, nkb;
   packed_geometry(K, prec, &npk, &nkb);
   return (size_t)nkb * chunk_k(prec) * npk * elem_size(prec) * split_terms(prec);
@@ -1329,8 +1444,8 @@ static double bf16_value(uint16_t h) {
 // the round-to-nearest remainder of the previous, from the FP64 value) as
 // three consecutive 16-byte units.
 void mp_pack(const double* B, int K, int prec, void* dst) {
-  if (prec == PREC_I8X7) {
-    oz_pack(B, K, dst);
+  if (prec_int8(prec)) {
+    oz_pack(B, K, prec_digits(prec), dst);
     return;
   }
   int npk, nkb;
@@ -1420,7 +1535,7 @@ static void launch_mp(int cls, int cfg, const PinvOps& op, int ax, bool fwd, con
                       const double* gt, hipStream_t s, double* rpart = nullptr,
                       int rscl = 0) {
   trace_begin(cls, s);
-  if constexpr (PREC == PREC_I8X7) {
+  if constexpr (prec_int8(PREC)) {
     (void)cfg;
     launch_oz(op, ax, fwd, X, Y, batch, st, la, lb, lc, a1, gt, rpart, s);
     trace_end(cls, s);
@@ -1508,7 +1623,7 @@ template <int PREC>
 static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, void* T0,
                         void* T1, int batch, const RhsState* st, hipStream_t s) {
   using tc = typename MT<PREC>::tc;
-  const int scl = (PREC == PREC_F64 || PREC == PREC_I8X7) ? 0 : 1;
+  const int scl = (PREC == PREC_F64 || prec_int8(PREC)) ? 0 : 1;
   const int dim = op.dim, ax = q % dim, last = 2 * dim - 1;
   const bool fwd = q < dim;
   void* T[2] = {T0, T1};
@@ -1571,7 +1686,7 @@ int pinv_ghat_blocks(const PinvOps& op) {
   const int q = op.dim - 1, ax = q;
   const int K = op.n[ax];
   const int64_t rows = op.N / K;
-  if (op.prec == PREC_I8X7) {   // one block per 64 (K <= 256) or 32 rows
+  if (prec_int8(op.prec)) {   // one block per 64 (K <= 256) or 32 rows
     const int br = oz_block_rows(K);
     const int64_t t = (rows + br - 1) / br;
     return t > (1 << 30) ? (1 << 30) : (int)t;
@@ -1601,6 +1716,7 @@ void pinv_product(const PinvOps& op, int q, const void* in, void* out, int batch
     case PREC_F32: product_t<PREC_F32>(op, q, in, out, batch, s); break;
     case PREC_BF16X6: product_t<PREC_BF16X6>(op, q, in, out, batch, s); break;
     case PREC_I8X7: product_t<PREC_I8X7>(op, q, in, out, batch, s); break;
+    case PREC_I8X6: product_t<PREC_I8X6>(op, q, in, out, batch, s); break;
     default: product_t<PREC_BF16>(op, q, in, out, batch, s); break;
   }
 }
@@ -1612,6 +1728,7 @@ void pinv_step(const PinvOps& op, int q, const double* R, double* Z, void* T0, v
     case PREC_F32: pinv_step_t<PREC_F32>(op, q, R, Z, T0, T1, batch, st, s); break;
     case PREC_BF16X6: pinv_step_t<PREC_BF16X6>(op, q, R, Z, T0, T1, batch, st, s); break;
     case PREC_I8X7: pinv_step_t<PREC_I8X7>(op, q, R, Z, T0, T1, batch, st, s); break;
+    case PREC_I8X6: pinv_step_t<PREC_I8X6>(op, q, R, Z, T0, T1, batch, st, s); break;
     default: pinv_step_t<PREC_BF16>(op, q, R, Z, T0, T1, batch, st, s); break;
   }
 }
@@ -1623,6 +1740,7 @@ void pinv_apply(const PinvOps& op, const double* R, double* Z, void* T0, void* T
     case PREC_F32: pinv_apply_t<PREC_F32>(op, R, Z, T0, T1, batch, st, s); break;
     case PREC_BF16X6: pinv_apply_t<PREC_BF16X6>(op, R, Z, T0, T1, batch, st, s); break;
     case PREC_I8X7: pinv_apply_t<PREC_I8X7>(op, R, Z, T0, T1, batch, st, s); break;
+    case PREC_I8X6: pinv_apply_t<PREC_I8X6>(op, R, Z, T0, T1, batch, st, s); break;
     default: pinv_apply_t<PREC_BF16>(op, R, Z, T0, T1, batch, st, s); break;
   }
 }

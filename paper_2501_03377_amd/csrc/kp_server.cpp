@@ -458,8 +458,8 @@ bool valid_request(const kp_request* r) {
   if ((double)r->nx * r->ny * r->nz >= 2147483648.0) return false;
   for (int a = 0; a < (r->nz > 1 ? 3 : 2); ++a)
     if (r->bc[a] < KP_BC_P || r->bc[a] > KP_BC_ND) return false;
-  if (r->prec < KP_PREC_F64 || r->prec > KP_PREC_I8X7) return false;
-  if (r->prec == KP_PREC_I8X7) {
+  if (r->prec < KP_PREC_F64 || r->prec > KP_PREC_I8X6) return false;
+  if (r->prec == KP_PREC_I8X7 || r->prec == KP_PREC_I8X6) {
     // the int8 split preconditioner's plans need every axis a multiple of 16
     // and at most 512
     const int n[3] = {r->nx, r->ny, r->nz};

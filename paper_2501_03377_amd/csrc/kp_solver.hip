@@ -175,7 +175,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 size_t elem_bytes(int prec) {
-  return (prec == PREC_F64 || prec == PREC_I8X7) ? 8 : (prec == PREC_BF16 ? 2 : 4);
+  return (prec == PREC_F64 || prec_int8(prec)) ? 8 : (prec == PREC_BF16 ? 2 : 4);
 }
 
 struct Layout {
@@ -304,7 +304,7 @@ int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int ba
   if (p->pc_kind == KP_PRECOND_LOWRANK) {
     op.gtab = p->lr_dev;
   } else if (part && st && !(flags & KP_FLAG_FLEX_BETA) &&
-             (p->prec == PREC_F64 || p->prec == PREC_I8X7)) {
+             (p->prec == PREC_F64 || prec_int8(p->prec))) {
     // <R, Z> by Parseval from the coefficients in the eigenbasis, which are
     // FP64-accurate only for the FP64 and the int8 split products; the FP32
     // and BF16 forms take the inner products in FP64 from R and Z in space
@@ -617,7 +617,7 @@ int solve_start(kp_ticket* t, kp_plan* p, const double* eta, double* u, int batc
                           ? p->expect_iters
                           : ((flags & KP_FLAG_NO_PRECOND)
                                  ? 8
-                                 : ((p->prec == PREC_F64 || p->prec == PREC_I8X7)
+                                 : ((p->prec == PREC_F64 || prec_int8(p->prec))
                                         ? 1
                                         : (p->prec == PREC_BF16 ? 8 : 2)));
     // a first chunk that ends where the previous solve stopped, before the
@@ -882,12 +882,12 @@ int kp_plan_create(kp_plan** out, int nx, int ny, int nz, const int bc[3], int p
   if (!out || !bc) return KP_EINVAL;
   *out = nullptr;
   if (nx < 3 || ny < 3 || !(nz >= 3 || nz == 1)) return KP_EINVAL;
-  if (prec < PREC_F64 || prec > PREC_I8X7 || max_batch < 1) return KP_EINVAL;
+  if (prec < PREC_F64 || prec > PREC_I8X6 || max_batch < 1) return KP_EINVAL;
   const int dim = nz == 1 ? 2 : 3;
   for (int a = 0; a < dim; ++a)
     if (bc[a] < 0 || bc[a] > 4) return KP_EINVAL;
   // the int8 split products digitise 16 values per lane along every axis
-  if (prec == PREC_I8X7) {
+  if (prec_int8(prec)) {
     const int n[3] = {nx, ny, nz};
     for (int a = 0; a < dim; ++a)
       if (n[a] % 16 != 0 || n[a] > 512) return KP_EINVAL;
@@ -1506,7 +1506,7 @@ int kp_plan_get_tuning(const kp_plan* p, int* cfg, int n) {
 }
 
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc) {
-  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_I8X7) return KP_EINVAL;
+  if (!wn || !wm || !wc || prec < PREC_F64 || prec > PREC_I8X6) return KP_EINVAL;
   if (!mp_config_allowed(id, prec)) return KP_EINVAL;
   mp_config(id, wn, wm, wc);
   return KP_OK;

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkpcg.so")
 
 BC = {"P": 0, "D": 1, "N": 2, "DN": 3, "ND": 4}
-PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3, "i8x7": 4}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x6": 3, "i8x7": 4, "i8x6": 5}
 
 KP_OK = 0
 KP_NOT_CONVERGED = 1

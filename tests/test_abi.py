@@ -119,20 +119,22 @@ def test_plan_size_limits_are_checked_before_any_device_call(dims):
 
 @pytest.mark.parametrize("dims", [(20, 32, 32), (32, 32, 40), (528, 16, 16), (16, 18, 1),
                                   (1024, 16, 16)])
-def test_int8_split_plans_need_axes_multiple_of_16_up_to_512(dims):
+@pytest.mark.parametrize("prec", ["i8x7", "i8x6"])
+def test_int8_split_plans_need_axes_multiple_of_16_up_to_512(dims, prec):
     # the int8 split products digitise 16 consecutive values per lane and
     # split at most two k-halves of 256 over the waves of a row tile
     from paper_2501_03377_amd.kpcg import KP_EINVAL, PREC, kp_plan_create
-    rc, _ = kp_plan_create(*dims, (1, 1, 1), PREC["i8x7"], 1, None)
+    rc, _ = kp_plan_create(*dims, (1, 1, 1), PREC[prec], 1, None)
     assert rc == KP_EINVAL, dims
 
 
 def test_int8_split_tile_id():
     # every int8 split product runs one kernel; its plans report id 13
     from paper_2501_03377_amd.kpcg import KP_EINVAL, KP_OK, PREC, kp_tile_shape
-    assert kp_tile_shape(13, PREC["i8x7"])[0] == KP_OK
-    assert kp_tile_shape(0, PREC["i8x7"])[0] == KP_EINVAL
-    assert kp_tile_shape(13, 5)[0] == KP_EINVAL
+    for p in ("i8x7", "i8x6"):
+        assert kp_tile_shape(13, PREC[p])[0] == KP_OK
+        assert kp_tile_shape(0, PREC[p])[0] == KP_EINVAL
+    assert kp_tile_shape(13, 6)[0] == KP_EINVAL
 
 
 def test_async_entry_points_reject_null_arguments():

@@ -36,7 +36,7 @@ def test_profiler_names_of_bf16_templates(bench):
     assert n("void kp::mp_kernel<2, bool _Accum, 8, 4, 2, true>") == \
         "kp::mp_kernel<2, __bf16, double, 8, 4, 2, true>"
     # everything else passes through
-    assert n("void kp::mp_ozh<4, 1>") == "kp::mp_ozh<4, 1>"
+    assert n("void kp::mp_ozh<4, 1, 7>") == "kp::mp_ozh<4, 1, 7>"
     assert n("kp::k_zm<1>") == "kp::k_zm<1>"
 
 
@@ -52,7 +52,7 @@ def _counter_file(d, counter, rows):
 def test_traffic_record_calibration_and_keys(bench, tmp_path):
     cal = bench.COPY_CAL_BYTES // 1024                # KiB
     big = 4 * cal                                     # a later, larger copy of the workload's data
-    prod = "void kp::mp_ozh<4, 1>(unsigned int __vector(4) const*, int const*)"
+    prod = "void kp::mp_ozh<4, 1, 7>(unsigned int __vector(4) const*, int const*)"
     vec = "void kp::k_zm<1>(kp::Geom, kp::ZGrid)"
     copy = "__amd_rocclr_copyBuffer"
     fetch = [(copy, 131072, cal / 2)] * bench.COPY_CAL_RUNS + [(copy, 131072, big / 2),
@@ -70,8 +70,8 @@ def test_traffic_record_calibration_and_keys(bench, tmp_path):
     assert rec["copy_fetch_kib"] == cal / 2 and rec["copy_write_kib"] == cal
     assert json.load(open(bench.traffic_path("large512")))["command"] == "cmd"
     # read factor 2, write factor 1, bytes per launch averaged over dispatches
-    got = bench.measured_traffic("large512", "kp::mp_ozh<4, 1>|2097152")
+    got = bench.measured_traffic("large512", "kp::mp_ozh<4, 1, 7>|2097152")
     assert got == pytest.approx(1100.0 * 1024 * 2 + 500.0 * 1024)
     assert bench.measured_traffic("large512", "kp::k_zm<1>") == pytest.approx(
         300.0 * 1024 * 2 + 200.0 * 1024)
-    assert bench.measured_traffic("large512", "kp::mp_ozh<4, 1>|1048576") is None
+    assert bench.measured_traffic("large512", "kp::mp_ozh<4, 1, 7>|1048576") is None

@@ -46,6 +46,7 @@ def test_warm_start_at_the_solution_makes_no_iteration(bcs):
 @pytest.mark.parametrize("prec,shape,bcs", [("f64", (20, 24, 32), ("P", "D", "DN")),
                                             ("f32", (16, 32, 48), ("N", "N", "N")),
                                             ("i8x7", (32, 32, 48), ("P", "P", "D")),
+                                            ("i8x6", (32, 48, 32), ("N", "P", "D")),
                                             ("bf16", (24, 20, 36), ("D", "P", "N")),
                                             ("f64", (40, 56), ("N", "DN"))])
 def test_warm_start_parity(prec, shape, bcs):

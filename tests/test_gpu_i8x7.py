@@ -1,6 +1,7 @@
-"""GPU parity of the FP64-accurate preconditioner on the int8 matrix cores
-(every value cut into seven 7-bit digits, 28 exact digit products): the
-application against the oracle's pseudoinverse (Algs. 6-7), and whole solves
+"""GPU parity of the FP64-accurate preconditioners on the int8 matrix cores
+(I8X7: every value cut into seven truncated 7-bit digits, 28 exact digit
+products; I8X6: six balanced base-256 digits, 21 products): the application
+against the oracle's pseudoinverse (Algs. 6-7), and whole solves
 (Algorithm 1) against the converged oracle solution."""
 
 import numpy as np
@@ -14,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 # the FP64 preconditioner's bound in the other parity tests
 PINV_TOL = 1e-12
+INT8 = ["i8x7", "i8x6"]
 
 
 def _plan(shape, bcs, prec="i8x7", max_batch=1):
@@ -33,17 +35,19 @@ def _plan(shape, bcs, prec="i8x7", max_batch=1):
     ((64, 80), ("P", "N")),               # 2D; 80 rows: a ragged row tile
     ((16, 16), ("D", "D")),
 ])
-def test_i8x7_pinv_parity(shape, bcs):
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_pinv_parity(shape, bcs, prec):
     rng = np.random.default_rng(40)
     r = rng.standard_normal(shape)
-    plan = _plan(shape, bcs)
+    plan = _plan(shape, bcs, prec=prec)
     z = to_host(plan.apply_pinv(to_dev(r)))
     plan.close()
     err = assert_close(z, oracle_pinv(r, bcs), PINV_TOL, (shape, bcs))
-    print(f"pinv i8x7 {shape} {bcs}: rel err (2-norm, max) {err[0]:.3e} {err[1]:.3e}")
+    print(f"pinv {prec} {shape} {bcs}: rel err (2-norm, max) {err[0]:.3e} {err[1]:.3e}")
 
 
-def test_i8x7_pinv_small_eigenvalue():
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_pinv_small_eigenvalue(prec):
     # (P, N, D) with a long Dirichlet axis: the smallest eigenvalue sum is
     # the Dirichlet axis's own smallest eigenvalue, 6.7e-5 at n = 384, and the
     # output is dominated by its mode.  LAPACK's eigenvalues (the oracle's)
@@ -58,38 +62,41 @@ def test_i8x7_pinv_small_eigenvalue():
     _, lam, _ = oracle.pinv_init(r.T.shape, bcs)
     mu_min = lam[2][0]                      # lambda_x(0) = lambda_y(0) = 0
     z = {}
-    for prec in ("i8x7", "f64"):
-        plan = _plan(shape, bcs, prec=prec)
-        z[prec] = to_host(plan.apply_pinv(to_dev(r)))
+    for p in (prec, "f64"):
+        plan = _plan(shape, bcs, prec=p)
+        z[p] = to_host(plan.apply_pinv(to_dev(r)))
         plan.close()
     ref = oracle_pinv(r, bcs)
     bound = PINV_TOL + 12 * np.finfo(float).eps / mu_min
-    for prec in z:
-        assert_close(z[prec], ref, bound, prec)
-    assert_close(z["i8x7"], z["f64"], PINV_TOL)
+    for p in z:
+        assert_close(z[p], ref, bound, p)
+    assert_close(z[prec], z["f64"], PINV_TOL)
 
 
-def test_i8x7_is_as_accurate_as_fp64():
-    # the split keeps about 49 bits of every row and column: its error to the
-    # exact pseudoinverse is within a small factor of the FP64 matrix cores'
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_is_as_accurate_as_fp64(prec):
+    # the splits keep 47 to 49 bits of every row and column: their error to
+    # the exact pseudoinverse is within a small factor of the FP64 matrix
+    # cores'
     shape, bcs = (32, 64, 128), ("P", "P", "DN")
     rng = np.random.default_rng(41)
     r = rng.standard_normal(shape)
     ref = oracle_pinv(r, bcs)
     err = {}
-    for prec in ("f64", "i8x7", "f32"):
-        plan = _plan(shape, bcs, prec=prec)
-        err[prec] = rel(to_host(plan.apply_pinv(to_dev(r))), ref)
+    for p in ("f64", prec, "f32"):
+        plan = _plan(shape, bcs, prec=p)
+        err[p] = rel(to_host(plan.apply_pinv(to_dev(r))), ref)
         plan.close()
     print("pinv errors", err)
-    assert err["i8x7"] <= 10 * err["f64"] + 1e-14, err
-    assert err["i8x7"] * 1e6 <= err["f32"], err
+    assert err[prec] <= 10 * err["f64"] + 1e-14, err
+    assert err[prec] * 1e6 <= err["f32"], err
 
 
 # (the long axis is not the only nonsingular one: see the small-eigenvalue test)
 @pytest.mark.parametrize("shape,bcs", [((16, 32, 64), ("D", "N", "P")),
                                        ((16, 16, 384), ("N", "D", "P"))])
-def test_i8x7_rows_of_any_magnitude(shape, bcs):
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_rows_of_any_magnitude(shape, bcs, prec):
     # every row gets its own power of two: right-hand sides from 1e-200 to
     # 1e200, and rows of one dominant entry, keep their relative accuracy;
     # each right-hand side of a batch equals its single application exactly
@@ -98,7 +105,7 @@ def test_i8x7_rows_of_any_magnitude(shape, bcs):
     r[0] *= 1e-200
     r[2] *= 1e200
     r[1, :, :, 5] *= 1e9
-    plan = _plan(shape, bcs, max_batch=3)
+    plan = _plan(shape, bcs, prec=prec, max_batch=3)
     zb = to_host(plan.apply_pinv(to_dev(r)))
     for b in range(3):
         z1 = to_host(plan.apply_pinv(to_dev(r[b])))
@@ -109,13 +116,14 @@ def test_i8x7_rows_of_any_magnitude(shape, bcs):
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 32), (16, 16, 320), (320, 16, 16)])
-def test_i8x7_nonfinite_input_gives_nonfinite_output(shape):
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_nonfinite_input_gives_nonfinite_output(shape, prec):
     # a NaN in R reaches every output, as in FP64 arithmetic (the solver's
     # non-finite checks rely on it)
     bcs = ("P", "D", "N")
     r = np.random.default_rng(43).standard_normal(shape)
     r[3, 4, 5] = np.nan
-    plan = _plan(shape, bcs)
+    plan = _plan(shape, bcs, prec=prec)
     z = to_host(plan.apply_pinv(to_dev(r)))
     plan.close()
     assert np.isnan(z).all()
@@ -127,17 +135,18 @@ def test_i8x7_nonfinite_input_gives_nonfinite_output(shape):
     ((64, 32, 96), ("P", "P", "D")),
     ((64, 96), ("D", "N")),
 ])
-def test_i8x7_solve_one_iteration(shape, bcs):
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_solve_one_iteration(shape, bcs, prec):
     # as with the FP64 pseudoinverse, one iteration reaches tol 1e-10
     from paper_2501_03377_amd import Plan
     eta = synth.charge_field(shape, ncharges=2000, seed=9)
     nx, ny, nz = grid_dims(shape)
-    plan = Plan(nx, ny, nz, bcs, prec="i8x7")
+    plan = Plan(nx, ny, nz, bcs, prec=prec)
     u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, raise_on_error=False)
     u = to_host(u)
     plan.close()
     err = rel(u, oracle_solve(eta, bcs))
-    print(f"i8x7 {shape} {bcs}: iters {res[0]['iterations']} err {err:.3e} "
+    print(f"{prec} {shape} {bcs}: iters {res[0]['iterations']} err {err:.3e} "
           f"rel_res {res[0]['rel_res']:.3e} true {res[0]['true_rel_res']:.3e}")
     assert rc == 0, res
     assert res[0]["iterations"] == 1, res
@@ -145,14 +154,15 @@ def test_i8x7_solve_one_iteration(shape, bcs):
     assert res[0]["true_rel_res"] <= 1e-10
 
 
-def test_i8x7_batch_solve_and_replay():
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_batch_solve_and_replay(prec):
     # a batch of 4 all-Neumann right-hand sides: each equals its single solve
     # bitwise, a repeated solve (graph replay) is bitwise identical, and all
     # match the oracle
     from paper_2501_03377_amd import Plan
     shape, bcs = (32, 32, 64), ("N", "N", "N")
     eta = np.stack([synth.charge_field(shape, ncharges=1000, seed=20 + b) for b in range(4)])
-    plan = Plan(64, 32, 32, bcs, prec="i8x7", max_batch=4)
+    plan = Plan(64, 32, 32, bcs, prec=prec, max_batch=4)
     ub, res, _, rc = plan.solve(to_dev(eta), tol=1e-10, raise_on_error=False)
     ub = to_host(ub)
     assert rc == 0, res

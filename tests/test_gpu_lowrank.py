@@ -11,7 +11,7 @@ from oracle.lowrank import lowrank_apply, lowrank_init
 
 pytestmark = pytest.mark.gpu
 
-PREC_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16x6": 2e-4, "i8x7": 1e-12}
+PREC_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16x6": 2e-4, "i8x7": 1e-12, "i8x6": 1e-12}
 
 
 def _plan(shape, bcs, prec="f64", max_batch=1):
@@ -30,7 +30,9 @@ def _plan(shape, bcs, prec="f64", max_batch=1):
                                                  ((48, 64), ("D", "N"), 3, "i8x7"),
                                                  ((80, 32), ("N", "P"), 5, "i8x7"),
                                                  # the table on a split axis (K > 256)
-                                                 ((320, 32), ("D", "N"), 3, "i8x7")])
+                                                 ((320, 32), ("D", "N"), 3, "i8x7"),
+                                                 ((48, 64), ("D", "N"), 3, "i8x6"),
+                                                 ((320, 32), ("D", "N"), 3, "i8x6")])
 def test_apply_parity(shape, bcs, rank, prec):
     rng = np.random.default_rng(90)
     batch = 2

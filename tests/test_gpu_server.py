@@ -114,10 +114,11 @@ def test_server_evicts_idle_plans_and_rejects_oversize():
         srv.close()
 
 
-def test_server_int8_split_requests():
-    # I8X7 requests are served like the others, in one iteration, and match
-    # the oracle; a grid the int8 split cannot take (an axis not a multiple
-    # of 16) is refused at submission, before any work is queued
+@pytest.mark.parametrize("prec", ["i8x7", "i8x6"])
+def test_server_int8_split_requests(prec):
+    # int8 split requests are served like the others, in one iteration, and
+    # match the oracle; a grid the int8 split cannot take (an axis not a
+    # multiple of 16) is refused at submission, before any work is queued
     from paper_2501_03377_amd import Server
     from paper_2501_03377_amd.kpcg import KpError
     srv = Server(hbm_budget=0, workers=2, max_batch=4)
@@ -128,10 +129,10 @@ def test_server_int8_split_requests():
         for k, (shape, bcs) in enumerate(cases):
             etas[k] = synth.charge_field(shape, ncharges=60, seed=1500 + k)
             outs[k] = np.empty(shape)
-            srv.submit(k, etas[k], bcs, tol=1e-10, prec="i8x7", u=outs[k])
+            srv.submit(k, etas[k], bcs, tol=1e-10, prec=prec, u=outs[k])
         with pytest.raises(KpError):
             srv.submit(99, synth.charge_field((20, 32, 32), ncharges=10, seed=1599),
-                       ("P", "P", "D"), prec="i8x7")
+                       ("P", "P", "D"), prec=prec)
         done = _drain(srv, len(cases))
         for k, (shape, bcs) in enumerate(cases):
             c = done[k]
@@ -193,7 +194,8 @@ def test_two_workers_mixed_plans_alone_equals_mix():
     kinds = [((32, 32, 48), ("P", "P", "DN"), "i8x7", 0, 1e-10),
              ((20, 24, 28), ("N", "N", "N"), "bf16", KP_FLAG_FLEX_BETA, 1e-10),
              ((16, 20, 24), ("D", "P", "N"), "f64", 0, 1e-10),
-             ((24, 24, 24), ("DN", "D", "P"), "f32", 0, 1e-8)]
+             ((24, 24, 24), ("DN", "D", "P"), "f32", 0, 1e-8),
+             ((16, 32, 32), ("N", "D", "P"), "i8x6", 0, 1e-10)]
     reqs = [(k % len(kinds), 1800 + k) for k in range(16)]
     srv = Server(hbm_budget=0, workers=2, max_batch=3)
     try:

@@ -236,7 +236,7 @@ def test_lowmode_certificate_stop(prec, shape, bcs):
     assert abs(b - r["err_est"]) <= 1e-3 * b, (b, r["err_est"])
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64", "bf16", "i8x7"])
+@pytest.mark.parametrize("prec", ["f32", "f64", "bf16", "i8x7", "i8x6"])
 def test_manufactured_solution_512_cube(prec):
     # the 512^3 (P, P, D) grid at full size: eta = L u for a known u (the
     # oracle's stencil, eq. 3.2), so every entry of the solve is checked

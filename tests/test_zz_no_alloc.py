@@ -13,10 +13,10 @@ pytestmark = pytest.mark.gpu
 
 # relative error of one application against the exact L^+ (as the pinv parity
 # tests use)
-PINV_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16": 5e-2, "i8x7": 1e-12}
+PINV_TOL = {"f64": 1e-12, "f32": 2e-4, "bf16": 5e-2, "i8x7": 1e-12, "i8x6": 1e-12}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "i8x7"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "i8x7", "i8x6"])
 def test_noalloc_pinv_matches_apply_pinv(prec):
     import torch
     from paper_2501_03377_amd import Plan, kpcg
