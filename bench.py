@@ -4,10 +4,11 @@ Default workload (large512; one step = one whole solve, plan cached): the
 512^3 grid, periodic in x and y, Dirichlet in z; eta = 10^6 unit point
 charges of random sign at uniformly drawn cells plus N(0, 1e-3) noise, minus
 its mean (seed 5); FP64 vectors (1 GiB each), tol 1e-10.  The headline line is
-the preconditioner on the int8 matrix cores with FP64 accuracy (I8X7: exact
-seven-digit products, FP64 recombination); the same right-hand side is then
-solved with the FP64, FP32, BF16 (flexible beta) and split-BF16 (BF16X6)
-preconditioners for the mixed-versus-FP64 comparison, and the CPU oracle
+the preconditioner on the int8 matrix cores with FP64 accuracy (I8X6: exact
+products of six balanced base-256 digits, FP64 recombination); the same
+right-hand side is then solved with the FP64, FP32, BF16 (flexible beta),
+split-BF16 (BF16X6) and seven-digit int8 (I8X7) preconditioners for the
+mixed-versus-FP64 comparison, and the CPU oracle
 computes the minimum-norm solution of the same input on the host cores, which
 every precision's result is compared with (norm-wise and element-wise).
 
@@ -69,7 +70,7 @@ WORKLOADS = {
                  steps=10, field="charges", ncharges=10_000, seed=3000,
                  desc="64 RHS on 3D 128^3, BC (N,N,N) singular, 1e4 charges + N(0,1e-3) "
                       "noise per RHS (seed 3000+b), zero mean; one batched solve per step"),
-    "large512": dict(grid=(512, 512, 512), bcs=("P", "P", "D"), batch=1, prec="i8x7", tol=1e-10,
+    "large512": dict(grid=(512, 512, 512), bcs=("P", "P", "D"), batch=1, prec="i8x6", tol=1e-10,
                  steps=10, field="charges", ncharges=1_000_000, seed=5,
                  desc="3D 512^3, BC (P,P,D), 1e6 random-sign unit charges + N(0,1e-3) "
                       "noise, zero mean, seed 5; one solve per step"),

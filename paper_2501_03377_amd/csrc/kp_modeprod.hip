@@ -745,19 +745,27 @@ static size_t oz_digit_bytes(int K, int S) {
 
 // The lane's 16 consecutive values of each of its KBW k-blocks (from kb0)
 // of one row, read once, with their largest magnitude and whether any is not
-// finite.  k-blocks past K (padding of the split) read as zeros.
+// finite.  k-blocks past K (padding of the split) read as zeros.  Every load
+// is issued unconditionally (a padding k-block reads the row's first values,
+// then zeroed) and before any is used, so that all are in flight at once.
 template <int KBW>
 __device__ __forceinline__ void oz_load(const double* xr, int kb0, int K, int g,
                                         d2 (&raw)[KBW][8], double& mx, int& bad) {
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb) {
+    const int k0 = (kb0 + kb) * 64 + 16 * g;
+    const double* src = xr + (k0 < K ? k0 : 16 * g);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) raw[kb][q] = *reinterpret_cast<const d2*>(src + 2 * q);
+  }
   mx = 0.0;
   bad = 0;
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb) {
-    const int k0 = (kb0 + kb) * 64 + 16 * g;
+    const bool in = (kb0 + kb) * 64 + 16 * g < K;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      raw[kb][q] = (d2){0.0, 0.0};
-      if (k0 < K) raw[kb][q] = *reinterpret_cast<const d2*>(xr + k0 + 2 * q);
+      if (!in) raw[kb][q] = (d2){0.0, 0.0};
       const double a = fabs(raw[kb][q].x), b = fabs(raw[kb][q].y);
       bad |= !(a <= DBL_MAX) | !(b <= DBL_MAX);
       mx = fmax(mx, fmax(a, b));
