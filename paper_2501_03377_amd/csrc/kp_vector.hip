@@ -84,6 +84,12 @@ __device__ __forceinline__ void set_scale(RhsState& s, double sq, double N) {
 // ----------------------------------------------------------------- init ----
 // slots: a continuous batch, where only JOINING right-hand sides start (the
 // others are left as they are); otherwise every right-hand side starts.
+// With N even and the arrays 16-byte aligned (every right-hand side's slice
+// then is as well), a lane reads pairs, ET pairs in flight (all issued before any is used, with
+// clamped indices), block b sweeping chunks of ET * VT pairs from ET * VT * b
+// with stride ET * VT * G.  The split depends on N only.
+constexpr int ET = 4;
+
 __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict__ eta,
                                                 double* part, int G, const RhsState* st,
                                                 int slots) {
@@ -91,8 +97,21 @@ __global__ __launch_bounds__(VT) void k_eta_sum(Geom g, const double* __restrict
   if (slots && st[rhs].done != JOINING) return;
   const double* e = eta + (int64_t)rhs * g.N;
   double v[1] = {0.0};
+  if ((g.N & 1) == 0 && ((uintptr_t)e & 15) == 0) {
+    const d2* e2 = reinterpret_cast<const d2*>(e);
+    const uint32_t n2 = (uint32_t)(g.N >> 1);
+    for (uint32_t i0 = blockIdx.x * ET * VT + threadIdx.x; i0 < n2; i0 += G * ET * VT) {
+      d2 x[ET];
+#pragma unroll
+      for (int u = 0; u < ET; ++u) x[u] = e2[min(i0 + u * VT, n2 - 1)];
+#pragma unroll
+      for (int u = 0; u < ET; ++u)
+        if (i0 + u * VT < n2) v[0] += x[u].x + x[u].y;
+    }
+  } else {
 #pragma unroll 4
-  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) v[0] += e[i];
+    for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) v[0] += e[i];
+  }
   const int sl[1] = {S_SUM};
   write_partials<1>(v, sl, part, rhs, blockIdx.x);
 }
@@ -128,14 +147,37 @@ __global__ __launch_bounds__(VT) void k_eta_center(Geom g, const double* __restr
   const int64_t off = (int64_t)rhs * g.N;
   const double m = st[rhs].mean;
   double v[2] = {0.0, 0.0};
+  if ((g.N & 1) == 0 && (((uintptr_t)(eta + off) | (uintptr_t)(R ? R + off : nullptr) |
+                          (uintptr_t)(U ? U + off : nullptr)) & 15) == 0) {
+    const d2* e2 = reinterpret_cast<const d2*>(eta + off);
+    d2* R2 = R ? reinterpret_cast<d2*>(R + off) : nullptr;
+    d2* U2 = U ? reinterpret_cast<d2*>(U + off) : nullptr;
+    const uint32_t n2 = (uint32_t)(g.N >> 1);
+    for (uint32_t i0 = blockIdx.x * ET * VT + threadIdx.x; i0 < n2; i0 += G * ET * VT) {
+      d2 x[ET];
+#pragma unroll
+      for (int u = 0; u < ET; ++u) x[u] = e2[min(i0 + u * VT, n2 - 1)];
+#pragma unroll
+      for (int u = 0; u < ET; ++u) {
+        const uint32_t i = i0 + u * VT;
+        if (i >= n2) continue;
+        const d2 r = {x[u].x - m, x[u].y - m};   // eq. (3.6); m = 0 if nonsingular
+        if (R2) R2[i] = r;                     // (a nonsingular set reads eta as R_0)
+        if (U2) U2[i] = (d2){0.0, 0.0};        // U_0 = 0 (stored only when read before
+                                               // the first iteration writes U)
+        v[0] += r.x + r.y;
+        v[1] += r.x * r.x + r.y * r.y;
+      }
+    }
+  } else {
 #pragma unroll 4
-  for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
-    const double r = eta[off + i] - m;      // eq. (3.6); m = 0 if nonsingular
-    if (R) R[off + i] = r;                  // (a nonsingular set reads eta as R_0)
-    if (U) U[off + i] = 0.0;                // U_0 = 0 (stored only when read before the
-                                            // first iteration writes U)
-    v[0] += r;
-    v[1] += r * r;
+    for (uint32_t i = blockIdx.x * VT + threadIdx.x; i < (uint32_t)g.N; i += G * VT) {
+      const double r = eta[off + i] - m;
+      if (R) R[off + i] = r;
+      if (U) U[off + i] = 0.0;
+      v[0] += r;
+      v[1] += r * r;
+    }
   }
   const int sl[2] = {S_SUM, S_SQ};
   write_partials<2>(v, sl, part, rhs, blockIdx.x);
