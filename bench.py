@@ -149,6 +149,8 @@ def launch_identity(cls, prec, grid, batch, tuning):
         # side as fill the chip once
         wn, wc = (8, 1) if tuning[q] == 20 else (4, 2)
         res_lds = {"f64": 131072, "f32": 65536, "bf16": 32768, "bf16x6": 98304}[prec]
+        if to == "__bf16":
+            res_lds += 128 * (64 + 8) * 2       # the staged output tile
         per_cu = max(1, min(4, 160 * 1024 // res_lds))
         nrb = -(-rows // 64)
         blocks = max(1, min(nrb, -(-256 * per_cu // batch))) * batch

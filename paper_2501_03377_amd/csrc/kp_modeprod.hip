@@ -500,7 +500,10 @@ __global__ __launch_bounds__(64 * WR * WC, WC == 1 ? 2 : 1) void mp_kernel(
 // next tile's rows are requested, so their loads overlap this tile's
 // products and stores.  Every output is summed over k in the same order as
 // in mp_kernel (bitwise the same product).  Spectral partials go to one slot
-// per row tile (their number depends on the grid only).
+// per row tile (their number depends on the grid only).  BF16 outputs (the
+// HBM-bound products) are staged in LDS as [column][64 rows] and written a
+// column's 128 contiguous bytes at a time, 16 bytes a thread, instead of 8
+// bytes a lane scattered over 16 columns.
 template <int PREC, class Ti, class To, int WN, int WC>
 __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
     const u4* __restrict__ Bpk, int npk, const Ti* __restrict__ X, To* __restrict__ Y, int K,
@@ -533,6 +536,10 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
   const int nrb = (rows + BR - 1) / BR;
 
   __shared__ u4 lds[KBMAX * UNITS];
+  constexpr bool STG = sizeof(To) == 2;
+  constexpr int SE = 8, BRP = BR + SE;          // elements per 16-byte chunk; padded column
+  __shared__ __attribute__((aligned(16))) To stg[STG ? CB * BRP : 1];
+  const bool stage = STG && rows % SE == 0;
   for (int su = tid; su < nkb * UNITS; su += NT) {
     const int kk = su / UNITS, u = su % UNITS, gh = u / CB;
     const int c = min(u % CB, npk - 1);
@@ -633,6 +640,14 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
           ts[1] += zhat * zhat;
         }
       }
+      if constexpr (STG) {
+        if (stage) {
+          // the four rows of this lane are consecutive
+          To* q = stg + (cw + 16 * j + l16) * BRP + wr * 16 + M::row(lane, 0);
+          *reinterpret_cast<bf4*>(q) = (bf4){out[0], out[1], out[2], out[3]};
+          continue;
+        }
+      }
       bool done_store = false;
       if constexpr (PREC != PREC_F64) {
         if ((rows & 3) == 0 && rr[3] < rows) {
@@ -654,6 +669,21 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           if (rr[v] < rows) dst[rr[v]] = out[v];
+      }
+    }
+    if constexpr (STG) {
+      if (stage) {
+        __syncthreads();
+        constexpr int CPC = BR / SE;            // 16-byte chunks per column
+        const int nvalid = min(CB, K);
+        for (int c = tid; c < CB * CPC; c += NT) {
+          const int col = c / CPC, part = c - col * CPC;
+          const int row = rw - wr * 16 + part * SE;   // the tile's first row + 8 part
+          if (col >= nvalid || row >= rows) continue;  // (rows is a multiple of SE)
+          *reinterpret_cast<u4*>(Yb + (int64_t)col * rows + row) =
+              *reinterpret_cast<const u4*>(stg + col * BRP + part * SE);
+        }
+        __syncthreads();                        // the next tile stages over it
       }
     }
     if (rpart) {
@@ -1525,9 +1555,10 @@ static void launch_res(const PinvOps& op, int ax, bool fwd, const void* X, void*
   const int nrb = (rows + BR - 1) / BR;
   int npk, nkb;
   packed_geometry(K, PREC, &npk, &nkb);
-  constexpr int per_cu = (160 * 1024) / res_lds_bytes<PREC>() < 1 ? 1
-                         : ((160 * 1024) / res_lds_bytes<PREC>() > 4 ? 4
-                            : (160 * 1024) / res_lds_bytes<PREC>());
+  // LDS per block: the operator, and for BF16 outputs the staged tile
+  constexpr int lds_b = res_lds_bytes<PREC>() + (sizeof(To) == 2 ? 128 * (WR * 16 + 8) * 2 : 0);
+  constexpr int per_cu = (160 * 1024) / lds_b < 1 ? 1
+                         : ((160 * 1024) / lds_b > 4 ? 4 : (160 * 1024) / lds_b);
   const int want = (256 * per_cu + batch - 1) / batch;
   const int nblk = std::max(1, std::min(nrb, want));
   dim3 grid(nblk, batch);
