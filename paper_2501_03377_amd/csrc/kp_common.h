@@ -32,6 +32,8 @@ enum Slot {
   S_DOT,       // inner product
   S_AUX,       // second sum of squares (||U||^2)
   S_AUX2,      // <R_old, Z> for the flexible beta
+  S_TSQ,       // ||eta_c - L U_1||^2 from the first U/R update (exit step's sums)
+  S_TSUM,      // sum of U_1, from the same pass
   NSLOTS
 };
 

@@ -144,10 +144,13 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 // A right-hand side's first iteration takes U_0 = 0 without reading it
 // (unless it was a warm start); r0: if not null, R_{s-1} is read from it
 // (R_0 = eta of a nonsingular set, in a solve's first iteration).  Right-hand
-// sides without a preconditioned residual yet are skipped.
+// sides without a preconditioned residual yet are skipped.  first: the
+// solve's first iteration from U_0 = 0, whose update also takes the exit
+// step's sums of U_1 (the exit step then skips its pass for a right-hand side
+// that stopped there).
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, const double* r0);
+                      int flags, hipStream_t s, const double* r0, bool first);
 // gate: a continuous batch, where only right-hand sides whose solve ended
 // run their exit step, once; the mirror is written for all.
 void launch_finish(const Geom& g, const double* eta, double* U, double* part, RhsState* st,

@@ -488,7 +488,7 @@ struct SolveRun {
   void iteration_head(bool first_iter, bool with_cert) {
     const bool u0 = first_iter && !t->warm;
     launch_iter_head(p->g, P, W, R, t->u, part, st, p->hist_dev, t->hs, t->batch, G, t->tol,
-                     t->flags, s, (u0 && !p->g.singular) ? t->eta : nullptr);
+                     t->flags, s, (u0 && !p->g.singular) ? t->eta : nullptr, u0);
     if (t->diag) launch_diag(p->g, t->eta, t->u, part, st, diag_dev, t->hs, t->batch, s);
     if (t->cert && with_cert)
       launch_cert(p->g, p->cert, R, (double*)(base + L.C1), (double*)(base + L.C2),
@@ -825,7 +825,7 @@ int slots_step(kp_plan* p, int iters, int nslots) {
                 run.s, 1);
     for (int i = 0; i < iters; ++i) {
       launch_iter_head(p->g, run.P, run.W, run.R, t.u, run.part, run.st, nullptr, 0, t.batch,
-                       run.G, t.tol, t.flags, run.s, nullptr);
+                       run.G, t.tol, t.flags, run.s, nullptr, false);
       if (t.cert)
         launch_cert(p->g, p->cert, run.R, (double*)(run.base + run.L.C1),
                     (double*)(run.base + run.L.C2), (double*)(run.base + run.L.C3), run.st,

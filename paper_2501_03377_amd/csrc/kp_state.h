@@ -53,6 +53,7 @@ struct RhsState {
   int need_cert;      // residual small enough, error bound still to be certified
   int warm;           // U_0 came from the caller (warm start): kept at exit
   int exit_gen;       // gated exit step (continuous batches): 0 due, 1 running, 2 done
+  int true_pre;       // the S_TSQ, S_TSUM sums hold the exit step's for the current U
   double u0mean;      // mean of U_0 (singular operators: the iterates keep it)
 };
 

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(VT) void k_update_p(Geom g, const double* __restric
 constexpr int STX = 64, RY = 4, STY = RY * (VT / 64);
 constexpr int NXCD = 8;
 
-enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC, ZM_DIAG, ZM_RES };
+enum ZMode { ZM_PW = 0, ZM_UR, ZM_TRUE, ZM_LAP, ZM_JAC, ZM_DIAG, ZM_RES, ZM_UR1 };
 
 struct ZGrid {
   int ntx, ntiles;    // tiles along x, tiles per plane
@@ -369,9 +369,16 @@ __device__ __forceinline__ int zload(int k, int nz, int bcz) {
 //          in a right-hand side's first iteration the previous U is 0 and is
 //          not read (unless a warm start supplied it);
 //          with eta the previous R is read from eta (R_0 of a nonsingular set)
+// ZM_UR1:  ZM_UR for the first iteration from U_0 = 0, which also takes the
+//          exit step's sums of U_1 = alpha P: the true residual
+//          R_0 - L U_1 (R_0 = eta - mean) from alpha times each loaded P value,
+//          i.e. from the very values U receives, in ZM_TRUE's order of
+//          operations and summation (S_TSQ, S_TSUM); a right-hand side not at
+//          its first iteration, or warm started, is updated as by ZM_UR
 // ZM_TRUE: P is U; partials ||(eta - mean) - L U||^2, sum U; a right-hand
 //          side that made no iteration has U = 0, which is written to U here
-//          (it was never stored) and used in place of what P holds
+//          (it was never stored) and used in place of what P holds; one whose
+//          sums the first U/R update took (true_pre) is skipped
 // ZM_LAP:  W = L P only
 // ZM_JAC:  one Jacobi(omega) step on L x = R (Sec. 4.3.1): P is x_{j-1}, W
 //          receives x_j = x_{j-1} + (R - L x_{j-1}) / (omega d), d the
@@ -396,6 +403,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     // exit step; with `gate`, only right-hand sides whose solve ended and
     // whose exit step has not run
     if (gate && !(terminal(st[rhs].done) && st[rhs].exit_gen == 0)) return;
+    if (st[rhs].true_pre) return;
   } else if (MODE != ZM_LAP && st && (st[rhs].done || (MODE != ZM_JAC && MODE != ZM_RES &&
                                                        st[rhs].pinv_count == 0))) {
     // (an iteration needs the right-hand side's first preconditioned
@@ -433,10 +441,12 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   // no cell is both read through P and written through U
   const bool uz = MODE == ZM_TRUE && st[rhs].iter == 0 && !st[rhs].warm;
   const double* p = (uz ? eta : P) + off;
-  const double alpha = (MODE == ZM_UR) ? st[rhs].alpha : 0.0;
+  constexpr bool UR = MODE == ZM_UR || MODE == ZM_UR1;
+  const double alpha = UR ? st[rhs].alpha : 0.0;
   // U/R update of a right-hand side's first iteration: U_0 = 0 is not read
   // (unless a warm start supplied it)
-  const bool ufirst = MODE == ZM_UR && st[rhs].iter == 0 && !st[rhs].warm;
+  const bool ufirst = UR && st[rhs].iter == 0 && !st[rhs].warm;
+  const bool tfirst = MODE == ZM_UR1 && ufirst;   // block-uniform
   const double mean =
       (MODE == ZM_TRUE || MODE == ZM_DIAG || MODE == ZM_RES) ? st[rhs].mean : 0.0;
   const int kb = grp * zg.pb, ke = run ? min(kb + zg.pb, nz) : kb;
@@ -459,14 +469,14 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
   };
 
   // the other streams of a mode (R and U, or eta, or R) at the cells of plane kk
-  constexpr bool XS = MODE == ZM_UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG ||
+  constexpr bool XS = UR || MODE == ZM_TRUE || MODE == ZM_JAC || MODE == ZM_DIAG ||
                       MODE == ZM_RES;
   auto extra = [&](int kk, double (&a)[RY], double (&b)[RY]) {
     const uint32_t base = (uint32_t)kk * plane;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int64_t idx = off + base + (uint32_t)min(y0 + r, ny - 1) * nx + ic;
-      if (MODE == ZM_UR) {
+      if (UR) {
         a[r] = eta ? eta[idx] : R[idx];   // R_0 = eta (nonsingular) is never stored
         b[r] = ufirst ? 0.0 : U[idx];
       } else if (MODE == ZM_JAC) {
@@ -477,13 +487,13 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     }
   };
 
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
   double pv[RY], cv[RY], nv[RY], nn[RY], ea[RY], eb[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) pv[r] = cv[r] = nv[r] = nn[r] = ea[r] = eb[r] = 0.0;
   // halo lookahead in planes: two, except for the U/R update, whose extra
   // streams leave no registers for it at four waves per SIMD
-  constexpr int HA = MODE == ZM_UR ? 1 : 2;
+  constexpr int HA = UR ? 1 : 2;
   double hlo = 0.0, hhi = 0.0, hed = 0.0;      // halo of plane k
   double h1lo = 0.0, h1hi = 0.0, h1ed = 0.0;   // halo of plane k + 1 (HA == 2)
   if (kb < ke) {
@@ -522,10 +532,23 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
       if (r >= re) vyh = twall ? ghost_hi(bcy, cc) : hhi;
       double wv = (2.0 * cc - vxl) - vxh;
       wv += (2.0 * cc - vyl) - vyh;
+      double vzl = 0.0, vzh = 0.0;
       if (three) {
-        const double vzl = k > 0 || bcz == BC_P ? pv[r] : ghost_lo(bcz, cc);
-        const double vzh = k < nz - 1 || bcz == BC_P ? nv[r] : ghost_hi(bcz, cc);
+        vzl = k > 0 || bcz == BC_P ? pv[r] : ghost_lo(bcz, cc);
+        vzh = k < nz - 1 || bcz == BC_P ? nv[r] : ghost_hi(bcz, cc);
         wv += (2.0 * cc - vzl) - vzh;
+      }
+      // L U_1 from the values U_1 = alpha P takes at the cell and its
+      // neighbours (ghosts follow: alpha times a ghost is the ghost of U_1);
+      // each product is rounded before it is subtracted, as U_1 is stored
+      // rounded (no fused multiply-add in this block)
+      double wt = 0.0;
+      if (MODE == ZM_UR1 && tfirst) {
+#pragma clang fp contract(off)
+        const double uc = alpha * cc;
+        wt = (2.0 * uc - alpha * vxl) - alpha * vxh;
+        wt += (2.0 * uc - alpha * vyl) - alpha * vyh;
+        if (three) wt += (2.0 * uc - alpha * vzl) - alpha * vzh;
       }
       if (col_ok && r <= re) {
         const int64_t idx = off + pbase + (uint32_t)(y0 + r) * nx + i;
@@ -533,7 +556,7 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           a0 += wv * cc;
           a1 += wv;
           if (W) W[idx] = wv;
-        } else if (MODE == ZM_UR) {
+        } else if (UR) {
           const double u = eb[r] + alpha * cc;    // U_s = U_{s-1} + alpha_s P_{s-1}
           const double rr = ea[r] - alpha * wv;   // R_s = R_{s-1} - alpha_s W_s
           U[idx] = u;
@@ -541,6 +564,11 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
           a0 += rr;
           a1 += rr * rr;
           a2 += u * u;
+          if (MODE == ZM_UR1 && tfirst) {
+            const double rt = ea[r] - wt;         // R_0 - L U_1, as ZM_TRUE forms it
+            a3 += rt * rt;
+            a4 += u;                              // U_1 = 0 + alpha P, as stored
+          }
         } else if (MODE == ZM_TRUE) {
           const double rr = (ea[r] - mean) - (uz ? 0.0 : wv);
           a0 += rr * rr;
@@ -595,6 +623,10 @@ __global__ __launch_bounds__(VT) void k_zm(Geom g, ZGrid zg, const double* __res
     double v[3] = {a0, a1, a2};
     const int sl[3] = {S_SUM, S_SQ, S_AUX};
     write_partials<3>(v, sl, part, rhs, b);
+  } else if (MODE == ZM_UR1) {
+    double v[5] = {a0, a1, a2, a3, a4};
+    const int sl[5] = {S_SUM, S_SQ, S_AUX, S_TSQ, S_TSUM};
+    write_partials<5>(v, sl, part, rhs, b);
   } else if (MODE == ZM_PW) {
     double v[2] = {a0, a1};
     const int sl[2] = {S_DOT, S_SUM};
@@ -659,9 +691,11 @@ __global__ __launch_bounds__(VT) void k_fin_alpha(Geom g, const double* part, Rh
   s.hs_ring[(s.iter + 1) % HS_DELAY] = t;
 }
 
+// fused: the update was ZM_UR1, whose exit-step sums hold for a right-hand
+// side at its first iteration from U_0 = 0 (any later update voids them).
 __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsState* st,
                                                 double* hist, int hist_stride, int G, double tol,
-                                                int flags) {
+                                                int flags, int fused) {
   const int rhs = blockIdx.x;
   if (st[rhs].done || st[rhs].pinv_count == 0) return;   // as the U/R update
   double v[3];
@@ -674,6 +708,7 @@ __global__ __launch_bounds__(VT) void k_fin_res(Geom g, const double* part, RhsS
   // ||U_s||^2 of the zero-mean iterate: the updates have zero mean on a
   // singular set, so U_s keeps the mean of a warm start U_0 (removed at exit)
   s.uu = s.warm ? fmax(v[2] - (double)g.N * s.u0mean * s.u0mean, 0.0) : v[2];
+  s.true_pre = (fused && s.iter == 0 && !s.warm) ? 1 : 0;
   s.iter += 1;
   s.need_cert = 0;   // a certificate applies to this iterate only
   s.rel_res = sqrt(v[1] / s.h2);
@@ -747,7 +782,9 @@ __global__ __launch_bounds__(VT) void k_fin_true(Geom g, const double* part, Rhs
   const int rhs = blockIdx.x;
   const bool run = !gate || (terminal(st[rhs].done) && st[rhs].exit_gen == 0);
   double v[2] = {0.0, 0.0};
-  const int sl[2] = {S_SQ, S_SUM};
+  // the sums of the first U/R update when they hold for U, else ZM_TRUE's
+  const bool pre = st[rhs].true_pre;
+  const int sl[2] = {pre ? S_TSQ : S_SQ, pre ? S_TSUM : S_SUM};
   if (run) read_partials<2>(part, rhs, sl, G, v);
   if (threadIdx.x != 0) return;
   RhsState& s = st[rhs];
@@ -877,7 +914,7 @@ void launch_after_pinv(const Geom& g, const double* R, const double* Z, const do
 
 void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U, double* part,
                       RhsState* st, double* hist, int hist_stride, int batch, int G, double tol,
-                      int flags, hipStream_t s, const double* r0) {
+                      int flags, hipStream_t s, const double* r0, bool first) {
   const ZGrid z = zgrid_for(g);
   const int Gz = z.nblocks;
   dim3 zgrid(z.nblocks, batch);
@@ -890,13 +927,18 @@ void launch_iter_head(const Geom& g, double* P, double* W, double* R, double* U,
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_alpha, dim3(batch), dim3(VT), 0, s, g, part, st, Gz);
   trace_end(KC_FINALIZE, s);
+  // a solve's first iteration from U_0 = 0 also takes the exit step's sums
   trace_begin(KC_UPDATE_UR, s);
-  hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P, (double*)nullptr,
-                     R, U, r0, part, (const RhsState*)st, 0.0, 0);
+  if (first)
+    hipLaunchKernelGGL(k_zm<ZM_UR1>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
+                       (double*)nullptr, R, U, r0, part, (const RhsState*)st, 0.0, 0);
+  else
+    hipLaunchKernelGGL(k_zm<ZM_UR>, zgrid, dim3(VT), 0, s, g, z, (const double*)P,
+                       (double*)nullptr, R, U, r0, part, (const RhsState*)st, 0.0, 0);
   trace_end(KC_UPDATE_UR, s);
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_res, dim3(batch), dim3(VT), 0, s, g, part, st, hist, hist_stride, Gz,
-                     tol, flags);
+                     tol, flags, first ? 1 : 0);
   trace_end(KC_FINALIZE, s);
   (void)G;
 }

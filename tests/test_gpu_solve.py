@@ -435,3 +435,37 @@ def test_solve_with_operator_resident_tiles(prec, cfg):
         # both solves are within 1e-10 of the answer
         assert np.linalg.norm(a[k] - b[k]) <= 2e-10 * np.linalg.norm(b[k])
     plan.close()
+
+
+@pytest.mark.parametrize("prec,shape,bcs", [
+    ("f64", (33, 67, 130), ("P", "P", "DN")),
+    ("f64", (40, 40, 40), ("N", "N", "N")),
+    ("i8x6", (320, 48, 32), ("D", "N", "P")),
+    ("f32", (36, 40, 48), ("D", "N", "P")),
+])
+def test_exit_true_residual(prec, shape, bcs):
+    """The exit step's ||eta_c - L U|| / ||eta_c||.  A solve that stops after
+    its first iteration from U_0 = 0 takes it in that iteration's U/R update,
+    from alpha times the loaded P values (the values U_1 receives); it must
+    equal bitwise the per-iterate descriptor that a pass over the stored U
+    gives, as the exit step's own pass does after more iterations (f32)."""
+    from paper_2501_03377_amd import Plan
+    from paper_2501_03377_amd.kpcg import KP_FLAG_DIAGNOSTICS
+    eta = synth.charge_field(shape, ncharges=1500, seed=12)
+    nx, ny, nz = grid_dims(shape)
+    plan = Plan(nx, ny, nz, bcs, prec=prec)
+    u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=50,
+                                  flags=KP_FLAG_DIAGNOSTICS, raise_on_error=False)
+    d = plan.diagnostics()[0]
+    plan.close()
+    assert rc == 0, res
+    s = res[0]["iterations"]
+    assert s == 1 if prec != "f32" else s >= 2, res
+    assert res[0]["true_rel_res"] == d[s, 0], (res[0]["true_rel_res"], d[s, 0])
+    # and it is the residual of the returned u: the CPU's own rounding of
+    # L u is of the size of the residual itself, so only its order is fixed
+    h = eta - eta.mean() if oracle.is_singular(bcs) else eta
+    uh = to_host(u)
+    lu = oracle.apply_minus_laplacian(uh.transpose(), bcs).transpose()
+    cpu = np.linalg.norm(h - lu) / np.linalg.norm(h)
+    assert cpu / 4 <= res[0]["true_rel_res"] <= 4 * cpu + 1e-15, (res[0]["true_rel_res"], cpu)
