@@ -26,10 +26,15 @@ struct PinvOps {
   int cfg[6];           // tile configuration of each mode product, in order
   const double* gtab = nullptr;   // 2D low-rank preconditioner: G_r in place of Ghat
   double* rpart = nullptr;        // the G product also leaves <R, Z>, ||Z||^2 (spectral)
+  double* hpart = nullptr;        // int8 splits: the first product also leaves the sum and
+                                  // the sum of squares of its FP64 input (S_SUM, S_SQ)
 };
 // Blocks per right-hand side of the product that carries Ghat (the number of
 // its spectral partial sums).
 int pinv_ghat_blocks(const PinvOps& op);
+// Blocks per right-hand side of the first product of an int8 split (the
+// number of its input sums); 0 for the other precisions.
+int pinv_first_blocks(const PinvOps& op);
 
 // G_r, the best rank-r approximation of the 2D Hadamard pseudoinverse with
 // g_ij = 1/(ln_i + lq_j) (kp_lowrank.cpp, host), to tab[j*n + i]; 0 or -1.
@@ -126,10 +131,16 @@ bool launch_vector_class(int cls, const Geom& g, double* P, double* W, double* R
 // nonsingular set uses eta itself), U_0 = 0 only when U is not null (the
 // first U/R update takes it as 0 without reading it, the exit step writes it
 // for a right-hand side that made no iteration).
-// slots: a continuous batch (only JOINING right-hand sides start)
+// slots: a continuous batch (only JOINING right-hand sides start).
+// state_only: only the states are reset; the sums of eta come from the first
+// preconditioner product instead (launch_fin_h after it).
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s,
-                 int slots = 0);
+                 int slots = 0, bool state_only = false);
+// ||eta_c||^2 and its consequences (zero or non-finite right-hand sides) from
+// G block sums in the S_SUM and S_SQ slots.
+void launch_fin_h(const Geom& g, double* part, RhsState* st, double* hist, int hist_stride,
+                  int batch, int G, hipStream_t s);
 // Warm start: R_0 = eta_c - L U_0 with its sums and the stopping rule at
 // s = 0 (after launch_init without R, which gives ||eta_c||).
 void launch_warm(const Geom& g, const double* eta, const double* U, double* R, double* part,

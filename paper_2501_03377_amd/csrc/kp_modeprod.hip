@@ -964,6 +964,47 @@ __device__ __forceinline__ double oz_value(const int (&a)[OZ_SMAX], int e, int f
   return e == OZ_BAD ? NAN : ldexp(val, e + f - 14);
 }
 
+// This lane's sums of its input values (rows past the end count nothing;
+// k past the operator was loaded as 0), reduced over the wave; lane 0 leaves
+// them in red[wave].  The block adds red over its waves in order.
+template <int KBW>
+__device__ __forceinline__ void oz_input_sums(const d2 (&raw)[KBW][8], bool row_ok, int lane,
+                                              int wave, double (*red)[2]) {
+  double s1 = 0.0, s2 = 0.0;
+  if (row_ok) {
+#pragma unroll
+    for (int kb = 0; kb < KBW; ++kb)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        s1 += raw[kb][q].x + raw[kb][q].y;
+        s2 += raw[kb][q].x * raw[kb][q].x + raw[kb][q].y * raw[kb][q].y;
+      }
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    red[wave][0] = s1;
+    red[wave][1] = s2;
+  }
+}
+
+// The block's input sums (after a barrier that follows oz_input_sums) to the
+// sum and sum-of-squares slots, in wave order.
+template <int NW>
+__device__ __forceinline__ void oz_input_store(const double (*red)[2], double* part, int rhs) {
+  double t0 = 0.0, t1 = 0.0;
+  for (int w = 0; w < NW; ++w) {
+    t0 += red[w][0];
+    t1 += red[w][1];
+  }
+  slot_ptr(part, rhs, S_SUM)[blockIdx.x] = t0;
+  slot_ptr(part, rhs, S_SQ)[blockIdx.x] = t1;
+}
+
+// rpart: with the Ghat epilogue (lc), the spectral <R, Z> and ||Z||^2; in a
+// plain product (no lc, no gt), the sum and the sum of squares of X's
+// entries, one partial per block (a nonsingular right-hand side's ||eta||^2
+// when the product is the solve's first and X is eta).
 template <int KBW, int KS, int S>
 __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
@@ -993,6 +1034,8 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
   double mx;
   int bad;
   oz_load<KBW>(xr, kb0, K, g, raw, mx, bad);
+  const bool insum = rpart && !lc && !gt;
+  if (insum) oz_input_sums<KBW>(raw, r < rows, lane, wave, fred);
   mx = fmax(mx, __shfl_xor(mx, 16, 64));
   mx = fmax(mx, __shfl_xor(mx, 32, 64));
   bad |= __shfl_xor(bad, 16, 64);
@@ -1025,6 +1068,7 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
 #pragma unroll
   for (int q = 0; q < UPT; ++q) lds[0][min(tid + q * NT, SU - 1)] = breg[q];
   __syncthreads();
+  if (insum && tid == 0) oz_input_store<NT / 64>(fred, rpart, rhs);
 
   double* Yb = Y + (int64_t)rhs * N;
   double fs[2] = {0.0, 0.0};                   // spectral <R, Z> and ||Z||^2
@@ -1092,7 +1136,7 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     for (int q = 0; q < UPT; ++q) lds[buf ^ 1][min(tid + q * NT, SU - 1)] = breg[q];
     __syncthreads();
   }
-  if (rpart) {
+  if (lc && rpart) {
     // fixed-order block reduction: lanes, then waves in order
     fs[0] = wave_sum(fs[0]);
     fs[1] = wave_sum(fs[1]);
@@ -1116,9 +1160,11 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
 }
 
 // K > 256: 32 rows per block (row group wr = wave & 1, k half h = wave >> 1).
-// EPI: 0 plain, 1 the Hadamard factor Ghat from the eigenvalue sums (la, lb
-// over the rows, lc over the columns; rpart, when given, takes the spectral
-// <R, Z> and ||Z||^2), 2 the Hadamard factor from the table gt [K][rows].
+// EPI: 0 plain (rpart, when given, takes the sum and the sum of squares of
+// X's entries, as in mp_oz), 1 the Hadamard factor Ghat from the eigenvalue
+// sums (la, lb over the rows, lc over the columns; rpart, when given, takes
+// the spectral <R, Z> and ||Z||^2), 2 the Hadamard factor from the table
+// gt [K][rows].
 // The k half (j & 1) finishes fragment j, the other hands it its sums.
 template <int KBW, int EPI, int S>
 __global__ __launch_bounds__(256, 2) void mp_ozh(
@@ -1166,12 +1212,15 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   double mx;
   int bad;
   oz_load<KBW>(xr, kb0, K, g, raw, mx, bad);
+  const bool insum = EPI == 0 && rpart;
+  if (insum) oz_input_sums<KBW>(raw, r < rows, lane, wave, fred);
   mx = fmax(mx, __shfl_xor(mx, 16, 64));
   mx = fmax(mx, __shfl_xor(mx, 32, 64));
   bad |= __shfl_xor(bad, 16, 64);
   bad |= __shfl_xor(bad, 32, 64);
   if (g == 0) hmax[h][wr][l16] = bad ? INFINITY : mx;
   __syncthreads();
+  if (insum && tid == 0) oz_input_store<NT / 64>(fred, rpart, rhs);
   {
     const double o = hmax[h ^ 1][wr][l16];
     bad |= !(o <= DBL_MAX);
@@ -1672,7 +1721,8 @@ static void pinv_step_t(const PinvOps& op, int q, const double* R, double* Z, vo
                       : (ax == 0 ? KC_MP_X_BWD : (ax == 1 ? KC_MP_Y_BWD : KC_MP_Z_BWD));
   if (q == 0) {
     launch_mp<PREC, double, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, scl, 0, nullptr,
-                                nullptr, nullptr, 1, nullptr, s);
+                                nullptr, nullptr, 1, nullptr, s,
+                                prec_int8(PREC) ? op.hpart : nullptr);
   } else if (q == last) {
     launch_mp<PREC, tc, double>(cls, op.cfg[q], op, ax, fwd, in, out, batch, st, 0, scl, nullptr,
                                 nullptr, nullptr, 1, nullptr, s);
@@ -1719,6 +1769,14 @@ static void product_t(const PinvOps& op, int q, const void* in, void* out, int b
   else
     launch_mp<PREC, tc, tc>(cls, op.cfg[q], op, ax, fwd, in, out, batch, nullptr, 0, 0, la, lb,
                             lc, op.n[0], nullptr, s);
+}
+
+int pinv_first_blocks(const PinvOps& op) {
+  if (!prec_int8(op.prec)) return 0;
+  const int K = op.n[0];
+  const int64_t rows = op.N / K, br = oz_block_rows(K);
+  const int64_t t = (rows + br - 1) / br;
+  return t > (1 << 30) ? (1 << 30) : (int)t;
 }
 
 int pinv_ghat_blocks(const PinvOps& op) {

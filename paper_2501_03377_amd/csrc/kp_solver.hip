@@ -286,9 +286,19 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // of <R, Z> and ||Z||^2 (spectral, Gdot blocks) -- then Z has zero mean and,
 // if `z0` is given, the result goes to z0 instead of Z (the first
 // application writes P_0 = Z_0 directly).
+// h_fold (the first application of a solve whose eta is R_0, int8 split
+// pseudoinverse): the first product also leaves eta's sums in the S_SUM and
+// S_SQ slots, and ||eta||^2 is finished from them before the second product
+// (in place of a pass over eta before the application).
+struct HFold {
+  RhsState* st;
+  double* hist;
+  int hist_stride;
+};
+
 int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int batch, int flags,
                  const RhsState* st, hipStream_t s, double* part = nullptr,
-                 double* z0 = nullptr) {
+                 double* z0 = nullptr, const HFold* h_fold = nullptr) {
   char* base = (char*)p->ws;
   if (flags & KP_FLAG_NO_PRECOND) {
     launch_copy(p->g, R, Z, st, batch, vec_blocks(p->g.N, batch), s);
@@ -314,7 +324,18 @@ int precondition(kp_plan* p, const Layout& L, const double* R, double* Z, int ba
       Gdot = b;
     }
   }
-  pinv_apply(op, R, (Gdot > 0 && z0) ? z0 : Z, base + L.T0, base + L.T1, batch, st, s);
+  double* out = (Gdot > 0 && z0) ? z0 : Z;
+  if (h_fold && part) {
+    op.hpart = part;
+    pinv_step(op, 0, R, out, base + L.T0, base + L.T1, batch, st, s);
+    op.hpart = nullptr;
+    launch_fin_h(p->g, part, h_fold->st, h_fold->hist, h_fold->hist_stride, batch,
+                 pinv_first_blocks(op), s);
+    for (int q = 1; q < 2 * op.dim; ++q)
+      pinv_step(op, q, R, out, base + L.T0, base + L.T1, batch, st, s);
+    return Gdot;
+  }
+  pinv_apply(op, R, out, base + L.T0, base + L.T1, batch, st, s);
   return Gdot;
 }
 
@@ -462,20 +483,33 @@ struct SolveRun {
     // update, which stores R_1 in R); a warm start stores eta_c - L U_0
     R0 = (p->g.singular || t->warm) ? R : t->eta;
   }
+  // ||eta||^2 taken by the first product of the first application: the int8
+  // splits read eta itself there (a nonsingular set from U_0 = 0) and apply
+  // no input scale, so nothing before that product needs it
+  bool fold_h() const {
+    if (!prec_int8(p->prec) || p->pc_kind != KP_PRECOND_PINV || p->g.singular || t->warm ||
+        t->diag || (t->flags & KP_FLAG_NO_PRECOND))
+      return false;
+    const int b = pinv_first_blocks(p->op);
+    return b > 0 && b <= GMAX;
+  }
   // R_0, Z_0 = M(R_0), rho_0, P_0 = Z_0
   void head() {
+    const bool fold = fold_h();
     // U_0 = 0 is stored only for the descriptors of iterate 0; R_0 = eta_c
     // only for a singular set started from zero
     launch_init(p->g, t->eta, (p->g.singular && !t->warm) ? R : nullptr,
                 (t->diag && !t->warm) ? t->u : nullptr, part, st, p->hist_dev, t->hs, t->batch,
-                G, s);
+                G, s, 0, fold);
     if (t->warm)
       launch_warm(p->g, t->eta, t->u, R, part, st, p->hist_dev, t->hs, t->batch, t->tol,
                   t->flags, s);
     if (t->diag) launch_diag(p->g, t->eta, t->u, part, st, diag_dev, t->hs, t->batch, s);
     // spectral sums: Z_0 has zero mean, so P_0 = Z_0 is written by the
     // application itself and the P update is skipped
-    const int Gdot = precondition(p, L, R0, Z, t->batch, t->flags, st, s, part, P);
+    const HFold hf{st, p->hist_dev, t->hs};
+    const int Gdot = precondition(p, L, R0, Z, t->batch, t->flags, st, s, part, P,
+                                  fold ? &hf : nullptr);
     launch_after_pinv(p->g, R0, Z, W, P, part, st, t->batch, G, 1, t->tol, t->flags, s, Gdot,
                       Gdot > 0);
   }

@@ -854,9 +854,17 @@ int vec_blocks(int64_t N, int batch) {
   return (int)g;
 }
 
+void launch_fin_h(const Geom& g, double* part, RhsState* st, double* hist, int hist_stride,
+                  int batch, int G, hipStream_t s) {
+  trace_begin(KC_FINALIZE, s);
+  hipLaunchKernelGGL(k_fin_h, dim3(batch), dim3(VT), 0, s, g, (const double*)part, st, hist,
+                     hist_stride, G, 0);
+  trace_end(KC_FINALIZE, s);
+}
+
 void launch_init(const Geom& g, const double* eta, double* R, double* U, double* part,
                  RhsState* st, double* hist, int hist_stride, int batch, int G, hipStream_t s,
-                 int slots) {
+                 int slots, bool state_only) {
   dim3 grid(G, batch);
   if (g.singular) {   // the mean of eta (eq. 3.6); a nonsingular set keeps eta as it is
     trace_begin(KC_INIT, s);
@@ -867,6 +875,7 @@ void launch_init(const Geom& g, const double* eta, double* R, double* U, double*
   trace_begin(KC_FINALIZE, s);
   hipLaunchKernelGGL(k_fin_mean, dim3(batch), dim3(VT), 0, s, g, part, st, G, slots);
   trace_end(KC_FINALIZE, s);
+  if (state_only) return;
   trace_begin(KC_INIT, s);
   hipLaunchKernelGGL(k_eta_center, grid, dim3(VT), 0, s, g, eta, R, U, part, (const RhsState*)st,
                      G, slots);

@@ -173,3 +173,36 @@ def test_int8_batch_solve_and_replay(prec):
         assert np.array_equal(ub[b], u1), b
         assert_close(ub[b], oracle_solve(eta[b], bcs), 1e-10, b)
     plan.close()
+
+
+@pytest.mark.parametrize("shape,bcs", [
+    ((48, 64, 192), ("D", "P", "N")),     # the first product on 192 (K <= 256 kernel)
+    ((64, 32, 512), ("P", "P", "D")),     # the first product on 512 (split kernel)
+    ((64, 80), ("P", "D")),               # 2D, a ragged row tile
+])
+@pytest.mark.parametrize("prec", INT8)
+def test_int8_norm_from_first_product(shape, bcs, prec):
+    # A nonsingular solve from U_0 = 0 takes ||eta||^2 from the first
+    # preconditioner product, which reads eta; with KP_FLAG_DIAGNOSTICS it
+    # comes from a pass of its own.  Only the rounding of that sum may differ:
+    # the same u, bit for bit, and residuals relative to ||eta|| equal to
+    # about the sum's rounding.
+    from paper_2501_03377_amd.kpcg import KP_FLAG_DIAGNOSTICS
+    eta = np.stack([synth.charge_field(shape, ncharges=800, seed=14),
+                    np.zeros(shape)])
+    plan = _plan(shape, bcs, prec=prec, max_batch=2)
+    out = []
+    for flags in (0, KP_FLAG_DIAGNOSTICS, 0):
+        u, res, hist, rc = plan.solve(to_dev(eta), tol=1e-10, max_iter=20, flags=flags,
+                                      raise_on_error=False)
+        assert rc == 0, res
+        out.append((to_host(u), res, hist))
+    plan.close()
+    (u0, r0, h0), (u1, r1, h1), (u2, r2, _) = out
+    assert np.array_equal(u0, u1) and np.array_equal(u0, u2)
+    assert np.array_equal(u0[1], np.zeros(shape)) and r0[1]["iterations"] == 0
+    assert r0[0]["iterations"] == r1[0]["iterations"] >= 1
+    assert h0[0, 0] == 1.0
+    for key in ("rel_res", "true_rel_res"):
+        assert abs(r0[0][key] - r1[0][key]) <= 1e-13 * r1[0][key], (key, r0[0], r1[0])
+        assert r0[0][key] == r2[0][key]

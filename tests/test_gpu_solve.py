@@ -336,7 +336,7 @@ def test_small_2d_path_agrees_with_general_path(bcs):
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "i8x6"])
 @pytest.mark.parametrize("bcs", [("D", "N", "P"), ("N", "N", "N")])
 def test_rhs_without_iterations_returns_zero_over_garbage(prec, bcs):
     # U_0 = 0 is never stored: a right-hand side that stops before its first
@@ -346,12 +346,14 @@ def test_rhs_without_iterations_returns_zero_over_garbage(prec, bcs):
     import torch
     from paper_2501_03377_amd import KP_ENONFINITE, Plan
     from paper_2501_03377_amd.kpcg import KP_FLAG_NO_GRAPH
-    shape = (12, 10, 16)
+    # (the int8 splits take axes that are multiples of 16; there a
+    # nonsingular set's ||eta|| comes from the first product)
+    shape = (16, 32, 16) if prec == "i8x6" else (12, 10, 16)
     rng = np.random.default_rng(21)
     eta = np.stack([rng.standard_normal(shape), np.full(shape, 2.5 if oracle.is_singular(bcs) else 0.0),
                     rng.standard_normal(shape), np.ones(shape)])
     eta[3, 1, 2, 3] = np.inf
-    plan = Plan(16, 10, 12, bcs, prec=prec, max_batch=4)
+    plan = Plan(shape[2], shape[1], shape[0], bcs, prec=prec, max_batch=4)
     e = to_dev(eta)
     for flags in (0, KP_FLAG_NO_GRAPH, 0):
         u = torch.full_like(e, float("nan"))
