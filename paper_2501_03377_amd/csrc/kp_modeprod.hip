@@ -760,6 +760,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void mp_res(
 // outputs.
 // ---------------------------------------------------------------------------
 constexpr int OZ_SMAX = 7;            // most digits per value
+constexpr int OZ_KMAX = 512;          // longest axis the int8 splits serve (plan check)
 constexpr int OZ_BAD = 0x40000000;    // exponent marker of a non-finite row
 
 static int oz_split(int K) { return K > 256 ? 2 : 1; }
@@ -1018,6 +1019,8 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
   __shared__ double hmax[KS][4][16];
   __shared__ v4i xch[KS == 2 ? 4 : 1][S][64];
   __shared__ double fred[NT / 64][2];
+  __shared__ int sfx[OZ_KMAX];                  // the column exponents and eigenvalues
+  __shared__ double slc[OZ_KMAX];               // of the epilogue, read once
 
   const int rhs = blockIdx.y;
   if (st && st[rhs].done) return;
@@ -1067,6 +1070,10 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
   for (int q = 0; q < UPT; ++q) breg[q] = Bpk[min(tid + q * NT, SU - 1)];
 #pragma unroll
   for (int q = 0; q < UPT; ++q) lds[0][min(tid + q * NT, SU - 1)] = breg[q];
+  for (int i = tid; i < K; i += NT) {
+    sfx[i] = fexp[i];
+    if (lc) slc[i] = lc[i];
+  }
   __syncthreads();
   if (insum && tid == 0) oz_input_store<NT / 64>(fred, rpart, rhs);
 
@@ -1103,8 +1110,8 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     }
     const int n = 16 * j + l16;
     if (h == 0 && n < K) {
-      const int f = fexp[n];
-      const double lcn = lc ? lc[n] : 0.0;
+      const int f = sfx[n];
+      const double lcn = lc ? slc[n] : 0.0;
       double out[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1179,6 +1186,8 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   __shared__ double hmax[2][2][16];
   __shared__ v4i xch[2][S][64];
   __shared__ double fred[NT / 64][2];
+  __shared__ int sfx[OZ_KMAX];                  // the column exponents and eigenvalues
+  __shared__ double slc[EPI == 1 ? OZ_KMAX : 1];  // of the epilogue, read once
 
   const int rhs = blockIdx.y;
   if (st && st[rhs].done) return;
@@ -1238,6 +1247,10 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
     const int rr = r0 + 4 * g + v, rc = rr < rows ? rr : 0;
     rowsum[v] = EPI == 1 ? la[rc % a1] + (lb ? lb[rc / a1] : 0.0) : 0.0;
   }
+  for (int i = tid; i < K; i += NT) {
+    sfx[i] = fexp[i];
+    if constexpr (EPI == 1) slc[i] = lc[i];
+  }
   __builtin_amdgcn_s_waitcnt(0);                // the first fragment has landed
   __syncthreads();
 
@@ -1267,8 +1280,8 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
     __syncthreads();                            // the fragment's digits are consumed
     if (j + 1 < nfr) stage(j + 1);
     if (h == fh) {
-      const int f = fexp[n];
-      const double lcn = EPI == 1 ? lc[n] : 0.0;
+      const int f = sfx[n];
+      const double lcn = EPI == 1 ? slc[n] : 0.0;
       double gv[4] = {0.0, 0.0, 0.0, 0.0};
       if constexpr (EPI == 2) {
         const d2* src =
