@@ -197,14 +197,21 @@ def test_two_workers_mixed_plans_alone_equals_mix():
              ((24, 24, 24), ("DN", "D", "P"), "f32", 0, 1e-8),
              ((16, 32, 32), ("N", "D", "P"), "i8x6", 0, 1e-10)]
     reqs = [(k % len(kinds), 1800 + k) for k in range(16)]
+    # every input is on the device before the first submission, so that the
+    # requests queue up together (built one by one between submissions, they
+    # could each be served before the next arrives, and never overlap)
+    etas, devs, outs = {}, {}, {}
+    for rid, (kind, seed) in enumerate(reqs):
+        shape = kinds[kind][0]
+        etas[rid] = synth.charge_field(shape, ncharges=100, seed=seed)
+        devs[rid] = to_dev(etas[rid])
+        outs[rid] = torch.empty(shape, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
     srv = Server(hbm_budget=0, workers=2, max_batch=3)
     try:
-        outs, etas = {}, {}
         for rid, (kind, seed) in enumerate(reqs):
             shape, bcs, prec, fl, tol = kinds[kind]
-            etas[rid] = synth.charge_field(shape, ncharges=100, seed=seed)
-            outs[rid] = torch.empty(shape, dtype=torch.float64, device="cuda")
-            srv.submit(rid, to_dev(etas[rid]), bcs, tol=tol, prec=prec, flags=fl, u=outs[rid])
+            srv.submit(rid, devs[rid], bcs, tol=tol, prec=prec, flags=fl, u=outs[rid])
         done = _drain(srv, len(reqs))
         assert all(c["status"] == 0 for c in done.values()), done
         assert len({c["worker"] for c in done.values()}) == 2
