@@ -1257,6 +1257,16 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   double* Yb = Y + (int64_t)rhs * N;
   const bool rows_ok = r0 < rows;               // the row group lies inside (rows % 16 == 0)
   double fs0 = 0.0, fs1 = 0.0;                  // spectral <R, Z> and ||Z||^2
+  // Ghat of this lane's four outputs in the next fragment the wave finishes:
+  // a wave computes them while the other k half finishes the fragment
+  // between (fragment 0: here)
+  double gn[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (EPI == 1) {
+    if (h == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gn[v] = ghat_fast(rowsum[v] + slc[l16]);
+    }
+  }
   for (int j = 0; j < nfr; ++j) {
     const int n = 16 * j + l16;
     v4i acc[OZ_SMAX];
@@ -1279,9 +1289,15 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
     }
     __syncthreads();                            // the fragment's digits are consumed
     if (j + 1 < nfr) stage(j + 1);
+    if constexpr (EPI == 1) {
+      if (h != fh && j + 1 < nfr) {
+        const double lcn = slc[16 * (j + 1) + l16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gn[v] = ghat_fast(rowsum[v] + lcn);
+      }
+    }
     if (h == fh) {
       const int f = sfx[n];
-      const double lcn = EPI == 1 ? slc[n] : 0.0;
       double gv[4] = {0.0, 0.0, 0.0, 0.0};
       if constexpr (EPI == 2) {
         const d2* src =
@@ -1300,7 +1316,7 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
         double val = oz_value<S>(a, erow[v], f);
         const double rhat = val;
         if constexpr (EPI == 1) {
-          val *= ghat_fast(rowsum[v] + lcn);
+          val *= gn[v];
           fs0 += rows_ok ? rhat * val : 0.0;
           fs1 += rows_ok ? val * val : 0.0;
         }
