@@ -136,9 +136,16 @@ def launch_identity(cls, prec, grid, batch, tuning):
         # per 32 rows, the epilogue kind (1: the Hadamard factor) and the
         # digit count parameters
         nkb, S = -(-K // 64), 7 if prec == "i8x7" else 6
+        epi = 1 if q == dim - 1 else 0
+        nrb = -(-rows // 128)
+        if K <= 128 and nrb * 8 <= 8192:
+            # operator-resident: persistent blocks of 8 waves, one or two per CU
+            lds = nkb * 4 * nkb * S * 64 * 16 + 64 * nkb * 12
+            per_cu = 2 if 2 * lds <= 160 * 1024 else 1
+            blocks = max(1, min(nrb, -(-256 * per_cu // batch))) * batch
+            return f"kp::mp_ozr<{nkb}, {epi}, {S}>|{blocks * 512}"
         if K <= 256:
             return f"kp::mp_oz<{nkb}, 1, {S}>|{-(-rows // 64) * batch * 256}"
-        epi = 1 if q == dim - 1 else 0
         return f"kp::mp_ozh<{-(-nkb // 2)}, {epi}, {S}>|{-(-rows // 32) * batch * 256}"
     tc = {"f64": "double", "f32": "float", "bf16": "__bf16", "bf16x6": "float"}[prec]
     ti = "double" if q == 0 else tc

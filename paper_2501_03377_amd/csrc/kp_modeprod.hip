@@ -784,8 +784,9 @@ __device__ __forceinline__ void oz_load(const double* xr, int kb0, int K, int g,
                                         d2 (&raw)[KBW][8], double& mx, int& bad) {
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb) {
+    // a block past K reads the row's first 16 values (K >= 16), zeroed below
     const int k0 = (kb0 + kb) * 64 + 16 * g;
-    const double* src = xr + (k0 < K ? k0 : 16 * g);
+    const double* src = xr + (k0 < K ? k0 : 0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) raw[kb][q] = *reinterpret_cast<const d2*>(src + 2 * q);
   }
@@ -794,6 +795,36 @@ __device__ __forceinline__ void oz_load(const double* xr, int kb0, int K, int g,
 #pragma unroll
   for (int kb = 0; kb < KBW; ++kb) {
     const bool in = (kb0 + kb) * 64 + 16 * g < K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (!in) raw[kb][q] = (d2){0.0, 0.0};
+      const double a = fabs(raw[kb][q].x), b = fabs(raw[kb][q].y);
+      bad |= !(a <= DBL_MAX) | !(b <= DBL_MAX);
+      mx = fmax(mx, fmax(a, b));
+    }
+  }
+}
+
+// oz_load in two halves, for a kernel that loads the next rows early: the
+// loads (issued together) and, once they are used, the masking of k past K
+// with the row's largest magnitude and finiteness.
+template <int KBW>
+__device__ __forceinline__ void oz_issue(const double* xr, int K, int g, d2 (&raw)[KBW][8]) {
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb) {
+    const int k0 = kb * 64 + 16 * g;
+    const double* src = xr + (k0 < K ? k0 : 0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) raw[kb][q] = *reinterpret_cast<const d2*>(src + 2 * q);
+  }
+}
+template <int KBW>
+__device__ __forceinline__ void oz_scan(int K, int g, d2 (&raw)[KBW][8], double& mx, int& bad) {
+  mx = 0.0;
+  bad = 0;
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb) {
+    const bool in = kb * 64 + 16 * g < K;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (!in) raw[kb][q] = (d2){0.0, 0.0};
@@ -1355,6 +1386,149 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   }
 }
 
+// K <= 128: the operator's digits, every column fragment, stay in LDS (at
+// most 112 KiB) and the block sweeps 128-row tiles, eight waves of 16 rows
+// with all of K each, so that no wave waits for another inside the sweep;
+// the next tile's rows are loaded while the current tile is multiplied.
+// Products, recombination and epilogues are those of mp_oz (bitwise the same
+// outputs).  EPI as in mp_ozh.  rpart: one partial per wave and row tile
+// (slot 8 t + wave), the spectral sums (EPI 1) or the sum and sum of squares
+// of X's entries (EPI 0).
+template <int KBW, int EPI, int S>
+__global__ __launch_bounds__(512, 1) void mp_ozr(
+    const u4* __restrict__ Bpk, const int* __restrict__ fexp, const double* __restrict__ X,
+    double* __restrict__ Y, int K, int rows, int64_t N, const RhsState* __restrict__ st,
+    const double* __restrict__ la, const double* __restrict__ lb, const double* __restrict__ lc,
+    int a1, const double* __restrict__ gt, double* __restrict__ rpart) {
+  constexpr int NT = 512, NW = NT / 64, BR = 16 * NW;
+  constexpr int FU = KBW * S * 64;              // 16-byte units per column fragment
+  constexpr int KM = 64 * KBW;                  // longest K of this instance
+  __shared__ u4 lds[(KM / 16) * FU];
+  __shared__ int sfx[KM];
+  __shared__ double slc[EPI == 1 ? KM : 1];
+
+  const int rhs = blockIdx.y;
+  if (st && st[rhs].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nfr = K / 16;                       // K is a multiple of 16 here
+  const int nrb = (rows + BR - 1) / BR;
+  const double* Xb = X + (int64_t)rhs * N;
+  double* Yb = Y + (int64_t)rhs * N;
+  for (int u = tid; u < nfr * FU; u += NT) lds[u] = Bpk[u];
+  for (int i = tid; i < K; i += NT) {
+    sfx[i] = fexp[i];
+    if constexpr (EPI == 1) slc[i] = lc[i];
+  }
+  // this lane's row of tile t (rows past the end read row 0, unused)
+  auto row_src = [&](int t) {
+    const int r = t * BR + wave * 16 + l16;
+    return Xb + (int64_t)((t < nrb && r < rows) ? r : 0) * K;
+  };
+  d2 raw[KBW][8];
+  oz_issue<KBW>(row_src(blockIdx.x), K, g, raw);
+  __syncthreads();
+
+  for (int t = blockIdx.x; t < nrb; t += gridDim.x) {
+    const int r0 = t * BR + wave * 16;
+    const bool row_ok = r0 + l16 < rows;
+    double mx;
+    int bad;
+    oz_scan<KBW>(K, g, raw, mx, bad);
+    double s0 = 0.0, s1 = 0.0;                  // input sums (EPI 0) or spectral (EPI 1)
+    if (EPI == 0 && rpart && row_ok) {
+#pragma unroll
+      for (int kb = 0; kb < KBW; ++kb)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          s0 += raw[kb][q].x + raw[kb][q].y;
+          s1 += raw[kb][q].x * raw[kb][q].x + raw[kb][q].y * raw[kb][q].y;
+        }
+    }
+    mx = fmax(mx, __shfl_xor(mx, 16, 64));
+    mx = fmax(mx, __shfl_xor(mx, 32, 64));
+    bad |= __shfl_xor(bad, 16, 64);
+    bad |= __shfl_xor(bad, 32, 64);
+    const int e = oz_exponent<S>(mx);
+    v4i xa[KBW][OZ_SMAX];
+    oz_digits<KBW, S>(raw, bad ? 4096 : oz_cshift<S>(e), xa);
+    const int eo = bad ? OZ_BAD : e;
+    int erow[4];
+    double rowsum[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      erow[v] = __shfl(eo, 4 * g + v, 64);
+      const int rr = r0 + 4 * g + v, rc = rr < rows ? rr : 0;
+      rowsum[v] = EPI == 1 ? la[rc % a1] + (lb ? lb[rc / a1] : 0.0) : 0.0;
+    }
+    // the next tile's rows, while this one is multiplied
+    oz_issue<KBW>(row_src(t + gridDim.x), K, g, raw);
+
+    for (int j = 0; j < nfr; ++j) {
+      v4i acc[OZ_SMAX];
+#pragma unroll
+      for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
+#pragma unroll
+      for (int kb = 0; kb < KBW; ++kb) {
+        v4i b[OZ_SMAX];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const u4 u = lds[((j * KBW + kb) * S + s) * 64 + lane];
+          b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+        }
+        oz_products<S>(xa[kb], b, acc);
+      }
+      const int n = 16 * j + l16;
+      const int f = sfx[n];
+      const double lcn = EPI == 1 ? slc[n] : 0.0;
+      double out[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r0 + 4 * g + v;
+        int a[OZ_SMAX];
+#pragma unroll
+        for (int d = 0; d < S; ++d) a[d] = acc[d][v];
+        double val = oz_value<S>(a, erow[v], f);
+        const double rhat = val;
+        if constexpr (EPI == 1) {
+          val *= ghat_fast(rowsum[v] + lcn);
+          if (rr < rows) {
+            s0 += rhat * val;
+            s1 += val * val;
+          }
+        }
+        if constexpr (EPI == 2) val *= gt[(int64_t)n * rows + (rr < rows ? rr : 0)];
+        out[v] = val;
+      }
+      double* dst = Yb + (int64_t)n * rows + r0 + 4 * g;
+      if ((rows & 1) == 0 && r0 + 4 * g + 3 < rows) {
+        *reinterpret_cast<d2*>(dst) = (d2){out[0], out[1]};
+        *reinterpret_cast<d2*>(dst + 2) = (d2){out[2], out[3]};
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (r0 + 4 * g + v < rows) dst[v] = out[v];
+      }
+    }
+    if (EPI != 2 && rpart) {
+      s0 = wave_sum(s0);
+      s1 = wave_sum(s1);
+      if (lane == 0) {
+        const int slot = t * NW + wave;
+        if (EPI == 1) {
+          slot_ptr(rpart, rhs, S_DOT)[slot] = s0;
+          slot_ptr(rpart, rhs, S_SUM)[slot] = 0.0;
+          slot_ptr(rpart, rhs, S_SQ)[slot] = s1;
+          slot_ptr(rpart, rhs, S_AUX2)[slot] = 0.0;
+        } else {
+          slot_ptr(rpart, rhs, S_SUM)[slot] = s0;
+          slot_ptr(rpart, rhs, S_SQ)[slot] = s1;
+        }
+      }
+    }
+  }
+}
+
 // Packs B (K x K, row-major, FP64) as the S digits read by mp_oz and mp_ozh:
 // for column fragment j, k-block kb (padded to the split), digit s and lane
 // 16 g + c, 16 bytes hold digit s of B[64 kb + 16 g + b][16 j + c],
@@ -1410,6 +1584,17 @@ static void oz_pack(const double* B, int K, int S, void* dst) {
 // Rows per block of the int8 split product for a K x K operator.
 static int oz_block_rows(int K) { return oz_split(K) == 2 ? 32 : 64; }
 
+// Whether the operator-resident kernel (mp_ozr) serves the product: K <= 128,
+// and its partial sums (eight per 128-row tile) fit the slots.
+static bool oz_resident(int K, int64_t rows) { return K <= 128 && (rows + 127) / 128 * 8 <= GMAX; }
+
+// Partial sums per right-hand side that an int8 product leaves.
+static int oz_partials(int K, int64_t rows) {
+  const int64_t t = oz_resident(K, rows) ? (rows + 127) / 128 * 8
+                                         : (rows + oz_block_rows(K) - 1) / oz_block_rows(K);
+  return t > (1 << 30) ? (1 << 30) : (int)t;
+}
+
 template <int S>
 static void launch_oz_t(const PinvOps& op, int ax, bool fwd, const void* X, void* Y, int batch,
                       const RhsState* st, const double* la, const double* lb, const double* lc,
@@ -1421,6 +1606,30 @@ static void launch_oz_t(const PinvOps& op, int ax, bool fwd, const void* X, void
   const int br = oz_block_rows(K);
   dim3 grid((rows + br - 1) / br, batch);
   const int kbw = oz_kb_per_wave(K), ks = oz_split(K);
+  if (oz_resident(K, rows)) {
+    // one or two blocks per CU (by LDS), each sweeping 128-row tiles
+    const int nrb = (rows + 127) / 128;
+    const size_t lds_b = (size_t)(kbw * 4) * kbw * S * 64 * 16 + (size_t)64 * kbw * 12;
+    const int per_cu = lds_b * 2 <= 160 * 1024 ? 2 : 1;
+    const int nblk = std::max(1, std::min(nrb, (256 * per_cu + batch - 1) / batch));
+    dim3 rg(nblk, batch);
+    const int epi = lc ? 1 : (gt ? 2 : 0);
+#define KP_OZR(W, E)                                                                         \
+  hipLaunchKernelGGL((mp_ozr<W, E, S>), rg, dim3(512), 0, s, (const u4*)Bp, fx,               \
+                     (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
+                     gt, rpart)
+    if (kbw == 1) {
+      if (epi == 1) KP_OZR(1, 1);
+      else if (epi == 2) KP_OZR(1, 2);
+      else KP_OZR(1, 0);
+    } else {
+      if (epi == 1) KP_OZR(2, 1);
+      else if (epi == 2) KP_OZR(2, 2);
+      else KP_OZR(2, 0);
+    }
+#undef KP_OZR
+    return;
+  }
 #define KP_OZ(W, S_)                                                                         \
   hipLaunchKernelGGL((mp_oz<W, S_, S>), grid, dim3(256 * S_), 0, s, (const u4*)Bp, fx,          \
                      (const double*)X, (double*)Y, K, rows, (int64_t)op.N, st, la, lb, lc, a1, \
@@ -1803,20 +2012,15 @@ static void product_t(const PinvOps& op, int q, const void* in, void* out, int b
 int pinv_first_blocks(const PinvOps& op) {
   if (!prec_int8(op.prec)) return 0;
   const int K = op.n[0];
-  const int64_t rows = op.N / K, br = oz_block_rows(K);
-  const int64_t t = (rows + br - 1) / br;
-  return t > (1 << 30) ? (1 << 30) : (int)t;
+  return oz_partials(K, op.N / K);
 }
 
 int pinv_ghat_blocks(const PinvOps& op) {
   const int q = op.dim - 1, ax = q;
   const int K = op.n[ax];
   const int64_t rows = op.N / K;
-  if (prec_int8(op.prec)) {   // one block per 64 (K <= 256) or 32 rows
-    const int br = oz_block_rows(K);
-    const int64_t t = (rows + br - 1) / br;
-    return t > (1 << 30) ? (1 << 30) : (int)t;
-  }
+  if (prec_int8(op.prec))     // eight per 128 rows (K <= 128), else one per block of 64 or 32 rows
+    return oz_partials(K, rows);
   const int CH = op.prec == PREC_F64 || op.prec == PREC_F32 ? 4 : 8;
   int wn = 4, wm = 2, wc = 2;   // the scalar-load tile of ragged contractions
   // the operator-resident tiles write one partial per 64-row tile
