@@ -213,6 +213,7 @@ def test_error_bound_stop(shape, bcs):
 
 
 @pytest.mark.parametrize("prec,shape,bcs", [("f32", (64, 96, 80), ("P", "P", "DN")),
+                                            ("f32", (36, 50, 48), ("D", "N", "P")),
                                             ("bf16x6", (40, 48, 56), ("N", "N", "P")),
                                             ("f32", (100, 120), ("D", "N"))])
 def test_lowmode_certificate_stop(prec, shape, bcs):
