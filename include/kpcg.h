@@ -399,8 +399,9 @@ int kp_plan_set_tuning(kp_plan* plan, const int* cfg, int n);
  * keep the whole operator in LDS and sweep row tiles with persistent blocks;
  * they serve contractions of length at most 128 only (kp_plan_set_tuning
  * refuses them for a longer axis, the autotuner skips them there).  I8X7
- * and I8X6 products run their own kernels (one 16-column fragment per step);
- * their plans accept and report id 13 only. */
+ * and I8X6 products run their own kernels (one 16-column fragment per step;
+ * contractions of length at most 128 with the whole operator in LDS); their
+ * plans accept and report id 13 only. */
 int kp_tile_shape(int id, int prec, int* wn, int* wm, int* wc);
 
 /* Per-kernel timing (the library's tracing facility).  When enabled, every
