@@ -972,6 +972,55 @@ __device__ __forceinline__ void oz_products(const v4i (&a)[OZ_SMAX], const v4i (
       acc[i + s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[s], acc[i + s], 0, 0, 0);
 }
 
+// 16 bytes a lane from global memory into LDS at the wave-uniform address
+// lds_addr + 16 lane (global_load_lds_dwordx4), no registers written.  The
+// caller waits for it (vmcnt) before any wave reads that LDS.
+// m0 is named as clobbered; no other code in these kernels keeps a value in it.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void oz_dma16(const u4* src, unsigned lds_addr) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :: "v"(src), "s"(lds_addr) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// The S operator digit fragments of one k-block from LDS (16 bytes a lane).
+template <int S>
+__device__ __forceinline__ void oz_ldsb(const u4* lds, int at, v4i (&b)[OZ_SMAX]) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const u4 u = lds[at + s * 64];
+    b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
+  }
+}
+
+// The products of KBW consecutive k-blocks whose operator digits sit in LDS
+// at at[(kb S + s) 64] (at: the first k-block, offset by the lane): each
+// k-block's digits are read while the k-block before it is multiplied (two
+// register sets, alternating), the reads spread over the first products.
+template <int KBW, int S>
+__device__ __forceinline__ void oz_kloop(const u4* at, const v4i (&xa)[KBW][OZ_SMAX],
+                                         v4i (&acc)[OZ_SMAX]) {
+  v4i b[2][OZ_SMAX];
+  oz_ldsb<S>(at, 0, b[0]);
+#pragma unroll
+  for (int kb = 0; kb < KBW; ++kb) {
+    if (kb + 1 < KBW) oz_ldsb<S>(at, (kb + 1) * S * 64, b[(kb + 1) & 1]);
+    oz_products<S>(xa[kb], b[kb & 1], acc);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, S, 0);     // DS reads
+#pragma unroll
+  for (int kb = 0; kb + 1 < KBW; ++kb) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // matrix-core ops
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, S * (S + 1) / 2 - 2 * S, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, S * (S + 1) / 2, 0);
+}
+
 // Ghat for the int8 split epilogues: the hardware reciprocal estimate and two
 // Newton steps r <- r + r (1 - s r), each squaring the relative error, reach
 // FP64 accuracy (within an ulp of 1/s) without the IEEE division sequence.
@@ -1118,16 +1167,7 @@ __global__ __launch_bounds__(256 * KS, 2 / KS) void mp_oz(
     v4i acc[OZ_SMAX];
 #pragma unroll
     for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
-#pragma unroll
-    for (int kb = 0; kb < KBW; ++kb) {
-      v4i b[OZ_SMAX];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const u4 u = lds[buf][((kb0 + kb) * S + s) * 64 + lane];
-        b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-      }
-      oz_products<S>(xa[kb], b, acc);
-    }
+    oz_kloop<KBW, S>(lds[buf] + kb0 * S * 64 + lane, xa, acc);
     if constexpr (KS == 2) {
       if (h == 1) {
 #pragma unroll
@@ -1235,15 +1275,16 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
   // 64 consecutive 16-byte units (the builtin writes lane l's 16 bytes at the
   // wave-uniform LDS address + 16 l), so a wave's chunk lies wholly inside or
   // wholly past the fragment
+  // (issued from asm, which the compiler does not track: every wait for these
+  // loads is explicit below, so that none also waits for the output stores)
   auto stage = [&](int j) {
     const u4* src = Bpk + (int64_t)j * SU;
 #pragma unroll
     for (int q = 0; q < UPT; ++q) {
       const int u0 = (tid & ~63) + q * NT;
       if (u0 < SU)
-        __builtin_amdgcn_global_load_lds((const void*)(src + u0 + lane),
-                                         (__attribute__((address_space(3))) void*)&lds[u0], 16,
-                                         0, 0);
+        oz_dma16(src + u0 + lane, __builtin_amdgcn_readfirstlane(
+            (unsigned)(uintptr_t)(__attribute__((address_space(3))) u4*)&lds[u0]));
     }
   };
   stage(0);                                     // in flight while the data loads
@@ -1303,16 +1344,7 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
     v4i acc[OZ_SMAX];
 #pragma unroll
     for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
-#pragma unroll
-    for (int kb = 0; kb < KBW; ++kb) {
-      v4i b[OZ_SMAX];
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const u4 u = lds[((kb0 + kb) * S + s) * 64 + lane];
-        b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-      }
-      oz_products<S>(xa[kb], b, acc);
-    }
+    oz_kloop<KBW, S>(lds + kb0 * S * 64 + lane, xa, acc);
     const int fh = j & 1;
     if (h != fh) {
 #pragma unroll
@@ -1360,8 +1392,17 @@ __global__ __launch_bounds__(256, 2) void mp_ozh(
         *reinterpret_cast<d2*>(dst + 2) = (d2){out[2], out[3]};
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);              // the next fragment has landed
-    __syncthreads();
+    // the next fragment has landed.  Vector memory operations complete in
+    // issue order, and a finishing wave's two output stores (one 16-byte
+    // store each) come after its loads of the next fragment, so that wave
+    // waits until at most those two are outstanding: the stores need not
+    // reach memory before the barrier.
+    // (__syncthreads() would wait for the stores as well: its fence orders
+    // the loads into LDS by waiting for every vector memory operation.)
+    if (__builtin_amdgcn_readfirstlane(h == fh && rows_ok))
+      asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   }
   if (EPI == 1 && rpart) {
     // fixed-order block reduction: lanes, then waves in order
@@ -1468,16 +1509,7 @@ __global__ __launch_bounds__(512, 1) void mp_ozr(
       v4i acc[OZ_SMAX];
 #pragma unroll
       for (int d = 0; d < S; ++d) acc[d] = (v4i){0, 0, 0, 0};
-#pragma unroll
-      for (int kb = 0; kb < KBW; ++kb) {
-        v4i b[OZ_SMAX];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const u4 u = lds[((j * KBW + kb) * S + s) * 64 + lane];
-          b[s] = (v4i){(int)u.x, (int)u.y, (int)u.z, (int)u.w};
-        }
-        oz_products<S>(xa[kb], b, acc);
-      }
+      oz_kloop<KBW, S>(lds + j * KBW * S * 64 + lane, xa, acc);
       const int n = 16 * j + l16;
       const int f = sfx[n];
       const double lcn = EPI == 1 ? slc[n] : 0.0;
