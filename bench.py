@@ -418,18 +418,27 @@ def product_bytes(name, prec, grid):
 
 
 def run_solves(plan, eta_d, u, steps, tol, flags=0, max_iter=60):
+    """steps solves back to back; Python's cyclic garbage collector runs
+    before them and not during them (as timeit does)."""
+    import gc
     import torch
     lat, res = [], None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        t = time.perf_counter()
-        _, res, _, rc = plan.solve(eta_d, tol=tol, max_iter=max_iter, flags=flags, out=u)
-        lat.append(time.perf_counter() - t)
-        if rc != 0:
-            raise RuntimeError(f"solve failed with status {rc}: {res}")
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, np.array(lat), res
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            t = time.perf_counter()
+            _, res, _, rc = plan.solve(eta_d, tol=tol, max_iter=max_iter, flags=flags, out=u)
+            lat.append(time.perf_counter() - t)
+            if rc != 0:
+                raise RuntimeError(f"solve failed with status {rc}: {res}")
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+    finally:
+        gc.enable()
+    return T, np.array(lat), res
 
 
 def cpu_baseline(wl, eta, budget_s=25.0):
